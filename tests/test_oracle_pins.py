@@ -1,0 +1,431 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+Each test checks the oracle against something other than itself: a
+hand-derived worked example, a closed form, an invariant, a special case
+that reduces to a textbook routine, brute force on tiny inputs, or an
+independent library.  Sizes are small so the CPU suite stays fast.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+from oracle import bounds, fom, mlp, pod, rom
+from paper_1910_01260_amd import workloads as W
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _tiny_advdiff(N=16, N_t=8, n_train=3):
+    return W.advdiff1d(N=N, N_t=N_t, n_train=n_train)
+
+
+def _tiny_transport(nx=4, ndir=4, N_t=6):
+    return W.transport2d(nx=nx, ndir=ndir, N_t=N_t)
+
+
+def _fom(prob, mu):
+    return fom.backward_euler(prob.operator(mu), prob.forcing(mu), prob.initial(mu), prob.dt)
+
+
+def _bases(prob, n_s, n_t, tau_t=1e-7):
+    U = pod.snapshot_matrix([_fom(prob, m) for m in prob.train_mu])
+    Phi_s, s, V = pod.pod(U, n_s)
+    nts = np.full(n_s, n_t) if np.isscalar(n_t) else np.asarray(n_t)
+    Phi_t, ranks = pod.temporal_bases(V, prob.N_t, len(prob.train_mu), nts, tau_t)
+    return U, Phi_s, s, V, Phi_t, ranks
+
+
+def _st_pieces(prob, Phi_s):
+    Ahat = [rom.spatial_operator(Phi_s, A) for A in prob.terms]
+    bhat = rom.reduced_vector(Phi_s, prob.Bf) if prob.Qf else np.zeros((Phi_s.shape[1], 0))
+    u0hat = rom.reduced_vector(Phi_s, prob.u0) if prob.Q0 else np.zeros((Phi_s.shape[1], 0))
+    return Ahat, bhat, u0hat
+
+
+def _system(prob, Phi_s, Phi_t, mu):
+    Ahat, bhat, u0hat = _st_pieces(prob, Phi_s)
+    tA, tf, t0 = prob.thetas(mu)
+    return rom.reduced_system(Ahat, tA[0], bhat, tf[0], prob.g, u0hat, t0[0], Phi_t, prob.dt)
+
+
+# ----------------------------------------------------------------------------
+# worked example and closed forms
+# ----------------------------------------------------------------------------
+
+def test_golden_scalar_two_step():
+    """Hand-derived 2-step scalar ST-ROM (tests/golden/scalar_two_step.json)."""
+    g = json.load(open(os.path.join(GOLDEN, "scalar_two_step.json")))
+    A = np.array([[g["system"]["A"]]])
+    dt = np.array(g["system"]["dt"])
+    Phi_s = np.array(g["basis"]["Phi_s"])
+    Phi_t = [np.array(g["basis"]["Phi_t"])]
+    Ahat = rom.spatial_operator(Phi_s, A)
+    M = rom.block_operator(Ahat, Phi_t, dt)
+    rhs = rom.initial_vector(Phi_s.T @ np.array([g["system"]["u0"]]), Phi_t)
+    np.testing.assert_allclose(M, g["Ahat_st"], rtol=0, atol=1e-15)
+    np.testing.assert_allclose(rhs, g["rhs"], rtol=0, atol=1e-15)
+    c = rom.solve(M, rhs)
+    np.testing.assert_allclose(c, g["c_hat"], rtol=1e-14)
+    np.testing.assert_allclose(rom.reconstruct(Phi_s, Phi_t, c)[0], g["trajectory"], rtol=1e-14)
+    # the full-order march gives the same trajectory
+    np.testing.assert_allclose(fom.backward_euler(A, np.zeros((1, 2)), [1.0], dt)[0], g["trajectory"], rtol=1e-15)
+
+
+def test_scalar_closed_form_fom_and_strom():
+    """P9: N_s = 1, A = -lam, constant input b: u^(k) = u0 q^k + b dt sum_{i=1..k} q^i,
+    q = 1/(1 + lam dt).  The full-order march and the complete-basis ST-ROM both
+    reproduce it."""
+    lam, b, u0, dt, Nt = 3.0, 0.7, 2.0, 0.1, 7
+    q = 1.0 / (1.0 + lam * dt)
+    exact = np.array([u0 * q ** k + b * dt * sum(q ** i for i in range(1, k + 1)) for k in range(1, Nt + 1)])
+    A = np.array([[-lam]])
+    F = np.full((1, Nt), b)
+    dts = np.full(Nt, dt)
+    np.testing.assert_allclose(fom.backward_euler(A, F, [u0], dts)[0], exact, rtol=1e-14)
+    rng = np.random.default_rng(0)
+    Phi_t = [np.linalg.qr(rng.standard_normal((Nt, Nt)))[0]]
+    Phi_s = np.eye(1)
+    M = rom.block_operator(rom.spatial_operator(Phi_s, A), Phi_t, dts)
+    rhs = rom.input_vector(F, Phi_t, dts) + rom.initial_vector(np.array([u0]), Phi_t)
+    c = rom.solve(M, rhs)
+    np.testing.assert_allclose(rom.reconstruct(Phi_s, Phi_t, c)[0], exact, rtol=1e-12)
+
+
+def test_fom_matches_dense_time_march_and_space_time_system():
+    """Sec. 2: the time march solves the space-time system Eq. (st-fom)."""
+    prob = _tiny_transport()
+    mu = prob.train_mu[3]
+    Ut = _fom(prob, mu)
+    A_st, f_st, u0_st = fom.space_time_system(prob.operator(mu), prob.forcing(mu), prob.initial(mu), prob.dt)
+    x = np.linalg.solve(A_st.toarray(), f_st + u0_st)
+    np.testing.assert_allclose(x, Ut.T.ravel(), rtol=1e-12, atol=1e-14)
+
+
+def test_oracle_fom_matches_workload_generator():
+    """The two independent full-order marches agree (oracle splu vs the input
+    generator, which uses source iteration for transport)."""
+    for prob in (_tiny_advdiff(), W.transport2d(nx=8, N_t=10), W.transport2d_absorber(nx=8, N_t=10)):
+        mu = prob.train_mu[-1]
+        a = _fom(prob, mu)
+        b = W.march(prob, mu)
+        assert np.linalg.norm(a - b) <= 1e-12 * np.linalg.norm(a)
+
+
+# ----------------------------------------------------------------------------
+# POD (Sec. 4.1)
+# ----------------------------------------------------------------------------
+
+def test_pod_orthonormal_and_eckart_young():
+    """P1 + P2: Phi_s^T Phi_s = I and ||U - Phi_s Phi_s^T U||_F^2 = sum_{i > n_s} sigma_i^2."""
+    prob = _tiny_advdiff(N=32, N_t=10, n_train=3)
+    U = pod.snapshot_matrix([_fom(prob, m) for m in prob.train_mu])
+    for n_s in (1, 3, 6):
+        Phi, s, V = pod.pod(U, n_s)
+        np.testing.assert_allclose(Phi.T @ Phi, np.eye(n_s), atol=1e-14)
+        resid = np.linalg.norm(U - Phi @ (Phi.T @ U), "fro") ** 2
+        np.testing.assert_allclose(resid, np.sum(s[n_s:] ** 2), rtol=1e-9, atol=1e-26)
+
+
+def test_pod_singular_values_are_gram_eigenvalues():
+    """P3: sigma_i^2 are the eigenvalues of U^T U (method of snapshots) and
+    U = W S V^T for the kept modes."""
+    prob = _tiny_advdiff(N=24, N_t=6, n_train=2)
+    U = pod.snapshot_matrix([_fom(prob, m) for m in prob.train_mu])
+    Phi, s, V = pod.pod(U, 5)
+    ev = np.sort(np.linalg.eigvalsh(U.T @ U))[::-1]
+    np.testing.assert_allclose(s[:5] ** 2, ev[:5], rtol=1e-10)
+    np.testing.assert_allclose(U @ V, Phi * s[:5], atol=1e-12 * s[0])
+
+
+def test_sign_rule():
+    assert pod.sign_fix(np.array([-0.1, -1.0, 0.9]))[1][1] > 0
+    assert pod.sign_fix(np.array([-0.3, 1.0]))[1][0] > 0       # first entry >= max/4
+    assert pod.sign_fix(np.array([-0.2, 1.0]))[1][1] > 0       # 0.2 < 1/4
+    assert pod.sign_fix(np.zeros(3))[0] == 1.0
+
+
+def test_temporal_basis_all_data_equals_svd_vectors():
+    """n_t <= rank: the temporal basis is the leading left singular vectors."""
+    rng = np.random.default_rng(1)
+    Y = rng.standard_normal((12, 5))
+    B, r, keep = pod.temporal_basis(Y, 4)
+    L, s, _ = np.linalg.svd(Y)
+    assert r == 5 and keep == 4
+    for j in range(4):
+        assert abs(abs(B[:, j] @ L[:, j]) - 1) < 1e-13
+
+
+def test_temporal_completion_of_zero_data_is_dct():
+    """Closed form: with no data the completion is the normalised DCT-II basis."""
+    N_t, n_t = 10, 6
+    B, r, keep = pod.temporal_basis(np.zeros((N_t, 3)), n_t)
+    assert r == 0 and keep == 0
+    k = np.arange(N_t)
+    for m in range(n_t):
+        c = np.cos(np.pi * m * (k + 0.5) / N_t)
+        c /= np.linalg.norm(c)
+        if c[0] < 0:
+            c = -c
+        np.testing.assert_allclose(B[:, m], c, atol=1e-14)
+
+
+def test_temporal_completion_orthonormal_and_keeps_data_span():
+    rng = np.random.default_rng(2)
+    Y = rng.standard_normal((16, 3)) @ np.diag([1, 1e-3, 1e-12])
+    B, r, keep = pod.temporal_basis(Y, 9, tau_t=1e-7)
+    assert r == 2 and keep == 2
+    np.testing.assert_allclose(B.T @ B, np.eye(9), atol=1e-14)
+    L = np.linalg.svd(Y)[0][:, :2]
+    np.testing.assert_allclose(np.linalg.svd(B[:, :2].T @ L, compute_uv=False), [1, 1], atol=1e-12)
+
+
+# ----------------------------------------------------------------------------
+# block structure (Sec. 4.3) against brute-force projection
+# ----------------------------------------------------------------------------
+
+@pytest.mark.parametrize("problem", ["advdiff", "transport"])
+def test_block_formulas_equal_bruteforce_paper_order(problem):
+    """P4: Eq. (ij-block-matrix), (j-block-vector), (j-block-vector-constant-input)
+    equal Phi_st^T A_st Phi_st etc. with Phi_st formed explicitly (paper order)."""
+    prob = _tiny_advdiff() if problem == "advdiff" else _tiny_transport()
+    n_s, n_t = 4, 3
+    U, Phi_s, s, V, Phi_t, _ = _bases(prob, n_s, n_t)
+    mu = prob.train_mu[1]
+    A = prob.operator(mu)
+    F = prob.forcing(mu)
+    A_st, f_st, u0_st = fom.space_time_system(A, F, prob.initial(mu), prob.dt)
+    Phi_st = rom.spacetime_basis(Phi_s, Phi_t, order="paper")
+    Ab, fb, ub = rom.project_space_time(Phi_st, A_st, f_st, u0_st)
+    Ahat = rom.spatial_operator(Phi_s, A)
+    np.testing.assert_allclose(rom.block_operator_paper(Ahat, Phi_t, prob.dt), Ab, atol=1e-12 * np.abs(Ab).max())
+    BF_hat = Phi_s.T @ F
+    np.testing.assert_allclose(rom.input_vector_paper(BF_hat, Phi_t, prob.dt), fb, atol=1e-14 + 1e-12 * np.abs(fb).max())
+    if prob.Qf:
+        const = rom.input_vector_constant_paper(Phi_s.T @ F[:, 0], Phi_t, prob.dt)
+        np.testing.assert_allclose(const, fb, atol=1e-12 * np.abs(fb).max())
+    u0hat = Phi_s.T @ prob.initial(mu)
+    np.testing.assert_allclose(rom.initial_vector_paper(u0hat, Phi_t), ub, atol=1e-14)
+
+
+def test_printed_initial_vector_differs_from_projection():
+    """Reading of Eq. (first-block-initial-vector): the printed form is not the
+    projection of u0_st; block j = D_1^j u0hat is."""
+    prob = _tiny_advdiff()
+    n_s, n_t = 4, 3
+    U, Phi_s, s, V, Phi_t, _ = _bases(prob, n_s, n_t)
+    mu = prob.train_mu[0]
+    A_st, f_st, u0_st = fom.space_time_system(prob.operator(mu), prob.forcing(mu), prob.initial(mu), prob.dt)
+    Phi_st = rom.spacetime_basis(Phi_s, Phi_t, order="paper")
+    ub = Phi_st.T @ u0_st
+    u0hat = Phi_s.T @ prob.initial(mu)
+    assert np.linalg.norm(rom.initial_vector_printed(u0hat, Phi_t) - ub) > 1e-2 * np.linalg.norm(ub)
+    np.testing.assert_allclose(rom.initial_vector_paper(u0hat, Phi_t), ub, atol=1e-14)
+
+
+@pytest.mark.parametrize("problem", ["advdiff", "transport"])
+def test_mode_major_ragged_equals_bruteforce(problem):
+    """P4 with a different n_t per mode, mode-major order."""
+    prob = _tiny_advdiff() if problem == "advdiff" else _tiny_transport()
+    n_t = np.array([5, 3, 1, 2])
+    U, Phi_s, s, V, Phi_t, _ = _bases(prob, 4, n_t)
+    mu = prob.train_mu[-1]
+    A_st, f_st, u0_st = fom.space_time_system(prob.operator(mu), prob.forcing(mu), prob.initial(mu), prob.dt)
+    Phi_st = rom.spacetime_basis(Phi_s, Phi_t, order="mode")
+    Ab, fb, ub = rom.project_space_time(Phi_st, A_st, f_st, u0_st)
+    M, rhs = _system(prob, Phi_s, Phi_t, mu)
+    np.testing.assert_allclose(M, Ab, atol=1e-12 * np.abs(Ab).max())
+    np.testing.assert_allclose(rhs, fb + ub, atol=1e-14 + 1e-12 * np.abs(fb + ub).max())
+
+
+def test_prefix_truncation_is_principal_submatrix():
+    """Truncating each mode's temporal basis to a prefix gives the principal
+    submatrix of the full reduced system (used for ragged query batches)."""
+    prob = _tiny_advdiff()
+    U, Phi_s, s, V, Phi_t, _ = _bases(prob, 4, 5)
+    mu = prob.train_mu[0]
+    M, rhs = _system(prob, Phi_s, Phi_t, mu)
+    nt = [3, 5, 1, 2]
+    Pt = [Phi_t[i][:, :nt[i]] for i in range(4)]
+    Mq, rq = _system(prob, Phi_s, Pt, mu)
+    idx = np.concatenate([5 * i + np.arange(nt[i]) for i in range(4)])
+    np.testing.assert_allclose(Mq, M[np.ix_(idx, idx)], atol=0)
+    np.testing.assert_allclose(rq, rhs[idx], atol=0)
+
+
+def test_temporal_gram_is_identity():
+    """P5: sum_k D_k^j' D_k^j = delta_j'j I, i.e. Phi_t^i^T Phi_t^i = I."""
+    prob = _tiny_advdiff()
+    _, _, _, _, Phi_t, _ = _bases(prob, 4, 6)
+    for P in Phi_t:
+        np.testing.assert_allclose(P.T @ P, np.eye(P.shape[1]), atol=1e-14)
+
+
+# ----------------------------------------------------------------------------
+# end-to-end special cases
+# ----------------------------------------------------------------------------
+
+@pytest.mark.parametrize("problem", ["advdiff", "transport"])
+def test_complete_bases_reproduce_fom(problem):
+    """P6: n_s = N_s and n_t = N_t: the ST-ROM solution is the FOM trajectory."""
+    prob = _tiny_advdiff(N=12, N_t=6) if problem == "advdiff" else _tiny_transport(nx=2, ndir=4, N_t=5)
+    N = prob.N_s
+    U, Phi_s, s, V, Phi_t, _ = _bases(prob, min(N, prob.N_t * len(prob.train_mu)), prob.N_t)
+    if Phi_s.shape[1] < N:  # complete the spatial basis too
+        Q, _ = np.linalg.qr(np.concatenate([Phi_s, np.eye(N)], axis=1))
+        Phi_s = Q[:, :N]
+        Phi_t = Phi_t + [np.eye(prob.N_t)] * (N - len(Phi_t))
+    for mu in (prob.train_mu[0], W.sample_params(prob, 1, seed=5)[0]):
+        M, rhs = _system(prob, Phi_s, Phi_t, mu)
+        c = rom.solve(M, rhs)
+        Ut = _fom(prob, mu)
+        np.testing.assert_allclose(rom.reconstruct(Phi_s, Phi_t, c), Ut, atol=1e-11 * np.abs(Ut).max())
+
+
+def test_training_parameters_reproduced_exactly():
+    """P7: n_s = rank U and n_t,i >= rank Y_i reproduce the training trajectories."""
+    prob = W.advdiff1d(N=40, N_t=5, n_train=2)
+    U = pod.snapshot_matrix([_fom(prob, m) for m in prob.train_mu])
+    rank = np.linalg.matrix_rank(U)
+    Phi_s, s, V = pod.pod(U, rank)
+    Phi_t, ranks = pod.temporal_bases(V, prob.N_t, 2, np.full(rank, 2), tau_t=1e-12)
+    for p, mu in enumerate(prob.train_mu):
+        M, rhs = _system(prob, Phi_s, Phi_t, mu)
+        c = rom.solve(M, rhs)
+        Ut = U[:, p * prob.N_t:(p + 1) * prob.N_t]
+        np.testing.assert_allclose(rom.reconstruct(Phi_s, Phi_t, c), Ut, atol=1e-10 * np.abs(Ut).max())
+
+
+def test_identity_temporal_basis_is_spatial_rom():
+    """P8: Phi_t^i = I_{N_t} for all i turns the ST-ROM into the spatial ROM
+    marched by backward Euler (Eq. (space_reduced_discretized_ODE))."""
+    prob = _tiny_transport(nx=4, ndir=4, N_t=6)
+    U, Phi_s, s, V, _, _ = _bases(prob, 5, 2)
+    Phi_t = [np.eye(prob.N_t)] * 5
+    mu = W.sample_params(prob, 1, seed=3)[0]
+    M, rhs = _system(prob, Phi_s, Phi_t, mu)
+    c = rom.solve(M, rhs)
+    Ahat = rom.spatial_operator(Phi_s, prob.operator(mu))
+    march = rom.spatial_rom_march(Ahat, Phi_s.T @ prob.forcing(mu), Phi_s.T @ prob.initial(mu), prob.dt)
+    np.testing.assert_allclose(c.reshape(5, prob.N_t), march, atol=1e-13 * np.abs(march).max())
+
+
+def test_complete_spatial_basis_spatial_rom_is_fom():
+    """P13: n_s = N_s makes the spatial ROM the FOM."""
+    prob = _tiny_advdiff(N=10, N_t=6)
+    mu = prob.train_mu[1]
+    Q = np.linalg.qr(np.random.default_rng(4).standard_normal((10, 10)))[0]
+    A = prob.operator(mu).toarray()
+    march = rom.spatial_rom_march(Q.T @ A @ Q, Q.T @ prob.forcing(mu), Q.T @ prob.initial(mu), prob.dt)
+    np.testing.assert_allclose(Q @ march, _fom(prob, mu), atol=1e-13)
+
+
+def test_galerkin_orthogonality():
+    """P10: Phi_st^T r_st(Phi_st c) = 0 for the ST-ROM solution c."""
+    prob = _tiny_transport()
+    U, Phi_s, s, V, Phi_t, _ = _bases(prob, 4, [3, 2, 2, 1])
+    mu = W.sample_params(prob, 1, seed=6)[0]
+    M, rhs = _system(prob, Phi_s, Phi_t, mu)
+    c = rom.solve(M, rhs)
+    A_st, f_st, u0_st = fom.space_time_system(prob.operator(mu), prob.forcing(mu), prob.initial(mu), prob.dt)
+    Phi_st = rom.spacetime_basis(Phi_s, Phi_t, order="mode")
+    r = A_st @ (Phi_st @ c) - f_st - u0_st
+    assert np.linalg.norm(Phi_st.T @ r) <= 1e-13 * np.linalg.norm(r) + 1e-15
+
+
+def test_error_bounds_hold():
+    """P11: Theorems 1, 2 (spatial ROM) and 3 (space-time ROM) bound the true error."""
+    prob = _tiny_transport(nx=4, ndir=4, N_t=6)
+    mu = W.sample_params(prob, 1, seed=8)[0]
+    A = prob.operator(mu).toarray()
+    F = prob.forcing(mu)
+    Ut = _fom(prob, mu)
+    U, Phi_s, s, V, Phi_t, _ = _bases(prob, 3, 2)
+    # spatial ROM (u0 = 0 so u~^(0) = u^(0))
+    Ahat = Phi_s.T @ A @ Phi_s
+    Usp = Phi_s @ rom.spatial_rom_march(Ahat, Phi_s.T @ F, Phi_s.T @ prob.initial(mu), prob.dt)
+    err = np.linalg.norm(Ut - Usp, axis=0)
+    assert np.all(err <= bounds.theorem1_bound(A, F, Usp, prob.initial(mu), prob.dt) * (1 + 1e-12))
+    assert np.all(err <= bounds.theorem2_bound(A, F, Usp, prob.dt) * (1 + 1e-12))
+    # space-time ROM
+    M, rhs = _system(prob, Phi_s, Phi_t, mu)
+    c = rom.solve(M, rhs)
+    ust = rom.reconstruct(Phi_s, Phi_t, c).T.ravel()
+    A_st, f_st, u0_st = fom.space_time_system(A, F, prob.initial(mu), prob.dt)
+    true = bounds.st_inf_norm(Ut.T.ravel() - ust, prob.N_s)
+    assert true <= bounds.theorem3_bound(A_st, f_st, u0_st, ust, prob.N_s) * (1 + 1e-12)
+
+
+@pytest.mark.parametrize("problem", ["advdiff", "transport"])
+def test_symmetric_part_positive_definite(problem):
+    """P12: sym(A) <= 0 gives lambda_min(sym Ahat_st) >= 1 - cos(pi/(N_t+1)) > 0."""
+    prob = _tiny_advdiff() if problem == "advdiff" else _tiny_transport()
+    U, Phi_s, s, V, Phi_t, _ = _bases(prob, 4, [4, 3, 3, 2])
+    for mu in W.sample_params(prob, 3, seed=9):
+        M, _ = _system(prob, Phi_s, Phi_t, mu)
+        lam = np.linalg.eigvalsh(0.5 * (M + M.T)).min()
+        assert lam >= (1 - math.cos(math.pi / (prob.N_t + 1))) * (1 - 1e-10)
+
+
+# ----------------------------------------------------------------------------
+# surrogate reference network
+# ----------------------------------------------------------------------------
+
+def test_mlp_gradients_match_finite_differences():
+    rng = np.random.default_rng(10)
+    params = mlp.init_params([3, 7, 6, 4], rng)
+    X = rng.standard_normal((5, 3))
+    T = rng.standard_normal((5, 4))
+    Y, cache = mlp.forward(params, X)
+    grads = mlp.backward(params, cache, Y, T)
+    h = 1e-6
+    for li in range(len(params)):
+        for pi in range(2):
+            p = params[li][pi]
+            flat = p.reshape(-1)
+            for idx in rng.choice(flat.size, size=min(5, flat.size), replace=False):
+                old = flat[idx]
+                flat[idx] = old + h
+                lp = mlp.mse(mlp.forward(params, X)[0], T)
+                flat[idx] = old - h
+                lm = mlp.mse(mlp.forward(params, X)[0], T)
+                flat[idx] = old
+                fd = (lp - lm) / (2 * h)
+                assert abs(fd - grads[li][pi].reshape(-1)[idx]) <= 1e-7 * max(1.0, abs(fd))
+
+
+def test_mlp_matches_torch_autograd():
+    """Independent library: torch autograd in float64 on the CPU."""
+    import torch
+
+    rng = np.random.default_rng(11)
+    params = mlp.init_params([3, 16, 16, 5], rng)
+    X = rng.standard_normal((8, 3))
+    T = rng.standard_normal((8, 5))
+    Y, cache = mlp.forward(params, X)
+    grads = mlp.backward(params, cache, Y, T)
+    tp = [(torch.tensor(W, requires_grad=True), torch.tensor(b, requires_grad=True)) for W, b in params]
+    h = torch.tensor(X)
+    for li, (Wt, bt) in enumerate(tp):
+        h = h @ Wt.T + bt
+        if li < len(tp) - 1:
+            h = torch.nn.functional.gelu(h)
+    loss = torch.mean((h - torch.tensor(T)) ** 2)
+    loss.backward()
+    np.testing.assert_allclose(h.detach().numpy(), Y, rtol=1e-13)
+    for (Wt, bt), (gW, gb) in zip(tp, grads):
+        np.testing.assert_allclose(Wt.grad.numpy(), gW, rtol=1e-10, atol=1e-14)
+        np.testing.assert_allclose(bt.grad.numpy(), gb, rtol=1e-10, atol=1e-14)
+
+
+def test_adam_first_step_closed_form():
+    """First Adam step moves each parameter by lr * g / (|g| + eps)."""
+    p = [(np.array([[1.0, -2.0]]), np.array([0.5]))]
+    g = [(np.array([[0.3, -4.0]]), np.array([1e-9]))]
+    st = {}
+    mlp.adam_step(p, g, st, lr=0.01)
+    np.testing.assert_allclose(p[0][0], [[1.0 - 0.01 * 0.3 / (0.3 + 1e-8), -2.0 + 0.01 * 4.0 / (4.0 + 1e-8)]], rtol=1e-14)
+    np.testing.assert_allclose(p[0][1], [0.5 - 0.01 * 1e-9 / (1e-9 + 1e-8)], rtol=1e-12)
