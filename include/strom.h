@@ -1,0 +1,276 @@
+/*
+ * strom.h - C ABI of the space-time reduced-order model (ST-ROM) hot path on
+ * AMD Instinct MI355X (gfx950).
+ *
+ * Method: Choi, Brown, Arrighi, Anderson, "Space-time reduced order model for
+ * large-scale linear dynamical systems with application to Boltzmann
+ * transport problems".  The system is du/dt = A(mu) u + B f(t; mu),
+ * u(0) = u0(mu) (Sec. 2, Eq. (Dynamicalstate)), discretised by backward Euler
+ * with steps dt_k (Sec. 2, Eq. (fom)).  The library provides:
+ *
+ *   st_build_bases  POD of the snapshot matrix: spatial basis Phi_s and one
+ *                   temporal basis per spatial mode (Sec. 4.1).
+ *   st_assemble     projection of the affine operator terms onto Phi_s
+ *                   (Sec. 3.1, Eq. (galerkin)) and the mu-independent
+ *                   temporal contractions of the block formulas (Sec. 4.3).
+ *   st_form         per-query reduced space-time system Ahat_st(mu) and
+ *                   right-hand side (Sec. 4.3, Eq. (ij-block-matrix),
+ *                   (j-block-vector), and the projection of u0_st).
+ *   st_solve        per-query reduced solve Ahat_st c = fhat_st + u0hat_st
+ *                   (Sec. 3.2, Eq. (st-galerkin)) for a ragged batch.
+ *   st_mlp_*        a surrogate network mu -> c with a residual check
+ *                   (not part of the paper; see the st_mlp section).
+ *
+ * Conventions (all entry points):
+ *   - Every pointer marked [dev] is device memory owned by the caller; the
+ *     library never frees it and never keeps it after the call returns.
+ *     Pointers marked [host] are read during the call only.
+ *   - Dense matrices are column-major FP64 unless stated otherwise.
+ *   - Work is enqueued on `stream` (a hipStream_t; NULL = the null stream)
+ *     and is asynchronous: outputs are valid once the caller has
+ *     synchronised that stream.  The library allocates no device memory in
+ *     st_solve/st_form/st_mlp_*: the caller passes a workspace whose size is
+ *     given by the matching *_workspace function.  st_build_bases and
+ *     st_assemble likewise take a caller workspace.
+ *   - Argument errors are detected on the host before any launch and
+ *     reported through the return value; nothing is written then.
+ *   - Per-query numerical outcomes are written to a device `info` array:
+ *        0  success
+ *       k>0 the LU met an exactly zero pivot at step k (1-based); the
+ *           query's coefficients are set to NaN
+ *       -1  iterative refinement did not reach ir_tol in ir_max steps (the
+ *           last iterate is returned)
+ *       -3  the query did not fit in the coefficient or workspace capacity
+ *       -4  invalid per-query temporal profile (nt_q out of range)
+ *       -5  non-finite parameter coefficient
+ *   - Reduced coordinates are ordered mode-major: spatial mode i's temporal
+ *     coefficients j = 0..n_t,i-1 are contiguous.  This is the paper's
+ *     ordering i + n_s (j-1) of Eq. (spacetimebasis) up to a symmetric
+ *     permutation, and it allows a different temporal basis size per mode.
+ */
+#ifndef STROM_H
+#define STROM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t st_status;
+
+#define ST_OK 0
+#define ST_EINVAL (-1)        /* invalid argument (shape, null pointer, range) */
+#define ST_EDEVICE (-2)       /* a HIP call failed */
+#define ST_EWORKSPACE (-3)    /* workspace or output buffer too small */
+#define ST_ERANK (-4)         /* requested basis exceeds the data (n_s > min(N_s, n_mu N_t)) */
+#define ST_EUNSUPPORTED (-5)  /* size or precision outside what the kernels handle */
+
+/* arithmetic precisions */
+#define ST_F64 0
+#define ST_F32 1
+#define ST_BF16X3 2           /* split-BF16: x = hi + lo, hi*hi + hi*lo + lo*hi, FP32 accumulate */
+
+/* Static, NUL-terminated description of a status code. */
+const char* st_strerror(st_status s);
+
+/* ABI version (incremented on incompatible change). */
+int32_t st_version(void);
+
+/* ------------------------------------------------------------------------
+ * Square sparse matrix in CSR form; all arrays [dev].  Column indices within
+ * a row need not be sorted.
+ * ---------------------------------------------------------------------- */
+typedef struct {
+  int32_t n_rows;          /* N_s */
+  int64_t nnz;
+  const int32_t* row_ptr;  /* [dev] n_rows + 1 */
+  const int32_t* col_idx;  /* [dev] nnz */
+  const double* val;       /* [dev] nnz */
+} st_csr;
+
+/* ------------------------------------------------------------------------
+ * Shape of a reduced model.
+ *   n_s    number of spatial modes
+ *   N_t    number of time steps
+ *   Q      number of affine terms of A(mu) = sum_q theta_A[q] A_q      (>= 1)
+ *   Qf     number of input terms  B f^(k) = sum_q theta_f[q] g[k,q] Bf_q (>= 0)
+ *   Q0     number of initial-state terms u0 = sum_q theta_0[q] u0_q    (>= 0)
+ *   n_t    [host] n_s entries: temporal basis size of each mode (1..N_t);
+ *          queries may use any prefix of each mode's basis.
+ * n = sum_i n_t[i] is the full reduced dimension.
+ * ---------------------------------------------------------------------- */
+typedef struct {
+  int32_t n_s;
+  int32_t N_t;
+  int32_t Q;
+  int32_t Qf;
+  int32_t Q0;
+  const int32_t* n_t;
+} st_rom_desc;
+
+/* Byte offsets of the sections of a ROM buffer (filled by st_rom_layout).
+ * All sections are FP64 except the two index tables (int32).
+ *   Ahat   Q  x (n_s x n_s)  Ahat_q = Phi_s^T A_q Phi_s           (Eq. (galerkin))
+ *   bhat   Qf x n_s          Phi_s^T Bf_q
+ *   u0hat  Q0 x n_s          Phi_s^T u0_q
+ *   T      n x n             T[a,b] = sum_k dt_k phi_a(k) phi_b(k)  (weighted temporal Gram)
+ *   K      sum_i n_t,i^2     per mode, column-major n_t,i x n_t,i:
+ *                            K_i[j',j] = sum_k phi_ij'(k) phi_ij(k) - sum_{k<N_t} phi_ij'(k+1) phi_ij(k)
+ *   Wf     Qf x n            Wf[q,a] = sum_k dt_k g[k,q] phi_a(k)
+ *   P1     n                 P1[a] = phi_a(first step)
+ *   mode   n (int32)         spatial mode of reduced index a
+ *   moff   n_s + 1 (int32)   mode offsets into the reduced index
+ *   koff   n_s + 1 (int64)   element offsets of each K_i inside K
+ * where phi_a is column a of the concatenated temporal bases (mode-major).
+ */
+typedef struct {
+  size_t Ahat, bhat, u0hat, T, K, Wf, P1, mode, moff, koff, total;
+} st_rom_layout_t;
+
+st_status st_rom_layout(const st_rom_desc* d, st_rom_layout_t* out);
+
+/* ========================================================================
+ * st_build_bases - POD (Sec. 4.1, Eq. (snapshotmat), (POD), (SVD),
+ * (temporalSVD)).
+ *
+ * U        [dev] snapshot matrix N_s x (n_mu N_t), column-major with leading
+ *          dimension ldU >= N_s, columns parameter-major then time
+ *          (U = [U_1 ... U_nmu], U_p = [u^(1) ... u^(N_t)] at mu_p).
+ *          U_prec = ST_F64 (double) or ST_F32 (float storage).
+ * gram_prec  arithmetic of the snapshot Gram: ST_F64 (FP64 MFMA), ST_F32
+ *          (FP32 MFMA) or ST_BF16X3 (split-BF16 MFMA, FP32 accumulate).
+ *          The eigen-decomposition and re-orthonormalisation are FP64.
+ * n_s      spatial modes, 1 <= n_s <= min(N_s, n_mu N_t).
+ * n_t      [host] n_s temporal basis sizes, 1 <= n_t[i] <= N_t.
+ * tau_t    relative threshold of the numerical rank of each temporal
+ *          snapshot matrix (singular values <= tau_t * largest are dropped).
+ *
+ * The POD is computed by the method of snapshots: the smaller of U^T U and
+ * U U^T is formed, its leading n_s eigenpairs are found in FP64, the
+ * spatial basis is re-orthonormalised (two Cholesky-QR passes), and each
+ * temporal snapshot matrix Y_i (N_t x n_mu, Y_i[k,p] = v_i(p N_t + k)) is
+ * decomposed by one-sided Jacobi.  Temporal bases keep the left singular
+ * vectors above tau_t and are completed, when n_t[i] exceeds that rank,
+ * with DCT-II vectors cos(pi m (k+1/2)/N_t), m = 0,1,..., each orthogonalised
+ * twice against the kept vectors and accepted if >= 1e-2 of its norm
+ * survives.  Signs: each vector is made positive at its first entry whose
+ * magnitude is >= 1/4 of its largest magnitude.
+ *
+ * Outputs [dev]: Phi_s N_s x n_s (ld N_s); Phi_t N_t x n (ld N_t),
+ * mode-major columns; sigma n_s singular values; rank_t n_s numerical ranks
+ * of the temporal snapshot matrices (may be NULL).
+ * ====================================================================== */
+size_t st_build_bases_workspace(int64_t N_s, int32_t N_t, int32_t n_mu, int32_t n_s, const int32_t* n_t,
+                                int32_t gram_prec);
+
+st_status st_build_bases(const void* U, int32_t U_prec, int64_t ldU, int64_t N_s, int32_t N_t, int32_t n_mu,
+                         int32_t n_s, const int32_t* n_t, int32_t gram_prec, double tau_t,
+                         double* Phi_s, double* Phi_t, double* sigma, int32_t* rank_t,
+                         void* ws, size_t ws_bytes, void* stream);
+
+/* ========================================================================
+ * st_assemble - offline reduced operators.
+ *
+ * Projection (Sec. 3.1, Eq. (galerkin); Sec. 4.3 notes that Ahat is the
+ * spatial-ROM operator and can be precomputed): for each affine term,
+ * Ahat_q = Phi_s^T (A_q Phi_s) by CSR SpMM against the tall-skinny basis;
+ * bhat_q = Phi_s^T Bf_q; u0hat_q = Phi_s^T u0_q (reference state zero).
+ * Phi_s^T (I - dt A) Phi_s = I - dt Ahat follows from Phi_s^T Phi_s = I.
+ *
+ * Temporal contractions (Sec. 4.3, Eq. (ij-block-matrix), (j-block-vector)):
+ * T, K, Wf and P1 of the layout above, from the temporal bases and steps.
+ *
+ * d        [host] model shape; d->n_t must match the bases.
+ * Phi_s    [dev] N_s x n_s (ld N_s); Phi_t [dev] N_t x n (ld N_t).
+ * dt       [dev] N_t step sizes.
+ * A        [host] array of d->Q CSR descriptors (device arrays), N_s rows.
+ * Bf       [dev] N_s x Qf (ld N_s) input vectors, or NULL when Qf = 0.
+ * g        [dev] N_t x Qf (ld N_t) input time profiles, or NULL (all ones).
+ * u0       [dev] N_s x Q0 (ld N_s) initial-state terms, or NULL when Q0 = 0.
+ * rom      [dev] output buffer of st_rom_layout(d).total bytes.
+ * ====================================================================== */
+size_t st_assemble_workspace(const st_rom_desc* d, int64_t N_s);
+
+st_status st_assemble(const st_rom_desc* d, int64_t N_s, const double* Phi_s, const double* Phi_t,
+                      const double* dt, const st_csr* A, const double* Bf, const double* g, const double* u0,
+                      void* rom, size_t rom_bytes, void* ws, size_t ws_bytes, void* stream);
+
+/* ========================================================================
+ * Per-query inputs shared by st_form and st_solve.
+ *
+ * n_q      number of queries (>= 0; 0 is a no-op).
+ * theta_A  [dev] n_q x Q, query-major (row q holds theta_A(mu_q)).
+ * theta_f  [dev] n_q x Qf, or NULL when Qf = 0.
+ * theta_0  [dev] n_q x Q0, or NULL when Q0 = 0.
+ * nt_q     [dev] n_q x n_s, query-major: query q uses the first nt_q[q,i]
+ *          temporal vectors of mode i (0 <= nt_q[q,i] <= n_t[i]); NULL means
+ *          every query uses the full bases.  A query's reduced system is the
+ *          principal submatrix of the full one on its index set.
+ * Query q's width is w_q = sum_i nt_q[q,i]; coeff_off[q] = sum_{p<q} w_p.
+ * ====================================================================== */
+
+/* ========================================================================
+ * st_form - reduced space-time systems for a batch of queries
+ * (Sec. 4.3, Eq. (block-reduced-state-mat), (ij-block-matrix),
+ * (j-block-vector), and the projection of u0_st).
+ *
+ * Entry (a, b) of query q's matrix, a = (i', j'), b = (i, j):
+ *   delta_{i'i} K_i[j', j] - Ahat(mu_q)[i', i] T[a, b],
+ *   Ahat(mu_q) = sum_q theta_A[q] Ahat_q.
+ * Right-hand side entry a = (i, j):
+ *   sum_q theta_f[q] Wf[q,a] bhat_q[i] + P1[a] (sum_q theta_0[q] u0hat_q[i]).
+ * (The printed Eq. (first-block-initial-vector) keeps only the first temporal
+ * block; the projection of u0_st gives P1[a] u0hat_i for every a.)
+ *
+ * out_prec ST_F64 or ST_F32 element type of `mats`.
+ * mats     [dev] capacity mats_cap elements; query q's w_q x w_q matrix is
+ *          stored ROW-major at element offset mat_off[q] = sum_{p<q} w_p^2.
+ * rhs      [dev] coeff_cap doubles, query q at coeff_off[q].
+ * coeff_off, mat_off  [dev] n_q + 1 int64 outputs.
+ * info     [dev] n_q int32 outputs (codes above).
+ * ====================================================================== */
+size_t st_form_workspace(const st_rom_desc* d, int32_t n_q);
+
+st_status st_form(const st_rom_desc* d, const void* rom, int32_t n_q, const double* theta_A,
+                  const double* theta_f, const double* theta_0, const int32_t* nt_q, int32_t out_prec,
+                  void* mats, int64_t mats_cap, double* rhs, int64_t coeff_cap, int64_t* coeff_off,
+                  int64_t* mat_off, int32_t* info, void* ws, size_t ws_bytes, void* stream);
+
+/* ========================================================================
+ * st_solve - reduced space-time solve for a ragged batch (Sec. 3.2,
+ * Eq. (st-galerkin); the paper does not name the dense solver: LU with
+ * partial pivoting, as LAPACK gesv).
+ *
+ * Forms each query's system (as st_form), factors it by a blocked
+ * right-looking LU with partial pivoting in lu_prec (ST_F64 or ST_F32), and
+ * solves.  With lu_prec = ST_F32 the FP32 factors drive iterative
+ * refinement: r = b - Ahat_st x is evaluated in FP64 from the ROM pieces
+ * (never from the FP32 matrix), d = LU^{-1} r, x += d, until
+ * ||r||_2 <= ir_tol ||b||_2 or ir_max refinement steps were taken.  With
+ * ST_F64, ir_max extra refinement steps (usually 0) are taken the same way.
+ * The final relative residual ||b - Ahat_st x|| / ||b|| (FP64) is written
+ * to relres in both cases.
+ *
+ * coeff    [dev] coeff_cap doubles: query q's solution at coeff_off[q].
+ * coeff_off [dev] n_q + 1 int64 outputs.
+ * relres   [dev] n_q doubles; info [dev] n_q int32; iters [dev] n_q int32
+ *          refinement steps taken (may be NULL).
+ * ws       [dev] st_solve_workspace(d, n_q, sum_w, sum_w2, lu_prec) bytes,
+ *          where sum_w = sum_q w_q and sum_w2 = sum_q w_q^2 (upper bounds
+ *          are fine: n_q * n and n_q * n^2).  A query that does not fit gets
+ *          info = -3.
+ * ====================================================================== */
+size_t st_solve_workspace(const st_rom_desc* d, int32_t n_q, int64_t sum_w, int64_t sum_w2, int32_t lu_prec);
+
+st_status st_solve(const st_rom_desc* d, const void* rom, int32_t n_q, const double* theta_A,
+                   const double* theta_f, const double* theta_0, const int32_t* nt_q, int32_t lu_prec,
+                   double ir_tol, int32_t ir_max, double* coeff, int64_t coeff_cap, int64_t* coeff_off,
+                   double* relres, int32_t* info, int32_t* iters, void* ws, size_t ws_bytes, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* STROM_H */

@@ -1,0 +1,303 @@
+// Host side of the ST-ROM C ABI: argument validation, buffer layouts and the
+// launch sequences of st_assemble, st_form and st_solve.  All launches go to
+// the caller's stream; nothing here allocates device memory or synchronises.
+#include <math.h>
+#include <string.h>
+
+#include "internal.h"
+
+using namespace strom;
+
+namespace {
+
+int64_t total_nt(const st_rom_desc* d) {
+  int64_t n = 0;
+  for (int i = 0; i < d->n_s; ++i) n += d->n_t[i];
+  return n;
+}
+
+bool desc_ok(const st_rom_desc* d) {
+  if (!d || !d->n_t) return false;
+  if (d->n_s < 1 || d->n_s > kMaxModes || d->N_t < 1) return false;
+  if (d->Q < 1 || d->Q > kMaxTerms || d->Qf < 0 || d->Qf > kMaxTerms || d->Q0 < 0 || d->Q0 > kMaxTerms) return false;
+  for (int i = 0; i < d->n_s; ++i)
+    if (d->n_t[i] < 1 || d->n_t[i] > d->N_t) return false;
+  return true;
+}
+
+void layout_of(const st_rom_desc* d, st_rom_layout_t* L) {
+  const size_t n_s = (size_t)d->n_s, n = (size_t)total_nt(d);
+  size_t k2 = 0;
+  for (int i = 0; i < d->n_s; ++i) k2 += (size_t)d->n_t[i] * d->n_t[i];
+  size_t o = 0;
+  L->Ahat = o;  o = align_up(o + sizeof(double) * d->Q * n_s * n_s);
+  L->bhat = o;  o = align_up(o + sizeof(double) * d->Qf * n_s);
+  L->u0hat = o; o = align_up(o + sizeof(double) * d->Q0 * n_s);
+  L->T = o;     o = align_up(o + sizeof(double) * n * n);
+  L->K = o;     o = align_up(o + sizeof(double) * k2);
+  L->Wf = o;    o = align_up(o + sizeof(double) * d->Qf * n);
+  L->P1 = o;    o = align_up(o + sizeof(double) * n);
+  L->mode = o;  o = align_up(o + sizeof(int32_t) * n);
+  L->moff = o;  o = align_up(o + sizeof(int32_t) * (n_s + 1));
+  L->koff = o;  o = align_up(o + sizeof(int64_t) * (n_s + 1));
+  L->total = o;
+}
+
+RomView view_of(const st_rom_desc* d, const void* rom) {
+  st_rom_layout_t L;
+  layout_of(d, &L);
+  const char* b = static_cast<const char*>(rom);
+  RomView v;
+  v.Ahat = reinterpret_cast<const double*>(b + L.Ahat);
+  v.bhat = reinterpret_cast<const double*>(b + L.bhat);
+  v.u0hat = reinterpret_cast<const double*>(b + L.u0hat);
+  v.T = reinterpret_cast<const double*>(b + L.T);
+  v.K = reinterpret_cast<const double*>(b + L.K);
+  v.Wf = reinterpret_cast<const double*>(b + L.Wf);
+  v.P1 = reinterpret_cast<const double*>(b + L.P1);
+  v.mode = reinterpret_cast<const int32_t*>(b + L.mode);
+  v.moff = reinterpret_cast<const int32_t*>(b + L.moff);
+  v.koff = reinterpret_cast<const int64_t*>(b + L.koff);
+  v.n_s = d->n_s;
+  v.N_t = d->N_t;
+  v.n = (int32_t)total_nt(d);
+  v.Q = d->Q;
+  v.Qf = d->Qf;
+  v.Q0 = d->Q0;
+  return v;
+}
+
+#define ST_TRY(expr)                              \
+  do {                                            \
+    hipError_t e_ = (expr);                       \
+    if (e_ != hipSuccess) return ST_EDEVICE;      \
+  } while (0)
+
+struct Carver {
+  char* base;
+  size_t used = 0;
+  explicit Carver(void* p) : base(static_cast<char*>(p)) {}
+  template <typename T>
+  T* take(size_t count) {
+    T* p = reinterpret_cast<T*>(base + used);
+    used = align_up(used + sizeof(T) * count);
+    return p;
+  }
+};
+
+size_t plan_bytes(int32_t n_q) {
+  size_t o = 0;
+  o = align_up(o + sizeof(int32_t) * n_q);        // width
+  o = align_up(o + sizeof(int32_t) * n_q);        // order
+  o = align_up(o + sizeof(int32_t) * 4);          // counter
+  return o;
+}
+
+bool query_args_ok(const st_rom_desc* d, const void* rom, int32_t n_q, const double* thA, const double* thf,
+                   const double* th0) {
+  if (!desc_ok(d) || !rom || n_q < 0) return false;
+  if (n_q > 0 && !thA) return false;
+  if (n_q > 0 && d->Qf > 0 && !thf) return false;
+  if (n_q > 0 && d->Q0 > 0 && !th0) return false;
+  return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* st_strerror(st_status s) {
+  switch (s) {
+    case ST_OK: return "success";
+    case ST_EINVAL: return "invalid argument";
+    case ST_EDEVICE: return "HIP runtime error";
+    case ST_EWORKSPACE: return "workspace or output buffer too small";
+    case ST_ERANK: return "requested basis exceeds the rank of the data";
+    case ST_EUNSUPPORTED: return "size or precision not supported by the kernels";
+    default: return "unknown status";
+  }
+}
+
+int32_t st_version(void) { return 1; }
+
+st_status st_rom_layout(const st_rom_desc* d, st_rom_layout_t* out) {
+  if (!desc_ok(d) || !out) return ST_EINVAL;
+  layout_of(d, out);
+  return ST_OK;
+}
+
+size_t st_assemble_workspace(const st_rom_desc* d, int64_t N_s) {
+  if (!desc_ok(d) || N_s < 1) return 0;
+  const int64_t n = total_nt(d);
+  size_t part = tsgemm_partial_elems(N_s, d->n_s, d->n_s);
+  part = part > tsgemm_partial_elems(N_s, d->n_s, d->Qf) ? part : tsgemm_partial_elems(N_s, d->n_s, d->Qf);
+  part = part > tsgemm_partial_elems(N_s, d->n_s, d->Q0) ? part : tsgemm_partial_elems(N_s, d->n_s, d->Q0);
+  part = part > tsgemm_partial_elems(d->N_t, (int32_t)n, (int32_t)n) ? part
+                                                                      : tsgemm_partial_elems(d->N_t, (int32_t)n, (int32_t)n);
+  return align_up(sizeof(double) * (size_t)N_s * d->n_s) * 2 + align_up(sizeof(double) * part);
+}
+
+st_status st_assemble(const st_rom_desc* d, int64_t N_s, const double* Phi_s, const double* Phi_t, const double* dt,
+                      const st_csr* A, const double* Bf, const double* g, const double* u0, void* rom,
+                      size_t rom_bytes, void* ws, size_t ws_bytes, void* stream) {
+  if (!desc_ok(d) || N_s < 1 || N_s > 0x7fffffff || !Phi_s || !Phi_t || !dt || !A || !rom || !ws) return ST_EINVAL;
+  if (d->n_s > N_s) return ST_ERANK;
+  if (d->Qf > 0 && !Bf) return ST_EINVAL;
+  if (d->Q0 > 0 && !u0) return ST_EINVAL;
+  for (int q = 0; q < d->Q; ++q) {
+    if (A[q].n_rows != N_s || A[q].nnz < 0 || !A[q].row_ptr) return ST_EINVAL;
+    if (A[q].nnz > 0 && (!A[q].col_idx || !A[q].val)) return ST_EINVAL;
+  }
+  const int64_t n = total_nt(d);
+  if (n > kMaxWidth * 4) return ST_EUNSUPPORTED;
+  st_rom_layout_t L;
+  layout_of(d, &L);
+  if (rom_bytes < L.total) return ST_EWORKSPACE;
+  if (ws_bytes < st_assemble_workspace(d, N_s)) return ST_EWORKSPACE;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+
+  char* rb = static_cast<char*>(rom);
+  MutRomView mv;
+  mv.Ahat = reinterpret_cast<double*>(rb + L.Ahat);
+  mv.bhat = reinterpret_cast<double*>(rb + L.bhat);
+  mv.u0hat = reinterpret_cast<double*>(rb + L.u0hat);
+  mv.T = reinterpret_cast<double*>(rb + L.T);
+  mv.K = reinterpret_cast<double*>(rb + L.K);
+  mv.Wf = reinterpret_cast<double*>(rb + L.Wf);
+  mv.P1 = reinterpret_cast<double*>(rb + L.P1);
+  mv.mode = reinterpret_cast<int32_t*>(rb + L.mode);
+  mv.moff = reinterpret_cast<int32_t*>(rb + L.moff);
+  mv.koff = reinterpret_cast<int64_t*>(rb + L.koff);
+
+  Carver c(ws);
+  double* Phir = c.take<double>((size_t)N_s * d->n_s);
+  double* Y = c.take<double>((size_t)N_s * d->n_s);
+  double* part = reinterpret_cast<double*>(c.base + c.used);
+  const size_t part_elems = (ws_bytes - c.used) / sizeof(double);
+
+  ModeTable mt;
+  memset(&mt, 0, sizeof(mt));
+  mt.n_s = d->n_s;
+  for (int i = 0; i < d->n_s; ++i) mt.nt[i] = d->n_t[i];
+  ST_TRY(launch_index_tables(mt, d->N_t, mv, s));
+  const int32_t ns = d->n_s;
+  // projection: Ahat_q = Phi_s^T (A_q Phi_s)
+  ST_TRY(launch_transpose(Phi_s, N_s, ns, N_s, Phir, s));
+  for (int q = 0; q < d->Q; ++q) {
+    ST_TRY(launch_spmm_rowmajor(A[q], Phir, ns, Y, s));
+    ST_TRY(launch_tsgemm(N_s, ns, ns, Phir, ns, 1, Y, ns, 1, mv.Ahat + (size_t)q * ns * ns, ns, part, part_elems, s));
+  }
+  if (d->Qf > 0) ST_TRY(launch_tsgemm(N_s, ns, d->Qf, Phir, ns, 1, Bf, 1, N_s, mv.bhat, ns, part, part_elems, s));
+  if (d->Q0 > 0) ST_TRY(launch_tsgemm(N_s, ns, d->Q0, Phir, ns, 1, u0, 1, N_s, mv.u0hat, ns, part, part_elems, s));
+  // temporal contractions
+  ST_TRY(launch_tsgemm_w(d->N_t, (int32_t)n, (int32_t)n, Phi_t, 1, d->N_t, Phi_t, 1, d->N_t, dt, mv.T, (int32_t)n, part,
+                         part_elems, s));
+  ST_TRY(launch_temporal(Phi_t, d->N_t, (int32_t)n, dt, g, d->Qf, mt, mv, s));
+  return ST_OK;
+}
+
+size_t st_form_workspace(const st_rom_desc* d, int32_t n_q) {
+  if (!desc_ok(d) || n_q < 0) return 0;
+  return plan_bytes(n_q);
+}
+
+st_status st_form(const st_rom_desc* d, const void* rom, int32_t n_q, const double* theta_A, const double* theta_f,
+                  const double* theta_0, const int32_t* nt_q, int32_t out_prec, void* mats, int64_t mats_cap,
+                  double* rhs, int64_t coeff_cap, int64_t* coeff_off, int64_t* mat_off, int32_t* info, void* ws,
+                  size_t ws_bytes, void* stream) {
+  if (!query_args_ok(d, rom, n_q, theta_A, theta_f, theta_0)) return ST_EINVAL;
+  if (out_prec != ST_F64 && out_prec != ST_F32) return ST_EINVAL;
+  if (d->n_s > kMaxFormModes) return ST_EUNSUPPORTED;
+  if (mats_cap < 0 || coeff_cap < 0) return ST_EINVAL;
+  if (n_q == 0) return ST_OK;
+  if (!mats || !rhs || !coeff_off || !mat_off || !info || !ws) return ST_EINVAL;
+  if (ws_bytes < st_form_workspace(d, n_q)) return ST_EWORKSPACE;
+  const int64_t n = total_nt(d);
+  if (n > kMaxWidth) return ST_EUNSUPPORTED;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  RomView rv = view_of(d, rom);
+  Carver c(ws);
+  Plan plan;
+  plan.width = c.take<int32_t>(n_q);
+  plan.order = c.take<int32_t>(n_q);
+  plan.counter = c.take<int32_t>(4);
+  plan.mat_off = mat_off;
+  plan.coeff_off = coeff_off;
+  plan.info = info;
+  ST_TRY(launch_plan(n_q, d->n_s, rv.moff, nt_q, theta_A, theta_f, theta_0, d->Q, d->Qf, d->Q0, coeff_cap, mats_cap,
+                     plan, s));
+  ST_TRY(launch_form(rv, n_q, theta_A, theta_f, theta_0, nt_q, plan, out_prec, mats, rhs, (int32_t)n, s));
+  return ST_OK;
+}
+
+size_t st_solve_workspace(const st_rom_desc* d, int32_t n_q, int64_t sum_w, int64_t sum_w2, int32_t lu_prec) {
+  if (!desc_ok(d) || n_q < 0 || sum_w < 0 || sum_w2 < 0) return 0;
+  const size_t el = lu_prec == ST_F32 ? sizeof(float) : sizeof(double);
+  size_t o = plan_bytes(n_q);
+  o = align_up(o + sizeof(int32_t) * n_q);           // active
+  o = align_up(o + sizeof(int64_t) * (n_q + 1));     // mat_off
+  o = align_up(o + sizeof(double) * n_q) * 1;        // bnorm
+  o = align_up(o + sizeof(double) * n_q);            // rnorm
+  o = align_up(o + sizeof(double) * sum_w);          // b
+  o = align_up(o + sizeof(double) * sum_w);          // r
+  o = align_up(o + sizeof(int32_t) * sum_w);         // permutations
+  o = align_up(o + el * (size_t)sum_w2);             // matrices
+  return o;
+}
+
+st_status st_solve(const st_rom_desc* d, const void* rom, int32_t n_q, const double* theta_A, const double* theta_f,
+                   const double* theta_0, const int32_t* nt_q, int32_t lu_prec, double ir_tol, int32_t ir_max,
+                   double* coeff, int64_t coeff_cap, int64_t* coeff_off, double* relres, int32_t* info,
+                   int32_t* iters, void* ws, size_t ws_bytes, void* stream) {
+  if (!query_args_ok(d, rom, n_q, theta_A, theta_f, theta_0)) return ST_EINVAL;
+  if (lu_prec != ST_F64 && lu_prec != ST_F32) return ST_EINVAL;
+  if (!(ir_tol >= 0.0) || ir_max < 0 || ir_max > 1000 || coeff_cap < 0) return ST_EINVAL;
+  if (d->n_s > kMaxFormModes) return ST_EUNSUPPORTED;
+  if (n_q == 0) return ST_OK;
+  if (!coeff || !coeff_off || !relres || !info || !ws) return ST_EINVAL;
+  const int64_t n = total_nt(d);
+  if (n > kMaxWidth) return ST_EUNSUPPORTED;
+  const size_t fixed = st_solve_workspace(d, n_q, coeff_cap, 0, lu_prec);
+  if (ws_bytes < fixed) return ST_EWORKSPACE;
+  const size_t el = lu_prec == ST_F32 ? sizeof(float) : sizeof(double);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  RomView rv = view_of(d, rom);
+
+  Carver c(ws);
+  Plan plan;
+  plan.width = c.take<int32_t>(n_q);
+  plan.order = c.take<int32_t>(n_q);
+  plan.counter = c.take<int32_t>(4);
+  int32_t* active = c.take<int32_t>(n_q);
+  plan.mat_off = c.take<int64_t>(n_q + 1);
+  double* bnorm = c.take<double>(n_q);
+  double* rnorm = c.take<double>(n_q);
+  double* b = c.take<double>(coeff_cap);
+  double* r = c.take<double>(coeff_cap);
+  int32_t* perm = c.take<int32_t>(coeff_cap);
+  void* mats = c.base + c.used;
+  const int64_t mats_cap = (int64_t)((ws_bytes - c.used) / el);
+  plan.coeff_off = coeff_off;
+  plan.info = info;
+  const int32_t n_max = (int32_t)n;
+
+  ST_TRY(launch_plan(n_q, d->n_s, rv.moff, nt_q, theta_A, theta_f, theta_0, d->Q, d->Qf, d->Q0, coeff_cap, mats_cap,
+                     plan, s));
+  ST_TRY(launch_form(rv, n_q, theta_A, theta_f, theta_0, nt_q, plan, lu_prec, mats, b, n_max, s));
+  ST_TRY(launch_vec_norms(n_q, plan, b, bnorm, s));
+  ST_TRY(launch_lu(n_q, plan, lu_prec, mats, perm, n_max, s));
+  ST_TRY(launch_fill_i32(active, n_q, 1, s));
+  ST_TRY(launch_lu_solve(n_q, plan, lu_prec, mats, perm, b, coeff, 0, active, n_max, s));
+  for (int it = 0; it < ir_max; ++it) {
+    ST_TRY(launch_residual(rv, n_q, theta_A, nt_q, plan, b, coeff, r, rnorm, active, n_max, s));
+    ST_TRY(launch_ir_check(n_q, plan, rnorm, bnorm, ir_tol, it, 0, active, relres, iters, s));
+    ST_TRY(launch_lu_solve(n_q, plan, lu_prec, mats, perm, r, coeff, 1, active, n_max, s));
+  }
+  ST_TRY(launch_residual(rv, n_q, theta_A, nt_q, plan, b, coeff, r, rnorm, nullptr, n_max, s));
+  const int flag = (lu_prec == ST_F32 || ir_max > 0) ? 2 : 1;
+  ST_TRY(launch_ir_check(n_q, plan, rnorm, bnorm, ir_tol, ir_max, flag, active, relres, iters, s));
+  ST_TRY(launch_finalize(n_q, plan, coeff, info, s));
+  return ST_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,98 @@
+// Internal declarations shared by the host API and the HIP kernel files of
+// the ST-ROM library (gfx950).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+#include "../../include/strom.h"
+
+namespace strom {
+
+constexpr int kMaxModes = 512;     // n_s limit of the index-table kernels (by-value arguments)
+constexpr int kMaxFormModes = 128; // n_s limit of the query kernels (Ahat(mu) staged in LDS)
+constexpr int kMaxTerms = 16;      // Q, Qf, Q0 limit of the query kernels
+constexpr int kMaxWidth = 4096;    // reduced width limit of the query kernels
+
+struct ModeTable {
+  int32_t n_s;
+  int32_t nt[kMaxModes];
+};
+
+// Device view of a ROM buffer.
+struct RomView {
+  const double* Ahat;   // Q x n_s x n_s
+  const double* bhat;   // Qf x n_s
+  const double* u0hat;  // Q0 x n_s
+  const double* T;      // n x n
+  const double* K;      // sum n_t^2
+  const double* Wf;     // Qf x n
+  const double* P1;     // n
+  const int32_t* mode;  // n
+  const int32_t* moff;  // n_s + 1
+  const int64_t* koff;  // n_s + 1
+  int32_t n_s, N_t, n, Q, Qf, Q0;
+};
+
+struct MutRomView {
+  double *Ahat, *bhat, *u0hat, *T, *K, *Wf, *P1;
+  int32_t *mode, *moff;
+  int64_t* koff;
+};
+
+inline size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
+
+// Query-batch plan written by the plan kernel (device memory in the workspace).
+struct Plan {
+  int32_t* width;      // n_q
+  int32_t* order;      // n_q, queries sorted by width, largest first
+  int64_t* mat_off;    // n_q + 1, element offsets of the query matrices
+  int64_t* coeff_off;  // n_q + 1, offsets of the query vectors
+  int32_t* info;       // n_q
+  int32_t* counter;    // 4 work-queue counters
+};
+
+// ----------------------------------------------------------------------------
+// kernel launchers (each defined in the .hip file that holds the kernel)
+// ----------------------------------------------------------------------------
+
+// k_offline.hip: projection (a5) and temporal contractions (a6)
+hipError_t launch_index_tables(const ModeTable& mt, int32_t N_t, MutRomView rom, hipStream_t s);
+hipError_t launch_transpose(const double* src, int64_t rows, int32_t cols, int64_t ld, double* dst, hipStream_t s);
+hipError_t launch_spmm_rowmajor(const st_csr& A, const double* Xr, int32_t p, double* Yr, hipStream_t s);
+// C (p x q, column-major, ldc) = X^T Y over N rows; X element (r,a) at X[r*xrs + a*xcs]
+hipError_t launch_tsgemm(int64_t N, int32_t p, int32_t q, const double* X, int64_t xrs, int64_t xcs,
+                         const double* Y, int64_t yrs, int64_t ycs, double* C, int32_t ldc, double* partial,
+                         size_t partial_elems, hipStream_t s);
+hipError_t launch_tsgemm_w(int64_t N, int32_t p, int32_t q, const double* X, int64_t xrs, int64_t xcs,
+                           const double* Y, int64_t yrs, int64_t ycs, const double* wrow, double* C, int32_t ldc,
+                           double* partial, size_t partial_elems, hipStream_t s);
+size_t tsgemm_partial_elems(int64_t N, int32_t p, int32_t q);
+hipError_t launch_temporal(const double* Phi_t, int32_t N_t, int32_t n, const double* dt, const double* g, int32_t Qf,
+                           const ModeTable& mt, MutRomView rom, hipStream_t s);
+
+// k_query.hip: plan (per-query offsets), assembly (a7), residual
+hipError_t launch_plan(int32_t n_q, int32_t n_s, const int32_t* full_nt_dev, const int32_t* nt_q, const double* thA,
+                       const double* thf, const double* th0, int32_t Q, int32_t Qf, int32_t Q0, int64_t coeff_cap,
+                       int64_t mat_cap, Plan plan, hipStream_t s);
+hipError_t launch_form(const RomView& rom, int32_t n_q, const double* thA, const double* thf, const double* th0,
+                       const int32_t* nt_q, Plan plan, int32_t out_prec, void* mats, double* rhs, int32_t n_max,
+                       hipStream_t s);
+hipError_t launch_residual(const RomView& rom, int32_t n_q, const double* thA, const int32_t* nt_q, Plan plan,
+                           const double* rhs, const double* x, double* r, double* rnorm, const int32_t* active,
+                           int32_t n_max, hipStream_t s);
+
+// k_lu.hip: batched LU (a8) and triangular solves
+hipError_t launch_lu(int32_t n_q, Plan plan, int32_t prec, void* mats, int32_t* piv, int32_t n_max, hipStream_t s);
+// x (or x += solution when accumulate) for every active query: solve LU x = b
+hipError_t launch_lu_solve(int32_t n_q, Plan plan, int32_t prec, const void* mats, const int32_t* piv, const double* b,
+                           double* x, int accumulate, const int32_t* active, int32_t n_max, hipStream_t s);
+// refinement bookkeeping: relres, convergence flags, NaN for failed queries
+hipError_t launch_ir_check(int32_t n_q, Plan plan, const double* rnorm, const double* bnorm, double tol, int32_t step,
+                           int32_t last, int32_t* active, double* relres, int32_t* iters, hipStream_t s);
+hipError_t launch_vec_norms(int32_t n_q, Plan plan, const double* v, double* norms, hipStream_t s);
+hipError_t launch_finalize(int32_t n_q, Plan plan, double* coeff, int32_t* info_out, hipStream_t s);
+hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
+
+}  // namespace strom

@@ -1,0 +1,254 @@
+// Offline reduced operators on gfx950:
+//   * projection of the affine operator terms onto the spatial basis,
+//     Ahat_q = Phi_s^T (A_q Phi_s) (Sec. 3.1, Eq. (galerkin)), as a CSR SpMM
+//     against the row-major tall-skinny basis followed by a split-K
+//     tall-skinny product;
+//   * the mu-independent temporal contractions of the block formulas
+//     (Sec. 4.3, Eq. (ij-block-matrix), (j-block-vector)): the dt-weighted
+//     temporal Gram T, the per-mode blocks K_i, the input weights Wf and
+//     the first-step values P1.
+#include "internal.h"
+
+namespace strom {
+namespace {
+
+constexpr int kTile = 32;
+
+__global__ void index_tables_kernel(ModeTable mt, MutRomView rom) {
+  // one workgroup; n_s <= kMaxModes
+  __shared__ int32_t s_off[kMaxModes + 1];
+  const int n_s = mt.n_s;
+  if (threadIdx.x == 0) {
+    int32_t o = 0;
+    int64_t ko = 0;
+    for (int i = 0; i < n_s; ++i) {
+      s_off[i] = o;
+      rom.moff[i] = o;
+      rom.koff[i] = ko;
+      o += mt.nt[i];
+      ko += (int64_t)mt.nt[i] * mt.nt[i];
+    }
+    s_off[n_s] = o;
+    rom.moff[n_s] = o;
+    rom.koff[n_s] = ko;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < n_s; i += blockDim.x)
+    for (int j = s_off[i]; j < s_off[i + 1]; ++j) rom.mode[j] = i;
+}
+
+// dst (rows x cols, row-major) = src (rows x cols, column-major, leading dimension ld)
+__global__ void transpose_kernel(const double* __restrict__ src, int64_t rows, int32_t cols, int64_t ld,
+                                 double* __restrict__ dst) {
+  __shared__ double tile[kTile][kTile + 1];
+  const int64_t r0 = (int64_t)blockIdx.x * kTile;
+  const int c0 = blockIdx.y * kTile;
+  const int tx = threadIdx.x % kTile, ty = threadIdx.x / kTile;  // 32 x 8
+  for (int cc = ty; cc < kTile; cc += 8) {
+    int64_t r = r0 + tx;
+    int c = c0 + cc;
+    tile[cc][tx] = (r < rows && c < cols) ? src[r + (int64_t)c * ld] : 0.0;
+  }
+  __syncthreads();
+  for (int rr = ty; rr < kTile; rr += 8) {
+    int64_t r = r0 + rr;
+    int c = c0 + tx;
+    if (r < rows && c < cols) dst[r * cols + c] = tile[tx][rr];
+  }
+}
+
+// Yr (N x p, row-major) = A (CSR, N x N) * Xr (N x p, row-major); one wave per row,
+// lanes across the p columns so every gathered basis row is read contiguously.
+__global__ __launch_bounds__(256) void spmm_rowmajor_kernel(int32_t n_rows, const int32_t* __restrict__ row_ptr,
+                                                           const int32_t* __restrict__ col_idx,
+                                                           const double* __restrict__ val,
+                                                           const double* __restrict__ Xr, int32_t p,
+                                                           double* __restrict__ Yr) {
+  const int lane = threadIdx.x & 63;
+  const int64_t row = (int64_t)blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;
+  if (row >= n_rows) return;
+  const int32_t b = row_ptr[row], e = row_ptr[row + 1];
+  for (int m0 = 0; m0 < p; m0 += 64) {
+    const int m = m0 + lane;
+    double acc = 0.0;
+    if (m < p) {
+      for (int32_t z = b; z < e; ++z) acc = fma(val[z], Xr[(int64_t)col_idx[z] * p + m], acc);
+      Yr[row * p + m] = acc;
+    }
+  }
+}
+
+// Split-K tall-skinny product: partial[z] (p x q, column-major) = sum over the
+// z-th row range of w[r] X[r,:]^T Y[r,:].  32 x 32 output tile per workgroup.
+__global__ __launch_bounds__(256) void tsgemm_partial_kernel(int64_t N, int32_t p, int32_t q,
+                                                            const double* __restrict__ X, int64_t xrs, int64_t xcs,
+                                                            const double* __restrict__ Y, int64_t yrs, int64_t ycs,
+                                                            const double* __restrict__ wrow, int64_t rows_per_split,
+                                                            double* __restrict__ partial) {
+  __shared__ double Xs[kTile][kTile + 1];
+  __shared__ double Ys[kTile][kTile + 1];
+  const int a0 = blockIdx.x * kTile, b0 = blockIdx.y * kTile;
+  const int64_t rbeg = (int64_t)blockIdx.z * rows_per_split;
+  const int64_t rend = min(N, rbeg + rows_per_split);
+  const int tx = threadIdx.x % kTile, ty = threadIdx.x / kTile;  // 32 x 8
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  const bool x_rows_contig = (xrs == 1);
+  const bool y_rows_contig = (yrs == 1);
+  for (int64_t r0 = rbeg; r0 < rend; r0 += kTile) {
+    for (int i = threadIdx.x; i < kTile * kTile; i += blockDim.x) {
+      int kk, a;
+      if (x_rows_contig) { kk = i % kTile; a = i / kTile; } else { a = i % kTile; kk = i / kTile; }
+      const int64_t r = r0 + kk;
+      double v = 0.0;
+      if (r < rend && a0 + a < p) {
+        v = X[r * xrs + (int64_t)(a0 + a) * xcs];
+        if (wrow) v *= wrow[r];
+      }
+      Xs[kk][a] = v;
+      int bb;
+      if (y_rows_contig) { kk = i % kTile; bb = i / kTile; } else { bb = i % kTile; kk = i / kTile; }
+      const int64_t r2 = r0 + kk;
+      Ys[kk][bb] = (r2 < rend && b0 + bb < q) ? Y[r2 * yrs + (int64_t)(b0 + bb) * ycs] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll 8
+    for (int kk = 0; kk < kTile; ++kk) {
+      const double yv = Ys[kk][tx];
+#pragma unroll
+      for (int s = 0; s < 4; ++s) acc[s] = fma(Xs[kk][ty + 8 * s], yv, acc[s]);
+    }
+    __syncthreads();
+  }
+  double* out = partial + (int64_t)blockIdx.z * p * q;
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    const int a = a0 + ty + 8 * s, b = b0 + tx;
+    if (a < p && b < q) out[a + (int64_t)b * p] = acc[s];
+  }
+}
+
+// C[a + b*ldc] = sum_z partial[z][a + b*p], summed in split order (deterministic).
+__global__ void tsgemm_reduce_kernel(int32_t p, int32_t q, int32_t splits, const double* __restrict__ partial,
+                                     double* __restrict__ C, int32_t ldc) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t pq = (int64_t)p * q;
+  if (e >= pq) return;
+  double s = 0.0;
+  for (int z = 0; z < splits; ++z) s += partial[z * pq + e];
+  const int a = (int)(e % p), b = (int)(e / p);
+  C[a + (int64_t)b * ldc] = s;
+}
+
+int tsgemm_splits(int64_t N, int32_t p, int32_t q) {
+  const int64_t tiles = (int64_t)((p + kTile - 1) / kTile) * ((q + kTile - 1) / kTile);
+  if (tiles <= 0 || N <= 0) return 1;
+  int64_t splits = (512 + tiles - 1) / tiles;
+  const int64_t max_splits = (N + 255) / 256;
+  if (splits > max_splits) splits = max_splits;
+  if (splits < 1) splits = 1;
+  return (int)splits;
+}
+
+// K_i[j',j] = sum_k phi_ij'(k) phi_ij(k) - sum_{k < N_t - 1} phi_ij'(k+1) phi_ij(k), one mode per workgroup.
+__global__ __launch_bounds__(256) void temporal_K_kernel(const double* __restrict__ Phi, int32_t N_t,
+                                                        const int32_t* __restrict__ moff,
+                                                        const int64_t* __restrict__ koff, double* __restrict__ K) {
+  const int i = blockIdx.x;
+  const int c0 = moff[i];
+  const int nt = moff[i + 1] - c0;
+  const double* P = Phi + (int64_t)c0 * N_t;
+  for (int e = threadIdx.x; e < nt * nt; e += blockDim.x) {
+    const int jp = e % nt, j = e / nt;
+    const double* a = P + (int64_t)jp * N_t;
+    const double* b = P + (int64_t)j * N_t;
+    double g = 0.0, sh = 0.0;
+    for (int k = 0; k < N_t; ++k) g = fma(a[k], b[k], g);
+    for (int k = 0; k + 1 < N_t; ++k) sh = fma(a[k + 1], b[k], sh);
+    K[koff[i] + jp + (int64_t)j * nt] = g - sh;
+  }
+}
+
+// Wf[q*n + a] = sum_k dt_k g[k,q] phi_a(k) and P1[a] = phi_a(0): one wave per column a.
+__global__ __launch_bounds__(256) void temporal_vec_kernel(const double* __restrict__ Phi, int32_t N_t, int32_t n,
+                                                          const double* __restrict__ dt,
+                                                          const double* __restrict__ g, int32_t Qf,
+                                                          double* __restrict__ Wf, double* __restrict__ P1) {
+  const int lane = threadIdx.x & 63;
+  const int a = blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;
+  if (a >= n) return;
+  const double* col = Phi + (int64_t)a * N_t;
+  if (lane == 0) P1[a] = col[0];
+  for (int qf = 0; qf < Qf; ++qf) {
+    double s = 0.0;
+    for (int k = lane; k < N_t; k += 64) s = fma(dt[k] * (g ? g[k + (int64_t)qf * N_t] : 1.0), col[k], s);
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+    if (lane == 0) Wf[(int64_t)qf * n + a] = s;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_index_tables(const ModeTable& mt, int32_t N_t, MutRomView rom, hipStream_t s) {
+  (void)N_t;
+  hipLaunchKernelGGL(index_tables_kernel, dim3(1), dim3(256), 0, s, mt, rom);
+  return hipGetLastError();
+}
+
+hipError_t launch_transpose(const double* src, int64_t rows, int32_t cols, int64_t ld, double* dst, hipStream_t s) {
+  if (rows == 0 || cols == 0) return hipSuccess;
+  dim3 grid((unsigned)((rows + kTile - 1) / kTile), (unsigned)((cols + kTile - 1) / kTile));
+  hipLaunchKernelGGL(transpose_kernel, grid, dim3(256), 0, s, src, rows, cols, ld, dst);
+  return hipGetLastError();
+}
+
+hipError_t launch_spmm_rowmajor(const st_csr& A, const double* Xr, int32_t p, double* Yr, hipStream_t s) {
+  if (A.n_rows == 0) return hipSuccess;
+  const int rows_per_block = 4;
+  dim3 grid((unsigned)((A.n_rows + rows_per_block - 1) / rows_per_block));
+  hipLaunchKernelGGL(spmm_rowmajor_kernel, grid, dim3(256), 0, s, A.n_rows, A.row_ptr, A.col_idx, A.val, Xr, p, Yr);
+  return hipGetLastError();
+}
+
+size_t tsgemm_partial_elems(int64_t N, int32_t p, int32_t q) {
+  if (p <= 0 || q <= 0) return 0;
+  return (size_t)tsgemm_splits(N, p, q) * (size_t)p * (size_t)q;
+}
+
+hipError_t launch_tsgemm_w(int64_t N, int32_t p, int32_t q, const double* X, int64_t xrs, int64_t xcs, const double* Y,
+                           int64_t yrs, int64_t ycs, const double* wrow, double* C, int32_t ldc, double* partial,
+                           size_t partial_elems, hipStream_t s) {
+  if (p == 0 || q == 0) return hipSuccess;
+  const int splits = tsgemm_splits(N, p, q);
+  if ((size_t)splits * p * q > partial_elems) return hipErrorInvalidValue;
+  int64_t rps = (N + splits - 1) / splits;
+  rps = (rps + kTile - 1) / kTile * kTile;
+  dim3 grid((p + kTile - 1) / kTile, (q + kTile - 1) / kTile, splits);
+  hipLaunchKernelGGL(tsgemm_partial_kernel, grid, dim3(256), 0, s, N, p, q, X, xrs, xcs, Y, yrs, ycs, wrow, rps,
+                     partial);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int64_t pq = (int64_t)p * q;
+  hipLaunchKernelGGL(tsgemm_reduce_kernel, dim3((unsigned)((pq + 255) / 256)), dim3(256), 0, s, p, q, splits,
+                     partial, C, ldc);
+  return hipGetLastError();
+}
+
+hipError_t launch_tsgemm(int64_t N, int32_t p, int32_t q, const double* X, int64_t xrs, int64_t xcs, const double* Y,
+                         int64_t yrs, int64_t ycs, double* C, int32_t ldc, double* partial, size_t partial_elems,
+                         hipStream_t s) {
+  return launch_tsgemm_w(N, p, q, X, xrs, xcs, Y, yrs, ycs, nullptr, C, ldc, partial, partial_elems, s);
+}
+
+hipError_t launch_temporal(const double* Phi_t, int32_t N_t, int32_t n, const double* dt, const double* g, int32_t Qf,
+                           const ModeTable& mt, MutRomView rom, hipStream_t s) {
+  // T is formed by the caller with launch_tsgemm_w (weights dt); this launches K, Wf and P1.
+  hipError_t e = hipSuccess;
+  hipLaunchKernelGGL(temporal_K_kernel, dim3(mt.n_s), dim3(256), 0, s, Phi_t, N_t, (const int32_t*)rom.moff,
+                     (const int64_t*)rom.koff, rom.K);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(temporal_vec_kernel, dim3((n + 3) / 4), dim3(256), 0, s, Phi_t, N_t, n, dt, g, Qf, rom.Wf,
+                     rom.P1);
+  return hipGetLastError();
+}
+
+}  // namespace strom

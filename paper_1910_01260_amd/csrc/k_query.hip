@@ -1,0 +1,378 @@
+// Per-query kernels of the online phase on gfx950:
+//   * plan: widths, packed offsets, validation and a largest-first order;
+//   * form: the reduced space-time system of every query (Sec. 4.3,
+//     Eq. (ij-block-matrix), (j-block-vector), projection of u0_st),
+//     streamed row-major to HBM with coalesced stores;
+//   * residual: r = b - Ahat_st(mu) x in FP64 evaluated from the ROM pieces
+//     (T, K, Ahat_q), never from a stored matrix;
+//   * small bookkeeping kernels for iterative refinement.
+#include "internal.h"
+
+namespace strom {
+namespace {
+
+constexpr int kPlanThreads = 1024;
+constexpr int kFormRows = 32;     // rows of one query per workgroup
+constexpr int kFormThreads = 256;
+
+__device__ inline bool finite_d(double v) { return v == v && v - v == 0.0; }
+
+// One workgroup.  Writes width, info, coeff_off, mat_off, order, and zeroes the counters.
+__global__ __launch_bounds__(kPlanThreads) void plan_kernel(int32_t n_q, int32_t n_s, const int32_t* __restrict__ moff,
+                                                            const int32_t* __restrict__ nt_q,
+                                                            const double* __restrict__ thA,
+                                                            const double* __restrict__ thf,
+                                                            const double* __restrict__ th0, int32_t Q, int32_t Qf,
+                                                            int32_t Q0, int64_t coeff_cap, int64_t mat_cap, Plan plan) {
+  __shared__ int64_t s_w[kPlanThreads];
+  __shared__ int64_t s_w2[kPlanThreads];
+  __shared__ int32_t s_cnt[kMaxWidth + 1];
+  const int tid = threadIdx.x;
+  // 1. widths and validation
+  for (int q = tid; q < n_q; q += kPlanThreads) {
+    int32_t code = 0;
+    int64_t w = 0;
+    for (int i = 0; i < n_s; ++i) {
+      const int32_t full = moff[i + 1] - moff[i];
+      const int32_t v = nt_q ? nt_q[(int64_t)q * n_s + i] : full;
+      if (v < 0 || v > full) code = -4;
+      w += v;
+    }
+    for (int k = 0; k < Q; ++k) if (!finite_d(thA[(int64_t)q * Q + k])) code = code ? code : -5;
+    for (int k = 0; k < Qf; ++k) if (!finite_d(thf[(int64_t)q * Qf + k])) code = code ? code : -5;
+    for (int k = 0; k < Q0; ++k) if (!finite_d(th0[(int64_t)q * Q0 + k])) code = code ? code : -5;
+    if (w > kMaxWidth) code = code ? code : -3;
+    plan.info[q] = code;
+    plan.width[q] = code ? 0 : (int32_t)w;
+  }
+  __syncthreads();
+  // 2. exclusive prefix sums of w and w^2 over contiguous chunks
+  const int per = (n_q + kPlanThreads - 1) / kPlanThreads;
+  const int qb = min(n_q, tid * per), qe = min(n_q, qb + per);
+  int64_t sw = 0, sw2 = 0;
+  for (int q = qb; q < qe; ++q) {
+    const int64_t w = plan.width[q];
+    sw += w;
+    sw2 += w * w;
+  }
+  s_w[tid] = sw;
+  s_w2[tid] = sw2;
+  __syncthreads();
+  for (int off = 1; off < kPlanThreads; off <<= 1) {
+    int64_t a = 0, b = 0;
+    if (tid >= off) { a = s_w[tid - off]; b = s_w2[tid - off]; }
+    __syncthreads();
+    s_w[tid] += a;
+    s_w2[tid] += b;
+    __syncthreads();
+  }
+  int64_t cw = s_w[tid] - sw, cw2 = s_w2[tid] - sw2;
+  for (int q = qb; q < qe; ++q) {
+    const int64_t w = plan.width[q];
+    plan.coeff_off[q] = cw;
+    plan.mat_off[q] = cw2;
+    cw += w;
+    cw2 += w * w;
+    if (plan.info[q] == 0 && (cw > coeff_cap || cw2 > mat_cap)) plan.info[q] = -3;
+  }
+  if (tid == kPlanThreads - 1) {
+    plan.coeff_off[n_q] = s_w[tid];
+    plan.mat_off[n_q] = s_w2[tid];
+  }
+  // 3. order by width, largest first (counting sort; order within a width is irrelevant)
+  for (int i = tid; i <= kMaxWidth; i += kPlanThreads) s_cnt[i] = 0;
+  __syncthreads();
+  for (int q = tid; q < n_q; q += kPlanThreads) atomicAdd(&s_cnt[plan.width[q]], 1);
+  __syncthreads();
+  if (tid == 0) {
+    int32_t pos = 0;
+    for (int w = kMaxWidth; w >= 0; --w) {
+      const int32_t c = s_cnt[w];
+      s_cnt[w] = pos;
+      pos += c;
+    }
+  }
+  __syncthreads();
+  for (int q = tid; q < n_q; q += kPlanThreads) {
+    const int32_t p = atomicAdd(&s_cnt[plan.width[q]], 1);
+    plan.order[p] = q;
+  }
+  if (tid < 4) plan.counter[tid] = 0;
+}
+
+// Shared per-query setup: local -> global reduced index, local -> mode, local mode offsets,
+// and Ahat(mu) = sum_q theta_q Ahat_q in LDS.
+struct QueryLds {
+  int32_t* gmap;   // w
+  int16_t* mmap;   // w
+  int32_t* loff;   // n_s + 1
+  double* Ah;      // n_s * n_s
+};
+
+__device__ inline void query_setup(const RomView& rom, int32_t q, const double* __restrict__ thA,
+                                   const int32_t* __restrict__ nt_q, QueryLds L) {
+  const int n_s = rom.n_s;
+  if (threadIdx.x == 0) {
+    int32_t o = 0;
+    for (int i = 0; i < n_s; ++i) {
+      L.loff[i] = o;
+      o += nt_q ? nt_q[(int64_t)q * n_s + i] : (rom.moff[i + 1] - rom.moff[i]);
+    }
+    L.loff[n_s] = o;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < n_s; i += blockDim.x) {
+    const int32_t b = L.loff[i], e = L.loff[i + 1], g0 = rom.moff[i];
+    for (int32_t c = b; c < e; ++c) {
+      L.gmap[c] = g0 + (c - b);
+      L.mmap[c] = (int16_t)i;
+    }
+  }
+  const int ns2 = n_s * n_s;
+  for (int e = threadIdx.x; e < ns2; e += blockDim.x) {
+    double v = 0.0;
+    for (int k = 0; k < rom.Q; ++k) v = fma(thA[(int64_t)q * rom.Q + k], rom.Ahat[(int64_t)k * ns2 + e], v);
+    L.Ah[e] = v;
+  }
+  __syncthreads();
+}
+
+__device__ inline QueryLds carve_lds(char* base, int n_s, int w_max) {
+  QueryLds L;
+  L.Ah = reinterpret_cast<double*>(base);
+  L.gmap = reinterpret_cast<int32_t*>(base + sizeof(double) * n_s * n_s);
+  L.loff = L.gmap + w_max;
+  L.mmap = reinterpret_cast<int16_t*>(L.loff + n_s + 1);
+  return L;
+}
+
+__host__ __device__ inline size_t query_lds_bytes(int n_s, int w_max) {
+  return sizeof(double) * n_s * n_s + sizeof(int32_t) * (w_max + n_s + 1) + sizeof(int16_t) * w_max + 16;
+}
+
+template <typename OutT>
+__global__ __launch_bounds__(kFormThreads) void form_kernel(RomView rom, int32_t n_q, const double* __restrict__ thA,
+                                                            const double* __restrict__ thf,
+                                                            const double* __restrict__ th0,
+                                                            const int32_t* __restrict__ nt_q, Plan plan,
+                                                            OutT* __restrict__ mats, double* __restrict__ rhs,
+                                                            int32_t w_max) {
+  extern __shared__ __align__(16) char lds[];
+  const int32_t q = blockIdx.y;
+  if (plan.info[q] != 0) return;
+  const int32_t w = plan.width[q];
+  const int32_t r0 = blockIdx.x * kFormRows;
+  if (r0 >= w) return;
+  QueryLds L = carve_lds(lds, rom.n_s, w_max);
+  query_setup(rom, q, thA, nt_q, L);
+  const int n_s = rom.n_s;
+  const int64_t n = rom.n;
+  OutT* M = mats + plan.mat_off[q];
+  const int rend = min(w, r0 + kFormRows);
+  for (int r = r0; r < rend; ++r) {
+    const int ir = L.mmap[r];
+    const int gr = L.gmap[r];
+    const int jr = gr - rom.moff[ir];
+    const double* Tcol = rom.T + (int64_t)gr * n;  // T symmetric: column gr holds row gr
+    const int ntr = rom.moff[ir + 1] - rom.moff[ir];
+    const double* Kr = rom.K + rom.koff[ir] + jr;  // K_ir[jr, j] at Kr[j * ntr]
+    const double* Ahr = L.Ah + ir;                 // Ahat(mu)[ir, ic] at Ahr[ic * n_s]
+    OutT* Mr = M + (int64_t)r * w;
+    for (int c = threadIdx.x; c < w; c += kFormThreads) {
+      const int ic = L.mmap[c];
+      const int gc = L.gmap[c];
+      double v = -Ahr[ic * n_s] * Tcol[gc];
+      if (ic == ir) v += Kr[(int64_t)(gc - rom.moff[ic]) * ntr];
+      Mr[c] = (OutT)v;
+    }
+  }
+  // right-hand side of these rows
+  for (int r = r0 + threadIdx.x; r < rend; r += kFormThreads) {
+    const int i = L.mmap[r];
+    const int g = L.gmap[r];
+    double b = 0.0;
+    for (int k = 0; k < rom.Qf; ++k)
+      b = fma(thf[(int64_t)q * rom.Qf + k] * rom.Wf[(int64_t)k * n + g], rom.bhat[(int64_t)k * n_s + i], b);
+    double u0 = 0.0;
+    for (int k = 0; k < rom.Q0; ++k) u0 = fma(th0[(int64_t)q * rom.Q0 + k], rom.u0hat[(int64_t)k * n_s + i], u0);
+    rhs[plan.coeff_off[q] + r] = fma(rom.P1[g], u0, b);
+  }
+}
+
+// r = b - Ahat_st(mu) x for rows [r0, r0 + kFormRows) of each active query; one wave per row.
+__global__ __launch_bounds__(kFormThreads) void residual_kernel(RomView rom, int32_t n_q,
+                                                                const double* __restrict__ thA,
+                                                                const int32_t* __restrict__ nt_q, Plan plan,
+                                                                const double* __restrict__ rhs,
+                                                                const double* __restrict__ x, double* __restrict__ r,
+                                                                const int32_t* __restrict__ active, int32_t w_max) {
+  extern __shared__ __align__(16) char lds[];
+  const int32_t q = blockIdx.y;
+  if (plan.info[q] != 0) return;
+  if (active && !active[q]) return;
+  const int32_t w = plan.width[q];
+  const int32_t r0 = blockIdx.x * kFormRows;
+  if (r0 >= w) return;
+  QueryLds L = carve_lds(lds, rom.n_s, w_max);
+  double* xs = reinterpret_cast<double*>(lds + ((query_lds_bytes(rom.n_s, w_max) + 15) / 16) * 16);
+  const int64_t off = plan.coeff_off[q];
+  for (int c = threadIdx.x; c < w; c += kFormThreads) xs[c] = x[off + c];
+  query_setup(rom, q, thA, nt_q, L);
+  const int n_s = rom.n_s;
+  const int64_t n = rom.n;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int rend = min(w, r0 + kFormRows);
+  for (int row = r0 + wave; row < rend; row += kFormThreads / 64) {
+    const int ir = L.mmap[row];
+    const int gr = L.gmap[row];
+    const int jr = gr - rom.moff[ir];
+    const double* Tcol = rom.T + (int64_t)gr * n;
+    const int ntr = rom.moff[ir + 1] - rom.moff[ir];
+    const double* Kr = rom.K + rom.koff[ir] + jr;
+    const double* Ahr = L.Ah + ir;
+    double acc = 0.0;
+    for (int c = lane; c < w; c += 64) {
+      const int ic = L.mmap[c];
+      const int gc = L.gmap[c];
+      double v = -Ahr[ic * n_s] * Tcol[gc];
+      if (ic == ir) v += Kr[(int64_t)(gc - rom.moff[ic]) * ntr];
+      acc = fma(v, xs[c], acc);
+    }
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+    if (lane == 0) r[off + row] = rhs[off + row] - acc;
+  }
+}
+
+// norms[q] = ||v_q||_2 over the query's segment; one workgroup per query, fixed reduction order.
+__global__ __launch_bounds__(256) void vec_norms_kernel(int32_t n_q, Plan plan, const double* __restrict__ v,
+                                                        double* __restrict__ norms) {
+  __shared__ double red[256];
+  const int32_t q = blockIdx.x;
+  const int32_t w = plan.width[q];
+  const int64_t off = plan.coeff_off[q];
+  double s = 0.0;
+  if (plan.info[q] == 0)
+    for (int c = threadIdx.x; c < w; c += 256) s = fma(v[off + c], v[off + c], s);
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int k = 128; k > 0; k >>= 1) {
+    if (threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) norms[q] = sqrt(red[0]);
+}
+
+// Refinement bookkeeping for step `step` (last != 0: final check).
+__global__ void ir_check_kernel(int32_t n_q, Plan plan, const double* __restrict__ rnorm,
+                                const double* __restrict__ bnorm, double tol, int32_t step, int32_t last,
+                                int32_t* __restrict__ active, double* __restrict__ relres, int32_t* __restrict__ iters) {
+  const int32_t q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= n_q) return;
+  if (plan.info[q] != 0) {
+    if (last) relres[q] = __longlong_as_double(0x7ff8000000000000LL);
+    return;
+  }
+  const double bn = bnorm[q];
+  const double rel = bn > 0.0 ? rnorm[q] / bn : rnorm[q];
+  if (last) {
+    relres[q] = rel;
+    if (iters && active[q]) iters[q] = step;
+    if (tol > 0.0 && last > 1 && !(rel <= tol)) plan.info[q] = -1;
+    return;
+  }
+  if (!active[q]) return;
+  if (rel <= tol) {
+    active[q] = 0;
+    if (iters) iters[q] = step;
+  }
+}
+
+__global__ void finalize_kernel(int32_t n_q, Plan plan, double* __restrict__ coeff) {
+  const int32_t q = blockIdx.y;
+  if (plan.info[q] <= 0) return;
+  const int32_t w = plan.width[q];
+  const int64_t off = plan.coeff_off[q];
+  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < w; c += gridDim.x * blockDim.x)
+    coeff[off + c] = __longlong_as_double(0x7ff8000000000000LL);
+}
+
+__global__ void fill_i32_kernel(int32_t* p, int64_t n, int32_t v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+}  // namespace
+
+hipError_t launch_plan(int32_t n_q, int32_t n_s, const int32_t* moff, const int32_t* nt_q, const double* thA,
+                       const double* thf, const double* th0, int32_t Q, int32_t Qf, int32_t Q0, int64_t coeff_cap,
+                       int64_t mat_cap, Plan plan, hipStream_t s) {
+  hipLaunchKernelGGL(plan_kernel, dim3(1), dim3(kPlanThreads), 0, s, n_q, n_s, moff, nt_q, thA, thf, th0, Q, Qf, Q0,
+                     coeff_cap, mat_cap, plan);
+  return hipGetLastError();
+}
+
+hipError_t launch_form(const RomView& rom, int32_t n_q, const double* thA, const double* thf, const double* th0,
+                       const int32_t* nt_q, Plan plan, int32_t out_prec, void* mats, double* rhs, int32_t n_max,
+                       hipStream_t s) {
+  if (n_q == 0 || n_max == 0) return hipSuccess;
+  const size_t lds = query_lds_bytes(rom.n_s, n_max);
+  dim3 grid((n_max + kFormRows - 1) / kFormRows, n_q);
+  if (out_prec == ST_F64) {
+    hipError_t e = hipFuncSetAttribute((const void*)form_kernel<double>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(form_kernel<double>, grid, dim3(kFormThreads), lds, s, rom, n_q, thA, thf, th0, nt_q, plan,
+                       (double*)mats, rhs, n_max);
+  } else {
+    hipError_t e = hipFuncSetAttribute((const void*)form_kernel<float>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(form_kernel<float>, grid, dim3(kFormThreads), lds, s, rom, n_q, thA, thf, th0, nt_q, plan,
+                       (float*)mats, rhs, n_max);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_residual(const RomView& rom, int32_t n_q, const double* thA, const int32_t* nt_q, Plan plan,
+                           const double* rhs, const double* x, double* r, double* rnorm, const int32_t* active,
+                           int32_t n_max, hipStream_t s) {
+  if (n_q == 0 || n_max == 0) return hipSuccess;
+  const size_t lds = ((query_lds_bytes(rom.n_s, n_max) + 15) / 16) * 16 + sizeof(double) * n_max;
+  hipError_t e = hipFuncSetAttribute((const void*)residual_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)lds);
+  if (e != hipSuccess) return e;
+  dim3 grid((n_max + kFormRows - 1) / kFormRows, n_q);
+  hipLaunchKernelGGL(residual_kernel, grid, dim3(kFormThreads), lds, s, rom, n_q, thA, nt_q, plan, rhs, x, r, active,
+                     n_max);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  return launch_vec_norms(n_q, plan, r, rnorm, s);
+}
+
+hipError_t launch_vec_norms(int32_t n_q, Plan plan, const double* v, double* norms, hipStream_t s) {
+  if (n_q == 0) return hipSuccess;
+  hipLaunchKernelGGL(vec_norms_kernel, dim3(n_q), dim3(256), 0, s, n_q, plan, v, norms);
+  return hipGetLastError();
+}
+
+hipError_t launch_ir_check(int32_t n_q, Plan plan, const double* rnorm, const double* bnorm, double tol, int32_t step,
+                           int32_t last, int32_t* active, double* relres, int32_t* iters, hipStream_t s) {
+  if (n_q == 0) return hipSuccess;
+  hipLaunchKernelGGL(ir_check_kernel, dim3((n_q + 255) / 256), dim3(256), 0, s, n_q, plan, rnorm, bnorm, tol, step,
+                     last, active, relres, iters);
+  return hipGetLastError();
+}
+
+hipError_t launch_finalize(int32_t n_q, Plan plan, double* coeff, int32_t* info_out, hipStream_t s) {
+  (void)info_out;
+  if (n_q == 0) return hipSuccess;
+  hipLaunchKernelGGL(finalize_kernel, dim3(4, n_q), dim3(256), 0, s, n_q, plan, coeff);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_i32_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n, v);
+  return hipGetLastError();
+}
+
+}  // namespace strom

@@ -1,0 +1,275 @@
+"""ctypes binding of libstrom.so (the gfx950 ST-ROM library).
+
+Functions carry the C ABI's names and only marshal arguments: torch device
+tensors are passed as raw pointers, outputs and workspaces are allocated with
+torch (device memory plumbing), and the current torch stream is handed to the
+library.  Every computation runs in the library's HIP kernels; if the library
+is missing this module raises instead of falling back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libstrom.so")
+
+ST_F64, ST_F32, ST_BF16X3 = 0, 1, 2
+ST_OK = 0
+
+
+class StromError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        super().__init__(f"{where}: {st_strerror(code)} (status {code})")
+        self.code = code
+
+
+class st_csr(ctypes.Structure):
+    _fields_ = [("n_rows", ctypes.c_int32), ("nnz", ctypes.c_int64), ("row_ptr", ctypes.c_void_p),
+                ("col_idx", ctypes.c_void_p), ("val", ctypes.c_void_p)]
+
+
+class st_rom_desc(ctypes.Structure):
+    _fields_ = [("n_s", ctypes.c_int32), ("N_t", ctypes.c_int32), ("Q", ctypes.c_int32), ("Qf", ctypes.c_int32),
+                ("Q0", ctypes.c_int32), ("n_t", ctypes.POINTER(ctypes.c_int32))]
+
+
+class st_rom_layout_t(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_size_t) for k in ("Ahat", "bhat", "u0hat", "T", "K", "Wf", "P1", "mode", "moff", "koff",
+                                               "total")]
+
+
+_lib = None
+
+_P = ctypes.c_void_p
+_I32 = ctypes.c_int32
+_I64 = ctypes.c_int64
+_SZ = ctypes.c_size_t
+_D = ctypes.c_double
+
+_SIGNATURES = {
+    "st_strerror": (ctypes.c_char_p, [_I32]),
+    "st_version": (_I32, []),
+    "st_rom_layout": (_I32, [ctypes.POINTER(st_rom_desc), ctypes.POINTER(st_rom_layout_t)]),
+    "st_build_bases_workspace": (_SZ, [_I64, _I32, _I32, _I32, _P, _I32]),
+    "st_build_bases": (_I32, [_P, _I32, _I64, _I64, _I32, _I32, _I32, _P, _I32, _D, _P, _P, _P, _P, _P, _SZ, _P]),
+    "st_assemble_workspace": (_SZ, [ctypes.POINTER(st_rom_desc), _I64]),
+    "st_assemble": (_I32, [ctypes.POINTER(st_rom_desc), _I64, _P, _P, _P, ctypes.POINTER(st_csr), _P, _P, _P, _P, _SZ,
+                           _P, _SZ, _P]),
+    "st_form_workspace": (_SZ, [ctypes.POINTER(st_rom_desc), _I32]),
+    "st_form": (_I32, [ctypes.POINTER(st_rom_desc), _P, _I32, _P, _P, _P, _P, _I32, _P, _I64, _P, _I64, _P, _P, _P,
+                       _P, _SZ, _P]),
+    "st_solve_workspace": (_SZ, [ctypes.POINTER(st_rom_desc), _I32, _I64, _I64, _I32]),
+    "st_solve": (_I32, [ctypes.POINTER(st_rom_desc), _P, _I32, _P, _P, _P, _P, _I32, _D, _I32, _P, _I64, _P, _P, _P,
+                        _P, _P, _SZ, _P]),
+}
+
+EXPORTED = tuple(_SIGNATURES)
+
+
+def lib():
+    """Load libstrom.so once; raise if it is not built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"libstrom.so not built at {LIB_PATH}; run __graft_entry__.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGNATURES.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def st_strerror(code: int) -> str:
+    return lib().st_strerror(int(code)).decode()
+
+
+def st_version() -> int:
+    return int(lib().st_version())
+
+
+def _check(code: int, where: str):
+    if code != ST_OK:
+        raise StromError(code, where)
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("expected a device tensor")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class RomDesc:
+    """Host description of a reduced model (keeps its n_t array alive)."""
+
+    def __init__(self, n_t: Sequence[int], N_t: int, Q: int, Qf: int, Q0: int):
+        self.n_t_arr = np.ascontiguousarray(np.asarray(n_t, dtype=np.int32))
+        self.n_t_ptr = self.n_t_arr.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+        self.c = st_rom_desc(len(self.n_t_arr), int(N_t), int(Q), int(Qf), int(Q0), self.n_t_ptr)
+
+    @property
+    def n_s(self):
+        return int(self.c.n_s)
+
+    @property
+    def n(self):
+        return int(self.n_t_arr.sum())
+
+    def ref(self):
+        return ctypes.byref(self.c)
+
+
+def st_rom_layout(desc: RomDesc) -> dict:
+    out = st_rom_layout_t()
+    _check(lib().st_rom_layout(desc.ref(), ctypes.byref(out)), "st_rom_layout")
+    return {k: int(getattr(out, k)) for k, _ in st_rom_layout_t._fields_}
+
+
+def csr_to_device(row_ptr, col_idx, val, device="cuda"):
+    """Device copies of CSR arrays (int32, int32, float64) and their descriptor."""
+    rp = torch.as_tensor(np.asarray(row_ptr, dtype=np.int32), device=device)
+    ci = torch.as_tensor(np.asarray(col_idx, dtype=np.int32), device=device)
+    va = torch.as_tensor(np.asarray(val, dtype=np.float64), device=device)
+    d = st_csr(int(rp.numel() - 1), int(ci.numel()), rp.data_ptr(), ci.data_ptr(), va.data_ptr())
+    return d, (rp, ci, va)
+
+
+def st_build_bases(U: torch.Tensor, N_t: int, n_mu: int, n_s: int, n_t: Sequence[int], gram_prec: int = ST_F64,
+                   tau_t: float = 1e-7):
+    """POD on the device.  U: (N_s, n_mu*N_t) column-major, i.e. a tensor whose
+    transpose is contiguous (pass U.T.contiguous().T or torch.empty((m, N_s)).T).
+    Returns (Phi_s (N_s x n_s, column-major view), Phi_t (N_t x n), sigma, rank_t)."""
+    N_s = U.shape[0]
+    if U.T.is_contiguous():
+        ld = U.stride(1)
+    else:
+        raise ValueError("U must be column-major (U.T contiguous)")
+    prec = ST_F64 if U.dtype == torch.float64 else ST_F32
+    nt = np.ascontiguousarray(np.asarray(n_t, dtype=np.int32))
+    n = int(nt.sum())
+    ws_bytes = lib().st_build_bases_workspace(N_s, N_t, n_mu, n_s, nt.ctypes.data, gram_prec)
+    if ws_bytes == 0:
+        raise StromError(-1, "st_build_bases_workspace")
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device=U.device)
+    Phi_s = torch.empty((n_s, N_s), dtype=torch.float64, device=U.device)
+    Phi_t = torch.empty((n, N_t), dtype=torch.float64, device=U.device)
+    sigma = torch.empty(n_s, dtype=torch.float64, device=U.device)
+    rank = torch.empty(n_s, dtype=torch.int32, device=U.device)
+    _check(lib().st_build_bases(ctypes.c_void_p(U.data_ptr()), prec, ld, N_s, N_t, n_mu, n_s, nt.ctypes.data, gram_prec,
+                                float(tau_t), _ptr(Phi_s), _ptr(Phi_t), _ptr(sigma), _ptr(rank), _ptr(ws), ws_bytes,
+                                _stream()), "st_build_bases")
+    return Phi_s.T, Phi_t.T, sigma, rank
+
+
+def st_assemble(desc: RomDesc, Phi_s: torch.Tensor, Phi_t: torch.Tensor, dt: torch.Tensor, A_csr: list,
+                Bf: Optional[torch.Tensor] = None, g: Optional[torch.Tensor] = None,
+                u0: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Offline ROM buffer.  Phi_s (N_s x n_s) and Phi_t (N_t x n) column-major
+    (transposes contiguous); Bf (N_s x Qf), g (N_t x Qf), u0 (N_s x Q0)
+    column-major likewise; A_csr a list of st_csr descriptors."""
+    N_s = Phi_s.shape[0]
+
+    def colmajor(t):
+        if t is None:
+            return None
+        if not t.T.is_contiguous():
+            raise ValueError("expected a column-major tensor (transpose contiguous)")
+        return ctypes.c_void_p(t.data_ptr())
+
+    lay = st_rom_layout(desc)
+    rom = torch.empty(lay["total"], dtype=torch.uint8, device=Phi_s.device)
+    ws_bytes = lib().st_assemble_workspace(desc.ref(), N_s)
+    ws = torch.empty(max(ws_bytes, 1), dtype=torch.uint8, device=Phi_s.device)
+    arr = (st_csr * len(A_csr))(*A_csr)
+    _check(lib().st_assemble(desc.ref(), N_s, colmajor(Phi_s), colmajor(Phi_t), _ptr(dt), arr, colmajor(Bf),
+                             colmajor(g), colmajor(u0), _ptr(rom), lay["total"], _ptr(ws), ws_bytes, _stream()),
+           "st_assemble")
+    return rom
+
+
+def rom_section(desc: RomDesc, rom: torch.Tensor, name: str) -> torch.Tensor:
+    """View of one FP64 section of a ROM buffer (flat)."""
+    lay = st_rom_layout(desc)
+    order = ["Ahat", "bhat", "u0hat", "T", "K", "Wf", "P1", "mode", "moff", "koff", "total"]
+    i = order.index(name)
+    b0, b1 = lay[name], lay[order[i + 1]]
+    dtype = {"mode": torch.int32, "moff": torch.int32, "koff": torch.int64}.get(name, torch.float64)
+    return rom[b0:b1].view(dtype)
+
+
+def query_widths(desc: RomDesc, nt_q: Optional[np.ndarray], n_q: int) -> np.ndarray:
+    if nt_q is None:
+        return np.full(n_q, desc.n, dtype=np.int64)
+    return np.asarray(nt_q, dtype=np.int64).sum(axis=1)
+
+
+def st_form(desc: RomDesc, rom: torch.Tensor, theta_A: torch.Tensor, theta_f: Optional[torch.Tensor] = None,
+            theta_0: Optional[torch.Tensor] = None, nt_q: Optional[torch.Tensor] = None, out_prec: int = ST_F64,
+            widths: Optional[np.ndarray] = None):
+    """Per-query reduced systems.  Returns (mats flat, rhs, coeff_off, mat_off, info)."""
+    n_q = int(theta_A.shape[0])
+    dev = theta_A.device
+    if widths is None:
+        widths = query_widths(desc, None if nt_q is None else nt_q.cpu().numpy(), n_q)
+    sum_w = int(widths.sum())
+    sum_w2 = int((widths.astype(np.int64) ** 2).sum())
+    mats = torch.empty(max(sum_w2, 1), dtype=torch.float64 if out_prec == ST_F64 else torch.float32, device=dev)
+    rhs = torch.empty(max(sum_w, 1), dtype=torch.float64, device=dev)
+    coeff_off = torch.empty(n_q + 1, dtype=torch.int64, device=dev)
+    mat_off = torch.empty(n_q + 1, dtype=torch.int64, device=dev)
+    info = torch.empty(max(n_q, 1), dtype=torch.int32, device=dev)
+    ws_bytes = lib().st_form_workspace(desc.ref(), n_q)
+    ws = torch.empty(max(ws_bytes, 1), dtype=torch.uint8, device=dev)
+    _check(lib().st_form(desc.ref(), _ptr(rom), n_q, _ptr(theta_A), _ptr(theta_f), _ptr(theta_0), _ptr(nt_q),
+                         out_prec, _ptr(mats), sum_w2, _ptr(rhs), sum_w, _ptr(coeff_off), _ptr(mat_off), _ptr(info),
+                         _ptr(ws), ws_bytes, _stream()), "st_form")
+    return mats, rhs, coeff_off, mat_off, info[:n_q]
+
+
+class SolveBuffers:
+    """Preallocated outputs and workspace of st_solve for a fixed query mix."""
+
+    def __init__(self, desc: RomDesc, n_q: int, widths: np.ndarray, lu_prec: int, device="cuda"):
+        self.n_q = n_q
+        self.sum_w = int(widths.sum())
+        self.sum_w2 = int((widths.astype(np.int64) ** 2).sum())
+        self.lu_prec = lu_prec
+        self.coeff = torch.empty(max(self.sum_w, 1), dtype=torch.float64, device=device)
+        self.coeff_off = torch.empty(n_q + 1, dtype=torch.int64, device=device)
+        self.relres = torch.empty(max(n_q, 1), dtype=torch.float64, device=device)
+        self.info = torch.empty(max(n_q, 1), dtype=torch.int32, device=device)
+        self.iters = torch.empty(max(n_q, 1), dtype=torch.int32, device=device)
+        self.ws_bytes = lib().st_solve_workspace(desc.ref(), n_q, self.sum_w, self.sum_w2, lu_prec)
+        self.ws = torch.empty(max(self.ws_bytes, 1), dtype=torch.uint8, device=device)
+
+
+def st_solve(desc: RomDesc, rom: torch.Tensor, theta_A: torch.Tensor, theta_f: Optional[torch.Tensor] = None,
+             theta_0: Optional[torch.Tensor] = None, nt_q: Optional[torch.Tensor] = None, lu_prec: int = ST_F64,
+             ir_tol: float = 0.0, ir_max: int = 0, bufs: Optional[SolveBuffers] = None,
+             widths: Optional[np.ndarray] = None) -> SolveBuffers:
+    """Batched reduced solve; returns the SolveBuffers holding coeff, coeff_off,
+    relres, info, iters."""
+    n_q = int(theta_A.shape[0])
+    if bufs is None:
+        if widths is None:
+            widths = query_widths(desc, None if nt_q is None else nt_q.cpu().numpy(), n_q)
+        bufs = SolveBuffers(desc, n_q, widths, lu_prec, theta_A.device)
+    _check(lib().st_solve(desc.ref(), _ptr(rom), n_q, _ptr(theta_A), _ptr(theta_f), _ptr(theta_0), _ptr(nt_q),
+                          lu_prec, float(ir_tol), int(ir_max), _ptr(bufs.coeff), bufs.sum_w, _ptr(bufs.coeff_off),
+                          _ptr(bufs.relres), _ptr(bufs.info), _ptr(bufs.iters), _ptr(bufs.ws), bufs.ws_bytes,
+                          _stream()), "st_solve")
+    return bufs

@@ -1,0 +1,113 @@
+"""C ABI checks that need no GPU: the library loads, exports every function
+that include/strom.h declares, and rejects invalid arguments on the host
+before any launch."""
+import ctypes
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+from paper_1910_01260_amd import strom
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "strom.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(st_\w+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for n in ("st_build_bases", "st_assemble", "st_solve", "st_form", "st_strerror", "st_rom_layout"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    out = subprocess.run(["nm", "-D", "--defined-only", strom.LIB_PATH], capture_output=True, text=True, check=True)
+    exported = set(ln.split()[-1] for ln in out.stdout.splitlines() if ln.strip())
+    missing = [n for n in declared_functions() if n not in exported]
+    assert not missing, missing
+    lib = strom.lib()
+    for n in declared_functions():
+        assert hasattr(lib, n)
+
+
+def test_binding_names_match_header():
+    assert set(strom.EXPORTED) <= set(declared_functions())
+
+
+def test_strerror_and_version():
+    assert strom.st_version() == 1
+    assert "workspace" in strom.st_strerror(-3)
+    assert strom.st_strerror(12345) == "unknown status"
+
+
+def test_layout_is_deterministic_and_aligned():
+    d = strom.RomDesc([3, 5, 2], 10, 2, 1, 1)
+    lay = strom.st_rom_layout(d)
+    keys = ["Ahat", "bhat", "u0hat", "T", "K", "Wf", "P1", "mode", "moff", "koff", "total"]
+    offs = [lay[k] for k in keys]
+    assert offs == sorted(offs) and all(o % 256 == 0 for o in offs)
+    n = 10
+    assert lay["K"] - lay["T"] >= 8 * n * n
+
+
+def _null():
+    return ctypes.c_void_p(0)
+
+
+def test_host_validation_rejects_bad_arguments():
+    L = strom.lib()
+    good = strom.RomDesc([4, 4], 8, 2, 0, 1)
+    bad_nt = strom.RomDesc([4, 9], 8, 2, 0, 1)      # n_t > N_t
+    bad_q = strom.RomDesc([4, 4], 8, 0, 0, 1)       # Q = 0
+    lay = strom.st_rom_layout_t()
+    assert L.st_rom_layout(bad_nt.ref(), ctypes.byref(lay)) == -1
+    assert L.st_rom_layout(bad_q.ref(), ctypes.byref(lay)) == -1
+    assert L.st_rom_layout(None, ctypes.byref(lay)) == -1
+    # st_solve: null rom, negative n_q, bad precision, bad tolerance
+    fake = ctypes.c_void_p(0x1000)
+    args = lambda **kw: dict(dict(d=good.ref(), rom=fake, n_q=4, thA=fake, thf=None, th0=fake, nt=None, prec=0,
+                                  tol=0.0, irmax=0, coeff=fake, cap=100, coff=fake, relres=fake, info=fake,
+                                  iters=None, ws=fake, wsb=1 << 20, stream=None), **kw)
+
+    def call(a):
+        return L.st_solve(a["d"], a["rom"], a["n_q"], a["thA"], a["thf"], a["th0"], a["nt"], a["prec"], a["tol"],
+                          a["irmax"], a["coeff"], a["cap"], a["coff"], a["relres"], a["info"], a["iters"], a["ws"],
+                          a["wsb"], a["stream"])
+
+    assert call(args(rom=None)) == -1
+    assert call(args(n_q=-1)) == -1
+    assert call(args(prec=7)) == -1
+    assert call(args(tol=-1.0)) == -1
+    assert call(args(irmax=-2)) == -1
+    assert call(args(thA=None)) == -1
+    assert call(args(th0=None)) == -1                # Q0 = 1 needs theta_0
+    assert call(args(coeff=None)) == -1
+    assert call(args(wsb=16)) == -3                  # workspace too small
+    assert call(args(d=bad_nt.ref())) == -1
+    assert call(args(n_q=0)) == 0                    # empty batch: no-op, no launch
+    # st_form: bad output precision
+    assert L.st_form(good.ref(), fake, 4, fake, None, fake, None, 5, fake, 10, fake, 10, fake, fake, fake, fake,
+                     1 << 20, None) == -1
+    # st_assemble: rank and CSR shape checks
+    csr = (strom.st_csr * 2)(strom.st_csr(16, 0, 0x1000, 0, 0), strom.st_csr(16, 0, 0x1000, 0, 0))
+    assert L.st_assemble(good.ref(), 1, fake, fake, fake, csr, None, None, fake, fake, 1 << 20, fake, 1 << 20,
+                         None) == -4                 # n_s = 2 > N_s = 1
+    assert L.st_assemble(good.ref(), 8, fake, fake, fake, csr, None, None, fake, fake, 1 << 20, fake, 1 << 20,
+                         None) == -1                 # CSR rows 16 != N_s 8
+
+
+def test_workspace_sizes_with_empty_term_lists():
+    """Zero input or initial-state terms must size cleanly on the host."""
+    L = strom.lib()
+    for Qf, Q0 in ((0, 0), (0, 1), (1, 0), (3, 2)):
+        d = strom.RomDesc([8] * 8, 128, 2, Qf, Q0)
+        assert L.st_assemble_workspace(d.ref(), 256) >= 2 * 8 * 256 * 8
+        assert L.st_form_workspace(d.ref(), 10) > 0
+        assert L.st_solve_workspace(d.ref(), 10, 640, 40960, 0) > 40960 * 8
