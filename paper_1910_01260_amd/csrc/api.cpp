@@ -301,3 +301,168 @@ st_status st_solve(const st_rom_desc* d, const void* rom, int32_t n_q, const dou
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// st_build_bases (POD)
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr int kSubspaceIters = 10;
+constexpr int kMaxSubspace = 256;
+
+struct PodDims {
+  int64_t N_s, m, p;
+  int n_s, k, n;
+  bool transposed;  // Gram is U U^T (N_s < m)
+};
+
+bool pod_dims(int64_t N_s, int32_t N_t, int32_t n_mu, int32_t n_s, const int32_t* n_t, PodDims* d) {
+  if (N_s < 1 || N_t < 1 || n_mu < 1 || n_s < 1 || !n_t) return false;
+  d->N_s = N_s;
+  d->m = (int64_t)n_mu * N_t;
+  d->transposed = N_s < d->m;
+  d->p = d->transposed ? N_s : d->m;
+  d->n_s = n_s;
+  int64_t extra = d->p - n_s;
+  if (extra > 32) extra = 32;
+  d->k = (int)(n_s + (extra > 0 ? extra : 0));
+  int64_t n = 0;
+  for (int i = 0; i < n_s; ++i) n += n_t[i];
+  d->n = (int)n;
+  return true;
+}
+
+struct PodWs {
+  double *G, *X, *Y, *H, *Z, *Zs, *evals, *sig, *V, *P, *S, *Rinv, *part;
+  int32_t* moff;
+  size_t part_elems, total;
+};
+
+PodWs pod_ws(const PodDims& d, void* base) {
+  Carver c(base);
+  PodWs w;
+  w.G = c.take<double>((size_t)d.p * d.p);
+  w.X = c.take<double>((size_t)d.p * d.k);
+  w.Y = c.take<double>((size_t)d.p * d.k);
+  w.H = c.take<double>((size_t)d.k * d.k);
+  w.Z = c.take<double>((size_t)d.k * d.k);
+  w.Zs = c.take<double>((size_t)d.k * d.k);
+  w.evals = c.take<double>(d.k);
+  w.sig = c.take<double>(d.n_s);
+  w.V = c.take<double>((size_t)d.m * d.n_s);
+  w.P = c.take<double>((size_t)d.N_s * d.n_s);
+  w.S = c.take<double>((size_t)d.n_s * d.n_s);
+  w.Rinv = c.take<double>((size_t)d.n_s * d.n_s);
+  w.moff = c.take<int32_t>(d.n_s + 1);
+  size_t pe = gram_partial_elems(d.transposed ? d.m : d.N_s, (int)d.p);
+  const size_t cands[] = {tsgemm_partial_elems(d.p, (int)d.p, d.k), tsgemm_partial_elems(d.p, d.k, d.k),
+                          tsgemm_partial_elems(d.k, (int)d.p, d.k), tsgemm_partial_elems(d.N_s, (int)d.m, d.n_s),
+                          tsgemm_partial_elems(d.m, (int)d.N_s, d.n_s), tsgemm_partial_elems(d.N_s, d.n_s, d.n_s),
+                          tsgemm_partial_elems(d.n_s, (int)d.N_s, d.n_s)};
+  for (size_t v : cands) pe = v > pe ? v : pe;
+  w.part = c.take<double>(pe);
+  w.part_elems = pe;
+  w.total = c.used;
+  return w;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t st_build_bases_workspace(int64_t N_s, int32_t N_t, int32_t n_mu, int32_t n_s, const int32_t* n_t,
+                                int32_t gram_prec) {
+  (void)gram_prec;
+  PodDims d;
+  if (!pod_dims(N_s, N_t, n_mu, n_s, n_t, &d)) return 0;
+  return pod_ws(d, nullptr).total;
+}
+
+st_status st_build_bases(const void* U, int32_t U_prec, int64_t ldU, int64_t N_s, int32_t N_t, int32_t n_mu,
+                         int32_t n_s, const int32_t* n_t, int32_t gram_prec, double tau_t, double* Phi_s,
+                         double* Phi_t, double* sigma, int32_t* rank_t, void* ws, size_t ws_bytes, void* stream) {
+  PodDims d;
+  if (!U || !Phi_s || !Phi_t || !sigma || !ws || !pod_dims(N_s, N_t, n_mu, n_s, n_t, &d)) return ST_EINVAL;
+  if (U_prec != ST_F64 && U_prec != ST_F32) return ST_EINVAL;
+  if (gram_prec != ST_F64 && gram_prec != ST_F32 && gram_prec != ST_BF16X3) return ST_EINVAL;
+  if (ldU < N_s || !(tau_t >= 0.0)) return ST_EINVAL;
+  for (int i = 0; i < n_s; ++i)
+    if (n_t[i] < 1 || n_t[i] > N_t) return ST_EINVAL;
+  if ((int64_t)n_s > d.p) return ST_ERANK;
+  if (n_s > kMaxModes || d.k > kMaxSubspace || n_mu > 64 || d.p > 0x7fffffff) return ST_EUNSUPPORTED;
+  for (int i = 0; i < n_s; ++i)
+    if (n_t[i] > 512) return ST_EUNSUPPORTED;
+  if ((size_t)N_t * n_mu * sizeof(double) > 120 * 1024) return ST_EUNSUPPORTED;
+  if (ws_bytes < st_build_bases_workspace(N_s, N_t, n_mu, n_s, n_t, gram_prec)) return ST_EWORKSPACE;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  PodWs w = pod_ws(d, ws);
+  const int p = (int)d.p, k = d.k, ns = d.n_s;
+  const bool f32in = U_prec == ST_F32;
+
+  // a1: Gram of the snapshots (small side)
+  if (!d.transposed)
+    ST_TRY(launch_gram(N_s, p, U, U_prec, 1, ldU, gram_prec, w.G, w.part, w.part_elems, s));
+  else
+    ST_TRY(launch_gram(d.m, p, U, U_prec, ldU, 1, gram_prec, w.G, w.part, w.part_elems, s));
+
+  // a2: subspace iteration on G, then Rayleigh-Ritz
+  const uint64_t seed = 0x5EED1910ULL;
+  ST_TRY(launch_rand_fill(w.X, p, k, seed, s));
+  ST_TRY(launch_orth(w.X, p, k, seed + 1, s));
+  for (int it = 0; it < kSubspaceIters; ++it) {
+    ST_TRY(launch_tsgemm(p, p, k, w.G, 1, p, w.X, 1, p, w.Y, p, w.part, w.part_elems, s));  // Y = G X
+    ST_TRY(launch_copy_cols(w.Y, p, w.X, p, p, k, s));
+    ST_TRY(launch_orth(w.X, p, k, seed + 2 + it, s));
+  }
+  ST_TRY(launch_tsgemm(p, p, k, w.G, 1, p, w.X, 1, p, w.Y, p, w.part, w.part_elems, s));    // Y = G X
+  ST_TRY(launch_tsgemm(p, k, k, w.X, 1, p, w.Y, 1, p, w.H, k, w.part, w.part_elems, s));    // H = X^T G X
+  ST_TRY(launch_jacobi(k, w.H, w.Z, w.evals, w.Zs, s));
+  ST_TRY(launch_tsgemm(k, p, k, w.X, p, 1, w.Zs, 1, k, w.Y, p, w.part, w.part_elems, s));   // Ritz vectors Y = X Zs
+  ST_TRY(launch_sqrt_clamp(w.evals, w.sig, ns, s));
+
+  // a3: spatial basis and right singular vectors
+  if (d.transposed) {
+    // eigenvectors of U U^T are the left singular vectors
+    ST_TRY(launch_copy_cols(w.Y, p, Phi_s, N_s, N_s, ns, s));
+    ST_TRY(launch_sign_fix(Phi_s, N_s, ns, nullptr, 0, s));
+    // V = U^T Phi_s diag(1/sigma)
+    if (f32in)
+      ST_TRY(launch_tsgemm_xf(N_s, (int)d.m, ns, (const float*)U, 1, ldU, Phi_s, 1, N_s, w.V, (int)d.m, w.part,
+                              w.part_elems, s));
+    else
+      ST_TRY(launch_tsgemm(N_s, (int)d.m, ns, (const double*)U, 1, ldU, Phi_s, 1, N_s, w.V, (int)d.m, w.part,
+                           w.part_elems, s));
+    ST_TRY(launch_scale_or_refill(w.V, d.m, ns, w.sig, 0.0, seed + 101, s));
+  } else {
+    // eigenvectors of U^T U are the right singular vectors; Phi_s = U V diag(1/sigma), re-orthonormalised
+    ST_TRY(launch_copy_cols(w.Y, p, w.V, d.m, d.m, ns, s));
+    if (f32in)
+      ST_TRY(launch_tsgemm_xf(d.m, (int)N_s, ns, (const float*)U, ldU, 1, w.V, 1, d.m, w.P, (int)N_s, w.part,
+                              w.part_elems, s));
+    else
+      ST_TRY(launch_tsgemm(d.m, (int)N_s, ns, (const double*)U, ldU, 1, w.V, 1, d.m, w.P, (int)N_s, w.part,
+                           w.part_elems, s));
+    ST_TRY(launch_scale_or_refill(w.P, N_s, ns, w.sig, 1e-13, seed + 102, s));
+    for (int pass = 0; pass < 2; ++pass) {
+      double* src = pass == 0 ? w.P : Phi_s;
+      double* dst = pass == 0 ? Phi_s : w.P;
+      ST_TRY(launch_tsgemm(N_s, ns, ns, src, 1, N_s, src, 1, N_s, w.S, ns, w.part, w.part_elems, s));
+      ST_TRY(launch_chol_inv(ns, w.S, w.Rinv, s));
+      ST_TRY(launch_tsgemm(ns, (int)N_s, ns, src, N_s, 1, w.Rinv, 1, ns, dst, (int)N_s, w.part, w.part_elems, s));
+    }
+    ST_TRY(launch_copy_cols(w.P, N_s, Phi_s, N_s, N_s, ns, s));
+    ST_TRY(launch_sign_fix(Phi_s, N_s, ns, w.V, d.m, s));
+  }
+  ST_TRY(launch_copy_cols(w.sig, ns, sigma, ns, ns, 1, s));
+
+  // a4: temporal bases
+  ModeTable mt;
+  memset(&mt, 0, sizeof(mt));
+  mt.n_s = ns;
+  for (int i = 0; i < ns; ++i) mt.nt[i] = n_t[i];
+  ST_TRY(launch_mode_offsets(mt, w.moff, s));
+  ST_TRY(launch_temporal_svd(w.V, d.m, N_t, n_mu, ns, w.moff, tau_t, Phi_t, rank_t, s));
+  return ST_OK;
+}
+
+}  // extern "C"

@@ -68,9 +68,30 @@ hipError_t launch_tsgemm(int64_t N, int32_t p, int32_t q, const double* X, int64
 hipError_t launch_tsgemm_w(int64_t N, int32_t p, int32_t q, const double* X, int64_t xrs, int64_t xcs,
                            const double* Y, int64_t yrs, int64_t ycs, const double* wrow, double* C, int32_t ldc,
                            double* partial, size_t partial_elems, hipStream_t s);
+hipError_t launch_tsgemm_xf(int64_t N, int32_t p, int32_t q, const float* X, int64_t xrs, int64_t xcs,
+                            const double* Y, int64_t yrs, int64_t ycs, double* C, int32_t ldc, double* partial,
+                            size_t partial_elems, hipStream_t s);
 size_t tsgemm_partial_elems(int64_t N, int32_t p, int32_t q);
+hipError_t launch_mode_offsets(const ModeTable& mt, int32_t* moff, hipStream_t s);
 hipError_t launch_temporal(const double* Phi_t, int32_t N_t, int32_t n, const double* dt, const double* g, int32_t Qf,
                            const ModeTable& mt, MutRomView rom, hipStream_t s);
+
+// k_pod.hip: POD (a1-a4)
+size_t gram_partial_elems(int64_t K, int p);
+hipError_t launch_gram(int64_t K, int p, const void* X, int in_prec, int64_t ks, int64_t ms, int gram_prec, double* G,
+                       double* partial, size_t partial_elems, hipStream_t s);
+hipError_t launch_rand_fill(double* X, int64_t p, int k, uint64_t seed, hipStream_t s);
+hipError_t launch_orth(double* X, int64_t p, int k, uint64_t seed, hipStream_t s);
+hipError_t launch_jacobi(int k, double* A, double* Z, double* evals, double* Zout, hipStream_t s);
+hipError_t launch_chol_inv(int n, double* S, double* Rinv, hipStream_t s);
+hipError_t launch_scale_or_refill(double* X, int64_t p, int k, const double* sigma, double cut, uint64_t seed,
+                                  hipStream_t s);
+hipError_t launch_sqrt_clamp(const double* lam, double* sigma, int n, hipStream_t s);
+hipError_t launch_sign_fix(double* X, int64_t p, int k, double* Y, int64_t py, hipStream_t s);
+hipError_t launch_copy_cols(const double* src, int64_t ld_src, double* dst, int64_t ld_dst, int64_t p, int n,
+                            hipStream_t s);
+hipError_t launch_temporal_svd(const double* V, int64_t ldV, int N_t, int n_mu, int n_s, const int32_t* moff,
+                               double tau_t, double* Phi_t, int32_t* rank_out, hipStream_t s);
 
 // k_query.hip: plan (per-query offsets), assembly (a7), residual
 hipError_t launch_plan(int32_t n_q, int32_t n_s, const int32_t* full_nt_dev, const int32_t* nt_q, const double* thA,

@@ -80,8 +80,9 @@ __global__ __launch_bounds__(256) void spmm_rowmajor_kernel(int32_t n_rows, cons
 
 // Split-K tall-skinny product: partial[z] (p x q, column-major) = sum over the
 // z-th row range of w[r] X[r,:]^T Y[r,:].  32 x 32 output tile per workgroup.
+template <typename TX>
 __global__ __launch_bounds__(256) void tsgemm_partial_kernel(int64_t N, int32_t p, int32_t q,
-                                                            const double* __restrict__ X, int64_t xrs, int64_t xcs,
+                                                            const TX* __restrict__ X, int64_t xrs, int64_t xcs,
                                                             const double* __restrict__ Y, int64_t yrs, int64_t ycs,
                                                             const double* __restrict__ wrow, int64_t rows_per_split,
                                                             double* __restrict__ partial) {
@@ -101,7 +102,7 @@ __global__ __launch_bounds__(256) void tsgemm_partial_kernel(int64_t N, int32_t 
       const int64_t r = r0 + kk;
       double v = 0.0;
       if (r < rend && a0 + a < p) {
-        v = X[r * xrs + (int64_t)(a0 + a) * xcs];
+        v = (double)X[r * xrs + (int64_t)(a0 + a) * xcs];
         if (wrow) v *= wrow[r];
       }
       Xs[kk][a] = v;
@@ -214,16 +215,17 @@ size_t tsgemm_partial_elems(int64_t N, int32_t p, int32_t q) {
   return (size_t)tsgemm_splits(N, p, q) * (size_t)p * (size_t)q;
 }
 
-hipError_t launch_tsgemm_w(int64_t N, int32_t p, int32_t q, const double* X, int64_t xrs, int64_t xcs, const double* Y,
-                           int64_t yrs, int64_t ycs, const double* wrow, double* C, int32_t ldc, double* partial,
-                           size_t partial_elems, hipStream_t s) {
+template <typename TX>
+hipError_t tsgemm_go(int64_t N, int32_t p, int32_t q, const TX* X, int64_t xrs, int64_t xcs, const double* Y,
+                     int64_t yrs, int64_t ycs, const double* wrow, double* C, int32_t ldc, double* partial,
+                     size_t partial_elems, hipStream_t s) {
   if (p == 0 || q == 0) return hipSuccess;
   const int splits = tsgemm_splits(N, p, q);
   if ((size_t)splits * p * q > partial_elems) return hipErrorInvalidValue;
   int64_t rps = (N + splits - 1) / splits;
   rps = (rps + kTile - 1) / kTile * kTile;
   dim3 grid((p + kTile - 1) / kTile, (q + kTile - 1) / kTile, splits);
-  hipLaunchKernelGGL(tsgemm_partial_kernel, grid, dim3(256), 0, s, N, p, q, X, xrs, xcs, Y, yrs, ycs, wrow, rps,
+  hipLaunchKernelGGL(tsgemm_partial_kernel<TX>, grid, dim3(256), 0, s, N, p, q, X, xrs, xcs, Y, yrs, ycs, wrow, rps,
                      partial);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
@@ -233,10 +235,38 @@ hipError_t launch_tsgemm_w(int64_t N, int32_t p, int32_t q, const double* X, int
   return hipGetLastError();
 }
 
+hipError_t launch_tsgemm_w(int64_t N, int32_t p, int32_t q, const double* X, int64_t xrs, int64_t xcs, const double* Y,
+                           int64_t yrs, int64_t ycs, const double* wrow, double* C, int32_t ldc, double* partial,
+                           size_t partial_elems, hipStream_t s) {
+  return tsgemm_go<double>(N, p, q, X, xrs, xcs, Y, yrs, ycs, wrow, C, ldc, partial, partial_elems, s);
+}
+
 hipError_t launch_tsgemm(int64_t N, int32_t p, int32_t q, const double* X, int64_t xrs, int64_t xcs, const double* Y,
                          int64_t yrs, int64_t ycs, double* C, int32_t ldc, double* partial, size_t partial_elems,
                          hipStream_t s) {
-  return launch_tsgemm_w(N, p, q, X, xrs, xcs, Y, yrs, ycs, nullptr, C, ldc, partial, partial_elems, s);
+  return tsgemm_go<double>(N, p, q, X, xrs, xcs, Y, yrs, ycs, nullptr, C, ldc, partial, partial_elems, s);
+}
+
+hipError_t launch_tsgemm_xf(int64_t N, int32_t p, int32_t q, const float* X, int64_t xrs, int64_t xcs, const double* Y,
+                            int64_t yrs, int64_t ycs, double* C, int32_t ldc, double* partial, size_t partial_elems,
+                            hipStream_t s) {
+  return tsgemm_go<float>(N, p, q, X, xrs, xcs, Y, yrs, ycs, nullptr, C, ldc, partial, partial_elems, s);
+}
+
+__global__ void mode_offsets_kernel(ModeTable mt, int32_t* moff) {
+  if (threadIdx.x == 0) {
+    int32_t o = 0;
+    for (int i = 0; i < mt.n_s; ++i) {
+      moff[i] = o;
+      o += mt.nt[i];
+    }
+    moff[mt.n_s] = o;
+  }
+}
+
+hipError_t launch_mode_offsets(const ModeTable& mt, int32_t* moff, hipStream_t s) {
+  hipLaunchKernelGGL(mode_offsets_kernel, dim3(1), dim3(64), 0, s, mt, moff);
+  return hipGetLastError();
 }
 
 hipError_t launch_temporal(const double* Phi_t, int32_t N_t, int32_t n, const double* dt, const double* g, int32_t Qf,

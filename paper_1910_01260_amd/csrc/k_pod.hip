@@ -1,18 +1,752 @@
-// POD on gfx950 (Sec. 4.1): snapshot Gram, FP64 eigensolver, spatial basis
-// with re-orthonormalisation, temporal bases with completion.
+// POD on gfx950 (Sec. 4.1, Eq. (snapshotmat), (POD), (SVD), (temporalSVD)),
+// computed by the method of snapshots:
+//   a1  Gram of the snapshot matrix on the matrix cores (FP64 MFMA, or FP32 /
+//       split-BF16 MFMA with FP32 accumulation), lower tiles, split-K;
+//   a2  leading eigenpairs in FP64 by subspace iteration: products on the
+//       GPU, a one-workgroup classical Gram-Schmidt (twice) orthonormalisation,
+//       and a Rayleigh-Ritz step solved by a one-workgroup cyclic Jacobi
+//       eigensolver in parallel (round-robin) order;
+//   a3  spatial basis: the eigenvectors themselves when the Gram is U U^T,
+//       otherwise U V diag(1/sigma) re-orthonormalised by two Cholesky-QR passes;
+//   a4  temporal bases: per mode, a one-sided Jacobi SVD of the temporal
+//       snapshot matrix, a numerical-rank cut and a DCT-II completion.
+#include <math.h>
+
 #include "internal.h"
 
-extern "C" size_t st_build_bases_workspace(int64_t N_s, int32_t N_t, int32_t n_mu, int32_t n_s, const int32_t* n_t,
-                                           int32_t gram_prec) {
-  (void)N_s; (void)N_t; (void)n_mu; (void)n_s; (void)n_t; (void)gram_prec;
-  return 0;
+namespace strom {
+namespace {
+
+constexpr int kOneWG = 1024;
+
+__device__ inline uint64_t mix64(uint64_t z) {
+  // splitmix64 finaliser (Steele, Lea, Flood)
+  z += 0x9E3779B97F4A7C15ULL;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+  return z ^ (z >> 31);
 }
 
-extern "C" st_status st_build_bases(const void* U, int32_t U_prec, int64_t ldU, int64_t N_s, int32_t N_t, int32_t n_mu,
-                                    int32_t n_s, const int32_t* n_t, int32_t gram_prec, double tau_t, double* Phi_s,
-                                    double* Phi_t, double* sigma, int32_t* rank_t, void* ws, size_t ws_bytes,
-                                    void* stream) {
-  (void)U; (void)U_prec; (void)ldU; (void)N_s; (void)N_t; (void)n_mu; (void)n_s; (void)n_t; (void)gram_prec;
-  (void)tau_t; (void)Phi_s; (void)Phi_t; (void)sigma; (void)rank_t; (void)ws; (void)ws_bytes; (void)stream;
-  return ST_EUNSUPPORTED;
+__device__ inline double rand_pm(uint64_t seed, int64_t i, int64_t j) {
+  const uint64_t h = mix64(seed ^ mix64((uint64_t)i * 0x100000001B3ULL + (uint64_t)j));
+  return (double)(h >> 11) * (1.0 / 9007199254740992.0) - 0.5;
 }
+
+template <typename T>
+__device__ inline T block_sum(T v, T* red) {
+  // red: LDS of blockDim.x/64 entries; returns the sum to every thread
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  __syncthreads();
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  T s = 0;
+  for (int w = 0; w < nw; ++w) s += red[w];
+  return s;
+}
+
+__device__ inline double block_max(double v, double* red) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+  __syncthreads();
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  double s = red[0];
+  for (int w = 1; w < nw; ++w) s = fmax(s, red[w]);
+  return s;
+}
+
+__device__ inline int block_min_i(int v, int* red) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o));
+  __syncthreads();
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  int s = red[0];
+  for (int w = 1; w < nw; ++w) s = min(s, red[w]);
+  return s;
+}
+
+// ---------------------------------------------------------------------------
+// a1: Gram C = X^T X (p x p) with X of K rows; X element (k, a) at X[k*ks + a*ms].
+// 64 x 64 lower output tiles, 4 waves each owning 32 x 32 (2 x 2 MFMA tiles).
+// ---------------------------------------------------------------------------
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef short s4 __attribute__((ext_vector_type(4)));
+
+constexpr int kGT = 64;   // output tile
+constexpr int kGK = 32;   // K chunk
+
+__device__ inline void tile_of(int t, int& ti, int& tj) {
+  int i = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+  while ((i + 1) * (i + 2) / 2 <= t) ++i;
+  while (i * (i + 1) / 2 > t) --i;
+  ti = i;
+  tj = t - i * (i + 1) / 2;
+}
+
+template <typename InT>
+__device__ inline void gram_stage(const InT* __restrict__ X, int64_t K, int p, int64_t ks, int64_t ms, int64_t k0,
+                                  int64_t kend, int a0, float (*dst32)[kGT + 4], double (*dst64)[kGT + 1]) {
+  for (int e = threadIdx.x; e < kGK * kGT; e += blockDim.x) {
+    int kk, a;
+    if (ks == 1) { kk = e % kGK; a = e / kGK; } else { a = e % kGT; kk = e / kGT; }
+    const int64_t k = k0 + kk;
+    double v = 0.0;
+    if (k < kend && a0 + a < p) v = (double)X[k * ks + (int64_t)(a0 + a) * ms];
+    if (dst64) dst64[kk][a] = v;
+    else dst32[kk][a] = (float)v;
+  }
+}
+
+template <typename InT>
+__global__ __launch_bounds__(256) void gram_f64_kernel(int64_t K, int p, const InT* __restrict__ X, int64_t ks,
+                                                       int64_t ms, int64_t k_per_split, double* __restrict__ partial) {
+  __shared__ double Xa[kGK][kGT + 1];
+  __shared__ double Xb[kGK][kGT + 1];
+  int ti, tj;
+  tile_of(blockIdx.x, ti, tj);
+  const int a0 = ti * kGT, b0 = tj * kGT;
+  const int64_t kbeg = (int64_t)blockIdx.y * k_per_split;
+  const int64_t kend = min(K, kbeg + k_per_split);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wi = wave >> 1, wj = wave & 1;
+  const int li = lane & 15, lk = lane >> 4;
+  d4 acc[2][2];
+  for (int x = 0; x < 2; ++x)
+    for (int y = 0; y < 2; ++y) acc[x][y] = d4{0.0, 0.0, 0.0, 0.0};
+  for (int64_t k0 = kbeg; k0 < kend; k0 += kGK) {
+    gram_stage<InT>(X, K, p, ks, ms, k0, kend, a0, nullptr, Xa);
+    if (ti != tj) gram_stage<InT>(X, K, p, ks, ms, k0, kend, b0, nullptr, Xb);
+    __syncthreads();
+    double(*B)[kGT + 1] = (ti != tj) ? Xb : Xa;
+#pragma unroll
+    for (int kk = 0; kk < kGK; kk += 4) {
+      double av[2], bv[2];
+#pragma unroll
+      for (int x = 0; x < 2; ++x) av[x] = Xa[kk + lk][wi * 32 + x * 16 + li];
+#pragma unroll
+      for (int y = 0; y < 2; ++y) bv[y] = B[kk + lk][wj * 32 + y * 16 + li];
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y) acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[x], bv[y], acc[x][y], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  double* out = partial + (int64_t)blockIdx.y * p * p;
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int a = a0 + wi * 32 + x * 16 + lk + 4 * r;  // FP64 accumulator row = lane/16 + 4r
+        const int b = b0 + wj * 32 + y * 16 + li;
+        if (a < p && b < p) out[a + (int64_t)b * p] = acc[x][y][r];
+      }
+}
+
+// FP32 MFMA (ST_F32) or split-BF16 (ST_BF16X3): inputs rounded to FP32, products accumulated in FP32.
+__device__ inline short bf16_rne(float f) {
+  uint32_t u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (short)(u >> 16);
+}
+__device__ inline float bf16_to_f(short h) { return __uint_as_float(((uint32_t)(uint16_t)h) << 16); }
+
+template <typename InT, bool SPLIT>
+__global__ __launch_bounds__(256) void gram_f32_kernel(int64_t K, int p, const InT* __restrict__ X, int64_t ks,
+                                                       int64_t ms, int64_t k_per_split, double* __restrict__ partial) {
+  __shared__ float Xa[kGK][kGT + 4];
+  __shared__ float Xb[kGK][kGT + 4];
+  int ti, tj;
+  tile_of(blockIdx.x, ti, tj);
+  const int a0 = ti * kGT, b0 = tj * kGT;
+  const int64_t kbeg = (int64_t)blockIdx.y * k_per_split;
+  const int64_t kend = min(K, kbeg + k_per_split);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wi = wave >> 1, wj = wave & 1;
+  const int li = lane & 15, lk = lane >> 4;
+  f4 acc[2][2];
+  for (int x = 0; x < 2; ++x)
+    for (int y = 0; y < 2; ++y) acc[x][y] = f4{0.f, 0.f, 0.f, 0.f};
+  for (int64_t k0 = kbeg; k0 < kend; k0 += kGK) {
+    gram_stage<InT>(X, K, p, ks, ms, k0, kend, a0, Xa, nullptr);
+    if (ti != tj) gram_stage<InT>(X, K, p, ks, ms, k0, kend, b0, Xb, nullptr);
+    __syncthreads();
+    float(*B)[kGT + 4] = (ti != tj) ? Xb : Xa;
+    if (!SPLIT) {
+#pragma unroll
+      for (int kk = 0; kk < kGK; kk += 4) {
+        float av[2], bv[2];
+#pragma unroll
+        for (int x = 0; x < 2; ++x) av[x] = Xa[kk + lk][wi * 32 + x * 16 + li];
+#pragma unroll
+        for (int y = 0; y < 2; ++y) bv[y] = B[kk + lk][wj * 32 + y * 16 + li];
+#pragma unroll
+        for (int x = 0; x < 2; ++x)
+#pragma unroll
+          for (int y = 0; y < 2; ++y) acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[x], bv[y], acc[x][y], 0, 0, 0);
+      }
+    } else {
+      // bf16 16x16x16: operand A lane l holds A[l%16][4(l/16) .. 4(l/16)+3], B likewise B[4(l/16)..][l%16]
+#pragma unroll
+      for (int kk = 0; kk < kGK; kk += 16) {
+        s4 ah[2], al[2], bh[2], bl[2];
+#pragma unroll
+        for (int x = 0; x < 2; ++x)
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const float v = Xa[kk + 4 * lk + e][wi * 32 + x * 16 + li];
+            const short h = bf16_rne(v);
+            ah[x][e] = h;
+            al[x][e] = bf16_rne(v - bf16_to_f(h));
+          }
+#pragma unroll
+        for (int y = 0; y < 2; ++y)
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const float v = B[kk + 4 * lk + e][wj * 32 + y * 16 + li];
+            const short h = bf16_rne(v);
+            bh[y][e] = h;
+            bl[y][e] = bf16_rne(v - bf16_to_f(h));
+          }
+#pragma unroll
+        for (int x = 0; x < 2; ++x)
+#pragma unroll
+          for (int y = 0; y < 2; ++y) {
+            acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al[x], bh[y], acc[x][y], 0, 0, 0);
+            acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah[x], bl[y], acc[x][y], 0, 0, 0);
+            acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah[x], bh[y], acc[x][y], 0, 0, 0);
+          }
+      }
+    }
+    __syncthreads();
+  }
+  double* out = partial + (int64_t)blockIdx.y * p * p;
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int a = a0 + wi * 32 + x * 16 + 4 * lk + r;  // FP32 accumulator row = 4(lane/16) + r
+        const int b = b0 + wj * 32 + y * 16 + li;
+        if (a < p && b < p) out[a + (int64_t)b * p] = (double)acc[x][y][r];
+      }
+}
+
+// G[a,b] = G[b,a] = sum_z partial[z][max + min*p]
+__global__ void gram_finish_kernel(int p, int splits, const double* __restrict__ partial, double* __restrict__ G) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t pp = (int64_t)p * p;
+  if (e >= pp) return;
+  const int a = (int)(e % p), b = (int)(e / p);
+  const int hi = max(a, b), lo = min(a, b);
+  double s = 0.0;
+  for (int z = 0; z < splits; ++z) s += partial[z * pp + hi + (int64_t)lo * p];
+  G[e] = s;
+}
+
+// ---------------------------------------------------------------------------
+// a2: one-workgroup kernels
+// ---------------------------------------------------------------------------
+
+// X (p x k, column-major) <- pseudo-random entries
+__global__ void rand_fill_kernel(double* X, int64_t p, int k, uint64_t seed) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= p * k) return;
+  X[e] = rand_pm(seed, e % p, e / p);
+}
+
+// Orthonormalise the k columns of X (p x k, column-major) in place by
+// classical Gram-Schmidt applied twice per column; a column that loses all
+// but 1e-10 of its norm (dependent on the previous ones) is replaced by a
+// pseudo-random vector and orthogonalised again.
+__global__ __launch_bounds__(kOneWG) void orth_cgs2_kernel(double* X, int64_t p, int k, uint64_t seed) {
+  __shared__ double coef[256];
+  __shared__ double red[kOneWG / 64];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = kOneWG / 64;
+  for (int j = 0; j < k; ++j) {
+    double* xj = X + (int64_t)j * p;
+    for (int attempt = 0; attempt < 4; ++attempt) {
+      double n0 = 0.0;
+      for (int64_t r = tid; r < p; r += kOneWG) n0 = fma(xj[r], xj[r], n0);
+      n0 = sqrt(block_sum(n0, red));
+      for (int pass = 0; pass < 2 && j > 0; ++pass) {
+        for (int l = wave; l < j; l += nw) {
+          const double* xl = X + (int64_t)l * p;
+          double s = 0.0;
+          for (int64_t r = lane; r < p; r += 64) s = fma(xl[r], xj[r], s);
+          for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+          if (lane == 0) coef[l] = s;
+        }
+        __syncthreads();
+        for (int64_t r = tid; r < p; r += kOneWG) {
+          double v = xj[r];
+          for (int l = 0; l < j; ++l) v = fma(-coef[l], X[(int64_t)l * p + r], v);
+          xj[r] = v;
+        }
+        __syncthreads();
+      }
+      double n1 = 0.0;
+      for (int64_t r = tid; r < p; r += kOneWG) n1 = fma(xj[r], xj[r], n1);
+      n1 = sqrt(block_sum(n1, red));
+      if (n1 > 1e-10 * n0 && n1 > 0.0) {
+        const double inv = 1.0 / n1;
+        for (int64_t r = tid; r < p; r += kOneWG) xj[r] *= inv;
+        __syncthreads();
+        break;
+      }
+      // dependent column: refill and retry
+      for (int64_t r = tid; r < p; r += kOneWG) xj[r] = rand_pm(seed + 7919ULL * (attempt + 1), r, j);
+      __syncthreads();
+    }
+  }
+}
+
+// Symmetric eigen-decomposition of A (k x k, column-major, overwritten) by
+// cyclic Jacobi in round-robin parallel order; eigenvalues descending in
+// evals, eigenvectors in the matching columns of Zout.  Work arrays A, Z
+// (k*k each) may be global memory; k <= 256.
+__global__ __launch_bounds__(kOneWG) void jacobi_eig_kernel(int k, double* A, double* Z, double* evals, double* Zout,
+                                                            int max_sweeps) {
+  __shared__ int sp[128], sq[128];
+  __shared__ double sc[128], ss[128];
+  __shared__ double red[kOneWG / 64];
+  __shared__ int s_rot;
+  __shared__ int s_rank[256];
+  const int tid = threadIdx.x;
+  for (int e = tid; e < k * k; e += kOneWG) Z[e] = (e % k == e / k) ? 1.0 : 0.0;
+  const int kk = k + (k & 1);
+  const int m = kk - 1;
+  double fro = 0.0;
+  for (int e = tid; e < k * k; e += kOneWG) fro = fma(A[e], A[e], fro);
+  __syncthreads();
+  fro = sqrt(block_sum(fro, red));
+  const double thr = 1e-22 * fro;
+  for (int sweep = 0; sweep < max_sweeps && k > 1; ++sweep) {
+    if (tid == 0) s_rot = 0;
+    __syncthreads();
+    for (int rnd = 0; rnd < m; ++rnd) {
+      if (tid < kk / 2) {
+        int a, b;
+        if (tid == 0) { a = m; b = rnd; }
+        else { a = (rnd + tid) % m; b = (rnd - tid + m) % m; }
+        if (a > b) { const int t = a; a = b; b = t; }
+        double c = 1.0, s = 0.0;
+        if (b < k) {
+          const double apq = A[a + (int64_t)b * k];
+          const double app = A[a + (int64_t)a * k], aqq = A[b + (int64_t)b * k];
+          if (fabs(apq) > thr && fabs(apq) > 1e-17 * sqrt(fabs(app * aqq))) {
+            const double th = (aqq - app) / (2.0 * apq);
+            const double t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(1.0 + th * th));
+            c = 1.0 / sqrt(1.0 + t * t);
+            s = t * c;
+            s_rot = 1;
+          }
+        }
+        sp[tid] = a; sq[tid] = b; sc[tid] = c; ss[tid] = s;
+      }
+      __syncthreads();
+      const int np = kk / 2;
+      // rows p, q of A
+      for (int e = tid; e < np * k; e += kOneWG) {
+        const int t = e / k, j = e % k;
+        const int a = sp[t], b = sq[t];
+        if (b >= k || ss[t] == 0.0) continue;
+        const double c = sc[t], s = ss[t];
+        const double x = A[a + (int64_t)j * k], y = A[b + (int64_t)j * k];
+        A[a + (int64_t)j * k] = c * x - s * y;
+        A[b + (int64_t)j * k] = s * x + c * y;
+      }
+      __syncthreads();
+      // columns p, q of A and of Z
+      for (int e = tid; e < np * k; e += kOneWG) {
+        const int t = e / k, i = e % k;
+        const int a = sp[t], b = sq[t];
+        if (b >= k || ss[t] == 0.0) continue;
+        const double c = sc[t], s = ss[t];
+        double x = A[i + (int64_t)a * k], y = A[i + (int64_t)b * k];
+        // the rotation annihilates (a, b) and (b, a) exactly in exact arithmetic: store zeros
+        A[i + (int64_t)a * k] = (i == b) ? 0.0 : c * x - s * y;
+        A[i + (int64_t)b * k] = (i == a) ? 0.0 : s * x + c * y;
+        x = Z[i + (int64_t)a * k];
+        y = Z[i + (int64_t)b * k];
+        Z[i + (int64_t)a * k] = c * x - s * y;
+        Z[i + (int64_t)b * k] = s * x + c * y;
+      }
+      __syncthreads();
+    }
+    if (!s_rot) break;
+    __syncthreads();
+  }
+  // sort descending (rank by value, ties by index)
+  for (int i = tid; i < k; i += kOneWG) {
+    const double di = A[i + (int64_t)i * k];
+    int rank = 0;
+    for (int j = 0; j < k; ++j) {
+      const double dj = A[j + (int64_t)j * k];
+      if (dj > di || (dj == di && j < i)) ++rank;
+    }
+    s_rank[i] = rank;
+  }
+  __syncthreads();
+  for (int i = tid; i < k; i += kOneWG) evals[s_rank[i]] = A[i + (int64_t)i * k];
+  for (int e = tid; e < k * k; e += kOneWG) {
+    const int i = e % k, j = e / k;
+    Zout[i + (int64_t)s_rank[j] * k] = Z[e];
+  }
+}
+
+// Upper Cholesky factor of S (n x n, column-major) and its inverse:
+// S = R^T R, Rinv = R^{-1}.  Pivots are floored at 1e-30 of the largest
+// diagonal so the second pass of Cholesky-QR can repair a near-singular first.
+__global__ __launch_bounds__(kOneWG) void chol_inv_kernel(int n, double* S, double* Rinv) {
+  __shared__ double red[kOneWG / 64];
+  __shared__ double s_d;
+  const int tid = threadIdx.x;
+  double dmax = 0.0;
+  for (int i = tid; i < n; i += kOneWG) dmax = fmax(dmax, S[i + (int64_t)i * n]);
+  dmax = block_max(dmax, red);
+  // right-looking: after step j, row j of S holds row j of R
+  for (int j = 0; j < n; ++j) {
+    if (tid == 0) {
+      double d = S[j + (int64_t)j * n];
+      d = sqrt(fmax(d, 1e-30 * dmax));
+      s_d = d;
+      S[j + (int64_t)j * n] = d;
+    }
+    __syncthreads();
+    const double d = s_d;
+    for (int c = j + 1 + tid; c < n; c += kOneWG) S[j + (int64_t)c * n] /= d;
+    __syncthreads();
+    for (int e = tid; e < (n - j - 1) * (n - j - 1); e += kOneWG) {
+      const int r = j + 1 + e % (n - j - 1), c = j + 1 + e / (n - j - 1);
+      if (r <= c) S[r + (int64_t)c * n] -= S[j + (int64_t)r * n] * S[j + (int64_t)c * n];
+    }
+    __syncthreads();
+  }
+  // Rinv column c: solve R x = e_c (upper), one thread per column
+  for (int c = tid; c < n; c += kOneWG) {
+    for (int i = n - 1; i >= 0; --i) {
+      double v = (i == c) ? 1.0 : 0.0;
+      if (i > c) v = 0.0;
+      for (int l = i + 1; l <= c; ++l) v -= S[i + (int64_t)l * n] * Rinv[l + (int64_t)c * n];
+      Rinv[i + (int64_t)c * n] = (i <= c) ? v / S[i + (int64_t)i * n] : 0.0;
+    }
+  }
+}
+
+// Column j of X (p rows, column-major, ld p) scaled by 1/sigma_j when
+// sigma_j > cut * sigma_0, else replaced with a pseudo-random column.
+__global__ void scale_or_refill_kernel(double* X, int64_t p, int k, const double* sigma, double cut, uint64_t seed) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= p * k) return;
+  const int j = (int)(e / p);
+  const double s0 = sigma[0], sj = sigma[j];
+  if (sj > cut * s0 && sj > 0.0) X[e] /= sj;
+  else X[e] = rand_pm(seed, e % p, j);
+}
+
+// sigma_i = sqrt(max(lambda_i, 0))
+__global__ void sqrt_clamp_kernel(const double* lam, double* sigma, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) sigma[i] = sqrt(fmax(lam[i], 0.0));
+}
+
+// Sign convention: column j of X (ld p) becomes positive at its first entry whose
+// magnitude is >= 1/4 of its largest; the same flip is applied to column j of Y.
+__global__ __launch_bounds__(256) void sign_fix_kernel(double* X, int64_t p, double* Y, int64_t py) {
+  __shared__ double red[4];
+  __shared__ int redi[4];
+  __shared__ double s_flip;
+  const int j = blockIdx.x;
+  double* x = X + (int64_t)j * p;
+  double m = 0.0;
+  for (int64_t r = threadIdx.x; r < p; r += 256) m = fmax(m, fabs(x[r]));
+  m = block_max(m, red);
+  int first = 0x7fffffff;
+  for (int64_t r = threadIdx.x; r < p; r += 256)
+    if (m > 0.0 && fabs(x[r]) >= 0.25 * m) { first = (int)r; break; }
+  first = block_min_i(first, redi);
+  if (threadIdx.x == 0) s_flip = (m > 0.0 && x[first] < 0.0) ? -1.0 : 1.0;
+  __syncthreads();
+  const double f = s_flip;
+  if (f < 0.0) {
+    for (int64_t r = threadIdx.x; r < p; r += 256) x[r] = -x[r];
+    if (Y)
+      for (int64_t r = threadIdx.x; r < py; r += 256) Y[(int64_t)j * py + r] = -Y[(int64_t)j * py + r];
+  }
+}
+
+// Copy the first n columns of src (ld_src) into dst (ld_dst), p rows each.
+__global__ void copy_cols_kernel(const double* src, int64_t ld_src, double* dst, int64_t ld_dst, int64_t p, int n) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= p * n) return;
+  const int64_t r = e % p, c = e / p;
+  dst[r + c * ld_dst] = src[r + c * ld_src];
+}
+
+// ---------------------------------------------------------------------------
+// a4: temporal bases.  One workgroup per spatial mode i: Y_i[k, q] = V[q*N_t + k, i]
+// (N_t x n_mu) in LDS, one-sided Jacobi SVD, rank cut, DCT-II completion.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void temporal_svd_kernel(const double* __restrict__ V, int64_t ldV, int N_t, int n_mu,
+                                                           const int32_t* __restrict__ moff, double tau_t,
+                                                           double* __restrict__ Phi_t, int32_t* __restrict__ rank_out) {
+  extern __shared__ __align__(16) double Ys[];  // N_t * n_mu, then n_mu norms
+  __shared__ double red[4];
+  __shared__ int redi[4];
+  __shared__ int s_rot;
+  __shared__ int s_order[64];
+  __shared__ double s_coef[512];
+  const int i = blockIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int c0 = moff[i], nt = moff[i + 1] - c0;
+  double* out = Phi_t + (int64_t)c0 * N_t;
+  double* nrm = Ys + (int64_t)N_t * n_mu;
+  for (int e = tid; e < N_t * n_mu; e += 256) {
+    const int k = e % N_t, q = e / N_t;
+    Ys[e] = V[(int64_t)q * N_t + k + (int64_t)i * ldV];
+  }
+  __syncthreads();
+  // one-sided Jacobi: orthogonalise the columns pairwise (round-robin order, one pair per wave)
+  const int nn = n_mu + (n_mu & 1), m = nn - 1;
+  for (int sweep = 0; sweep < 40 && n_mu > 1; ++sweep) {
+    if (tid == 0) s_rot = 0;
+    __syncthreads();
+    for (int rnd = 0; rnd < m; ++rnd) {
+      for (int t = wave; t < nn / 2; t += 4) {
+        int a, b;
+        if (t == 0) { a = m; b = rnd; } else { a = (rnd + t) % m; b = (rnd - t + m) % m; }
+        if (a > b) { const int x = a; a = b; b = x; }
+        if (b >= n_mu) continue;
+        double* ya = Ys + (int64_t)a * N_t;
+        double* yb = Ys + (int64_t)b * N_t;
+        double al = 0.0, be = 0.0, ga = 0.0;
+        for (int k = lane; k < N_t; k += 64) {
+          al = fma(ya[k], ya[k], al);
+          be = fma(yb[k], yb[k], be);
+          ga = fma(ya[k], yb[k], ga);
+        }
+        for (int o = 32; o > 0; o >>= 1) {
+          al += __shfl_xor(al, o);
+          be += __shfl_xor(be, o);
+          ga += __shfl_xor(ga, o);
+        }
+        if (fabs(ga) > 1e-15 * sqrt(al * be) && fabs(ga) > 0.0) {
+          const double ze = (be - al) / (2.0 * ga);
+          const double tt = (ze >= 0.0 ? 1.0 : -1.0) / (fabs(ze) + sqrt(1.0 + ze * ze));
+          const double c = 1.0 / sqrt(1.0 + tt * tt), s = c * tt;
+          for (int k = lane; k < N_t; k += 64) {
+            const double x = ya[k], y = yb[k];
+            ya[k] = c * x - s * y;
+            yb[k] = s * x + c * y;
+          }
+          if (lane == 0) s_rot = 1;
+        }
+      }
+      __syncthreads();
+    }
+    if (!s_rot) break;
+    __syncthreads();
+  }
+  // column norms = singular values; order descending
+  for (int q = wave; q < n_mu; q += 4) {
+    double s = 0.0;
+    for (int k = lane; k < N_t; k += 64) s = fma(Ys[(int64_t)q * N_t + k], Ys[(int64_t)q * N_t + k], s);
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+    if (lane == 0) nrm[q] = sqrt(s);
+  }
+  __syncthreads();
+  if (tid < n_mu) {
+    int rank = 0;
+    for (int q = 0; q < n_mu; ++q)
+      if (nrm[q] > nrm[tid] || (nrm[q] == nrm[tid] && q < tid)) ++rank;
+    s_order[rank] = tid;
+  }
+  __syncthreads();
+  const double s1 = n_mu > 0 ? nrm[s_order[0]] : 0.0;
+  int r = 0;
+  for (int q = 0; q < n_mu; ++q)
+    if (s1 > 0.0 && nrm[q] > tau_t * s1) ++r;
+  if (tid == 0 && rank_out) rank_out[i] = r;
+  const int keep = min(r, nt);
+  int have = 0;
+  // data vectors: normalised columns in singular-value order
+  for (int j = 0; j < keep; ++j) {
+    const int q = s_order[j];
+    const double inv = 1.0 / nrm[q];
+    for (int k = tid; k < N_t; k += 256) out[(int64_t)j * N_t + k] = Ys[(int64_t)q * N_t + k] * inv;
+    have = j + 1;
+  }
+  __syncthreads();
+  // DCT-II completion, classical Gram-Schmidt twice against the kept vectors
+  double* cand = Ys;  // reuse LDS: N_t doubles
+  for (int mfreq = 0; have < nt && mfreq < N_t; ++mfreq) {
+    double c2 = 0.0;
+    for (int k = tid; k < N_t; k += 256) {
+      const double v = cos(M_PI * (double)mfreq * ((double)k + 0.5) / (double)N_t);
+      cand[k] = v;
+      c2 = fma(v, v, c2);
+    }
+    c2 = sqrt(block_sum(c2, red));
+    for (int pass = 0; pass < 2 && have > 0; ++pass) {
+      for (int l = wave; l < have; l += 4) {
+        double s = 0.0;
+        for (int k = lane; k < N_t; k += 64) s = fma(out[(int64_t)l * N_t + k], cand[k], s);
+        for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+        if (lane == 0) s_coef[l] = s;
+      }
+      __syncthreads();
+      for (int k = tid; k < N_t; k += 256) {
+        double v = cand[k];
+        for (int l = 0; l < have; ++l) v = fma(-s_coef[l], out[(int64_t)l * N_t + k], v);
+        cand[k] = v;
+      }
+      __syncthreads();
+    }
+    double n2 = 0.0;
+    for (int k = tid; k < N_t; k += 256) n2 = fma(cand[k], cand[k], n2);
+    n2 = sqrt(block_sum(n2, red));
+    if (n2 >= 1e-2 * c2) {
+      const double inv = 1.0 / n2;
+      for (int k = tid; k < N_t; k += 256) out[(int64_t)have * N_t + k] = cand[k] * inv;
+      ++have;
+    }
+    __syncthreads();
+  }
+  __syncthreads();
+  // sign convention on every column of this mode
+  for (int j = 0; j < nt; ++j) {
+    double* x = out + (int64_t)j * N_t;
+    double mx = 0.0;
+    for (int k = tid; k < N_t; k += 256) mx = fmax(mx, fabs(x[k]));
+    mx = block_max(mx, red);
+    int first = 0x7fffffff;
+    for (int k = tid; k < N_t; k += 256)
+      if (mx > 0.0 && fabs(x[k]) >= 0.25 * mx) { first = k; break; }
+    first = block_min_i(first, redi);
+    const bool flip = mx > 0.0 && x[first] < 0.0;
+    __syncthreads();
+    if (flip)
+      for (int k = tid; k < N_t; k += 256) x[k] = -x[k];
+    __syncthreads();
+  }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+size_t gram_partial_elems(int64_t K, int p) {
+  const int64_t nt = (p + kGT - 1) / kGT;
+  const int64_t tiles = nt * (nt + 1) / 2;
+  int64_t splits = (1024 + tiles - 1) / tiles;
+  const int64_t maxs = (K + 1023) / 1024;
+  if (splits > maxs) splits = maxs;
+  if (splits < 1) splits = 1;
+  return (size_t)splits * p * p;
+}
+
+hipError_t launch_gram(int64_t K, int p, const void* X, int in_prec, int64_t ks, int64_t ms, int gram_prec, double* G,
+                       double* partial, size_t partial_elems, hipStream_t s) {
+  const int64_t nt = (p + kGT - 1) / kGT;
+  const int64_t tiles = nt * (nt + 1) / 2;
+  const int splits = (int)(gram_partial_elems(K, p) / ((size_t)p * p));
+  if ((size_t)splits * p * p > partial_elems) return hipErrorInvalidValue;
+  int64_t kps = (K + splits - 1) / splits;
+  kps = (kps + kGK - 1) / kGK * kGK;
+  dim3 grid((unsigned)tiles, splits);
+  if (gram_prec == ST_F64) {
+    if (in_prec == ST_F64)
+      hipLaunchKernelGGL(gram_f64_kernel<double>, grid, dim3(256), 0, s, K, p, (const double*)X, ks, ms, kps, partial);
+    else
+      hipLaunchKernelGGL(gram_f64_kernel<float>, grid, dim3(256), 0, s, K, p, (const float*)X, ks, ms, kps, partial);
+  } else if (gram_prec == ST_F32) {
+    if (in_prec == ST_F64)
+      hipLaunchKernelGGL((gram_f32_kernel<double, false>), grid, dim3(256), 0, s, K, p, (const double*)X, ks, ms, kps,
+                         partial);
+    else
+      hipLaunchKernelGGL((gram_f32_kernel<float, false>), grid, dim3(256), 0, s, K, p, (const float*)X, ks, ms, kps,
+                         partial);
+  } else {
+    if (in_prec == ST_F64)
+      hipLaunchKernelGGL((gram_f32_kernel<double, true>), grid, dim3(256), 0, s, K, p, (const double*)X, ks, ms, kps,
+                         partial);
+    else
+      hipLaunchKernelGGL((gram_f32_kernel<float, true>), grid, dim3(256), 0, s, K, p, (const float*)X, ks, ms, kps,
+                         partial);
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int64_t pp = (int64_t)p * p;
+  hipLaunchKernelGGL(gram_finish_kernel, dim3((unsigned)((pp + 255) / 256)), dim3(256), 0, s, p, splits, partial, G);
+  return hipGetLastError();
+}
+
+hipError_t launch_rand_fill(double* X, int64_t p, int k, uint64_t seed, hipStream_t s) {
+  const int64_t n = p * k;
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(rand_fill_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, X, p, k, seed);
+  return hipGetLastError();
+}
+
+hipError_t launch_orth(double* X, int64_t p, int k, uint64_t seed, hipStream_t s) {
+  hipLaunchKernelGGL(orth_cgs2_kernel, dim3(1), dim3(kOneWG), 0, s, X, p, k, seed);
+  return hipGetLastError();
+}
+
+hipError_t launch_jacobi(int k, double* A, double* Z, double* evals, double* Zout, hipStream_t s) {
+  hipLaunchKernelGGL(jacobi_eig_kernel, dim3(1), dim3(kOneWG), 0, s, k, A, Z, evals, Zout, 60);
+  return hipGetLastError();
+}
+
+hipError_t launch_chol_inv(int n, double* S, double* Rinv, hipStream_t s) {
+  hipLaunchKernelGGL(chol_inv_kernel, dim3(1), dim3(kOneWG), 0, s, n, S, Rinv);
+  return hipGetLastError();
+}
+
+hipError_t launch_scale_or_refill(double* X, int64_t p, int k, const double* sigma, double cut, uint64_t seed,
+                                  hipStream_t s) {
+  const int64_t n = p * k;
+  hipLaunchKernelGGL(scale_or_refill_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, X, p, k, sigma, cut,
+                     seed);
+  return hipGetLastError();
+}
+
+hipError_t launch_sqrt_clamp(const double* lam, double* sigma, int n, hipStream_t s) {
+  hipLaunchKernelGGL(sqrt_clamp_kernel, dim3((n + 255) / 256), dim3(256), 0, s, lam, sigma, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_sign_fix(double* X, int64_t p, int k, double* Y, int64_t py, hipStream_t s) {
+  hipLaunchKernelGGL(sign_fix_kernel, dim3(k), dim3(256), 0, s, X, p, Y, py);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_cols(const double* src, int64_t ld_src, double* dst, int64_t ld_dst, int64_t p, int n,
+                            hipStream_t s) {
+  const int64_t e = p * n;
+  if (e == 0) return hipSuccess;
+  hipLaunchKernelGGL(copy_cols_kernel, dim3((unsigned)((e + 255) / 256)), dim3(256), 0, s, src, ld_src, dst, ld_dst, p,
+                     n);
+  return hipGetLastError();
+}
+
+hipError_t launch_temporal_svd(const double* V, int64_t ldV, int N_t, int n_mu, int n_s, const int32_t* moff,
+                               double tau_t, double* Phi_t, int32_t* rank_out, hipStream_t s) {
+  const size_t lds = sizeof(double) * ((size_t)N_t * n_mu + n_mu);
+  hipError_t e = hipFuncSetAttribute((const void*)temporal_svd_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(temporal_svd_kernel, dim3(n_s), dim3(256), lds, s, V, ldV, N_t, n_mu, moff, tau_t, Phi_t,
+                     rank_out);
+  return hipGetLastError();
+}
+
+}  // namespace strom
