@@ -269,6 +269,20 @@ st_status st_solve(const st_rom_desc* d, const void* rom, int32_t n_q, const dou
                    double ir_tol, int32_t ir_max, double* coeff, int64_t coeff_cap, int64_t* coeff_off,
                    double* relres, int32_t* info, int32_t* iters, void* ws, size_t ws_bytes, void* stream);
 
+/* ========================================================================
+ * Phase timing (measurement tools).  After st_timing_enable(1), every st_solve
+ * records HIP events on its stream at its phase boundaries; after the caller
+ * has synchronised that stream, st_timing_read fills ms[p] with the elapsed
+ * milliseconds of phase p of the most recent st_solve and returns the number
+ * of phases (or a negative status).  Phases: 0 plan, 1 form (assembly of
+ * every query's system), 2 right-hand-side norms, 3 batched LU, 4 first
+ * triangular solves, 5 all refinement steps, 6 final residual and checks.
+ * Not thread-safe; timing one solve at a time is the intended use.
+ * ====================================================================== */
+#define ST_TIMING_PHASES 7
+st_status st_timing_enable(int32_t on);
+int32_t st_timing_read(double* ms, int32_t cap);
+
 #ifdef __cplusplus
 }
 #endif

@@ -230,6 +230,45 @@ st_status st_form(const st_rom_desc* d, const void* rom, int32_t n_q, const doub
   return ST_OK;
 }
 
+}  // extern "C"
+
+namespace {
+bool g_timing = false;
+bool g_timing_recorded = false;
+hipEvent_t g_events[ST_TIMING_PHASES + 1];
+bool g_events_made = false;
+
+hipError_t mark(int i, hipStream_t s) {
+  if (!g_timing) return hipSuccess;
+  return hipEventRecord(g_events[i], s);
+}
+}  // namespace
+
+extern "C" {
+
+st_status st_timing_enable(int32_t on) {
+  if (on && !g_events_made) {
+    for (int i = 0; i <= ST_TIMING_PHASES; ++i)
+      if (hipEventCreate(&g_events[i]) != hipSuccess) return ST_EDEVICE;
+    g_events_made = true;
+  }
+  g_timing = on != 0;
+  g_timing_recorded = false;
+  return ST_OK;
+}
+
+int32_t st_timing_read(double* ms, int32_t cap) {
+  if (!ms || cap < 0) return ST_EINVAL;
+  if (!g_events_made || !g_timing_recorded) return ST_EINVAL;
+  const int n = cap < ST_TIMING_PHASES ? cap : ST_TIMING_PHASES;
+  for (int i = 0; i < n; ++i) {
+    float t = 0.f;
+    if (hipEventElapsedTime(&t, g_events[i], g_events[i + 1]) != hipSuccess) return ST_EDEVICE;
+    ms[i] = (double)t;
+  }
+  return ST_TIMING_PHASES;
+}
+
 size_t st_solve_workspace(const st_rom_desc* d, int32_t n_q, int64_t sum_w, int64_t sum_w2, int32_t lu_prec) {
   if (!desc_ok(d) || n_q < 0 || sum_w < 0 || sum_w2 < 0) return 0;
   const size_t el = lu_prec == ST_F32 ? sizeof(float) : sizeof(double);
@@ -281,22 +320,31 @@ st_status st_solve(const st_rom_desc* d, const void* rom, int32_t n_q, const dou
   plan.info = info;
   const int32_t n_max = (int32_t)n;
 
+  ST_TRY(mark(0, s));
   ST_TRY(launch_plan(n_q, d->n_s, rv.moff, nt_q, theta_A, theta_f, theta_0, d->Q, d->Qf, d->Q0, coeff_cap, mats_cap,
                      plan, s));
+  ST_TRY(mark(1, s));
   ST_TRY(launch_form(rv, n_q, theta_A, theta_f, theta_0, nt_q, plan, lu_prec, mats, b, n_max, s));
+  ST_TRY(mark(2, s));
   ST_TRY(launch_vec_norms(n_q, plan, b, bnorm, s));
+  ST_TRY(mark(3, s));
   ST_TRY(launch_lu(n_q, plan, lu_prec, mats, perm, n_max, s));
+  ST_TRY(mark(4, s));
   ST_TRY(launch_fill_i32(active, n_q, 1, s));
   ST_TRY(launch_lu_solve(n_q, plan, lu_prec, mats, perm, b, coeff, 0, active, n_max, s));
+  ST_TRY(mark(5, s));
   for (int it = 0; it < ir_max; ++it) {
     ST_TRY(launch_residual(rv, n_q, theta_A, nt_q, plan, b, coeff, r, rnorm, active, n_max, s));
     ST_TRY(launch_ir_check(n_q, plan, rnorm, bnorm, ir_tol, it, 0, active, relres, iters, s));
     ST_TRY(launch_lu_solve(n_q, plan, lu_prec, mats, perm, r, coeff, 1, active, n_max, s));
   }
+  ST_TRY(mark(6, s));
   ST_TRY(launch_residual(rv, n_q, theta_A, nt_q, plan, b, coeff, r, rnorm, nullptr, n_max, s));
   const int flag = (lu_prec == ST_F32 || ir_max > 0) ? 2 : 1;
   ST_TRY(launch_ir_check(n_q, plan, rnorm, bnorm, ir_tol, ir_max, flag, active, relres, iters, s));
   ST_TRY(launch_finalize(n_q, plan, coeff, info, s));
+  ST_TRY(mark(7, s));
+  if (g_timing) g_timing_recorded = true;
   return ST_OK;
 }
 

@@ -66,7 +66,11 @@ _SIGNATURES = {
     "st_solve_workspace": (_SZ, [ctypes.POINTER(st_rom_desc), _I32, _I64, _I64, _I32]),
     "st_solve": (_I32, [ctypes.POINTER(st_rom_desc), _P, _I32, _P, _P, _P, _P, _I32, _D, _I32, _P, _I64, _P, _P, _P,
                         _P, _P, _SZ, _P]),
+    "st_timing_enable": (_I32, [_I32]),
+    "st_timing_read": (_I32, [ctypes.POINTER(ctypes.c_double), _I32]),
 }
+
+TIMING_PHASES = ("plan", "form", "rhs_norms", "lu", "first_solve", "refinement", "final_check")
 
 EXPORTED = tuple(_SIGNATURES)
 
@@ -273,3 +277,16 @@ def st_solve(desc: RomDesc, rom: torch.Tensor, theta_A: torch.Tensor, theta_f: O
                           _ptr(bufs.relres), _ptr(bufs.info), _ptr(bufs.iters), _ptr(bufs.ws), bufs.ws_bytes,
                           _stream()), "st_solve")
     return bufs
+
+
+def st_timing_enable(on: bool = True):
+    _check(lib().st_timing_enable(1 if on else 0), "st_timing_enable")
+
+
+def st_timing_read() -> dict:
+    """Phase durations (ms) of the most recent st_solve; the stream must be synchronised."""
+    buf = (ctypes.c_double * len(TIMING_PHASES))()
+    n = lib().st_timing_read(buf, len(TIMING_PHASES))
+    if n < 0:
+        raise StromError(n, "st_timing_read")
+    return {k: float(buf[i]) for i, k in enumerate(TIMING_PHASES)}
