@@ -38,23 +38,315 @@ struct Mfma<float> {
   static __device__ inline int row(int lk, int r) { return 4 * lk + r; }
 };
 
+// Wavefront reductions of the device library (DPP based, all lanes active).
+extern "C" __device__ float __ockl_wfred_max_f32(float);
+extern "C" __device__ double __ockl_wfred_max_f64(double);
+extern "C" __device__ double __ockl_wfred_add_f64(double);
+
+__device__ inline float wave_max(float v) { return __ockl_wfred_max_f32(v); }
+__device__ inline double wave_max(double v) { return __ockl_wfred_max_f64(v); }
+
+// Block sizes per element type: NBO-wide outer blocks are factored as
+// NBI-wide sub-panels held in registers; updates run on the matrix cores from
+// LDS tiles of RB rows x K and K x CB columns (K <= NBO).
 template <typename T>
-__device__ inline T wave_shfl_xor(T v, int m) {
-  return __shfl_xor(v, m);
+struct LuCfg;
+template <>
+struct LuCfg<float> {
+  static constexpr int NBO = 128, RB = 128, CB = 64, CHW = 64;
+};
+template <>
+struct LuCfg<double> {
+  static constexpr int NBO = 64, RB = 64, CB = 64, CHW = 64;
+};
+
+constexpr int kLuThreads = 512;
+constexpr int kLuWaves = kLuThreads / 64;
+
+template <typename T>
+constexpr size_t lu_pool_elems() {
+  using C = LuCfg<T>;
+  // max of: update tiles ((RB + 2 CB) x (NBO + 4)), the row-permutation staging
+  // (2 NBO x CHW) and the unit lower block with its inverse (2 NBO x (NBO + 1)) plus the
+  // per-wave strips of the triangular product when they do not fit in the first
+  constexpr size_t a = (size_t)(C::RB + 2 * C::CB) * (C::NBO + 4);
+  constexpr size_t b = (size_t)2 * C::NBO * C::CHW;
+  constexpr size_t strips = (size_t)kLuWaves * C::NBO * 16;
+  constexpr size_t c = (size_t)2 * C::NBO * (C::NBO + 1) + (strips <= (size_t)C::NBO * (C::NBO + 1) ? 0 : strips);
+  return a > b ? (a > c ? a : c) : (b > c ? b : c);
 }
 
-template <typename T, int NB, int BLOCK, int R>
-__global__ __launch_bounds__(BLOCK) void lu_kernel(int32_t n_q, Plan plan, T* __restrict__ mats,
-                                                   int32_t* __restrict__ piv) {
-  constexpr int NW = BLOCK / 64;
+// A[r, c] -= sum_{k < K} A[r, k0 + k] A[k0 + k, c] for r in [r_lo, r_hi), c in
+// [c_lo, c_hi), on the matrix cores.  A is row-major with leading dimension w.
+// The left factor (RB rows x K) and the right factor (K x CB, stored
+// transposed) are staged in LDS with the K index permuted so that the four
+// K values a lane feeds to four consecutive MFMA steps are contiguous: one
+// 128-bit LDS read per operand per four steps.  Each wave owns an
+// (RB/4) x (CB/2) block of the output tile in 16 x 16 MFMA tiles, loaded from
+// global memory before the staging barrier so their latency overlaps it.
+template <typename T>
+struct Vec4;
+template <>
+struct Vec4<float> {
+  typedef float4 type;
+  static constexpr int per = 4;
+};
+template <>
+struct Vec4<double> {
+  typedef double2 type;
+  static constexpr int per = 2;
+};
+
+template <typename T>
+__device__ __forceinline__ int kperm(int k) {
+  constexpr int Q = LuCfg<T>::NBO / 4;
+  return (k & 3) * Q + (k >> 2);
+}
+
+template <typename T>
+__device__ __forceinline__ void tile_update(T* __restrict__ A, int w, int r_lo, int r_hi, int c_lo, int c_hi, int k0,
+                                            int K, T* __restrict__ pool) {
+  using C = LuCfg<T>;
+  constexpr int NBO = C::NBO, RB = C::RB, CB = C::CB;
+  constexpr int LDK = NBO + 4;  // row stride of the staged operands (16-byte aligned rows)
+  constexpr int Q = NBO / 4;
+  constexpr int MR = RB / 4 / 16, MC = CB / 2 / 16;
+  constexpr int PER = Vec4<T>::per;  // K steps per 128-bit read
+  constexpr int UPT = NBO * CB / kLuThreads;  // right-factor elements staged per thread
+  typedef typename Vec4<T>::type VT;
   typedef typename Mfma<T>::v4 v4;
-  __shared__ T s_urow[2][NB];
-  __shared__ T s_xrow[2][NB];
+  if (r_lo >= r_hi || c_lo >= c_hi || K <= 0) return;
+  T* Ls = pool;                   // RB x LDK
+  T* Us0 = pool + RB * LDK;       // CB x LDK, two buffers (transposed right factor)
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int wr = (wave >> 1) * (RB / 4);
+  const int wc = (wave & 1) * (CB / 2);
+  const int ksteps = (K + 3) / 4;
+  const int kchunks = (ksteps + PER - 1) / PER;
+  for (int rb = r_lo; rb < r_hi; rb += RB) {
+    const int nr = min(RB, r_hi - rb);
+    // register tiles for the current column tile and its successor
+    v4 acc[MR][MC];
+    T ur[UPT];
+    auto load_acc = [&](int cb, v4 (&dst)[MR][MC]) {
+      const int nc = min(CB, c_hi - cb);
+#pragma unroll
+      for (int x = 0; x < MR; ++x)
+#pragma unroll
+        for (int y = 0; y < MC; ++y)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int row = wr + 16 * x + Mfma<T>::row(lk, r);
+            const int col = wc + 16 * y + li;
+            dst[x][y][r] = (row < nr && col < nc) ? A[(int64_t)(rb + row) * w + cb + col] : T(0);
+          }
+    };
+    auto load_u = [&](int cb) {
+      const int nc = min(CB, c_hi - cb);
+#pragma unroll
+      for (int t = 0; t < UPT; ++t) {
+        const int e = tid + t * kLuThreads;
+        const int k = e / CB, j = e % CB;
+        ur[t] = (k < K && j < nc) ? A[(int64_t)(k0 + k) * w + cb + j] : T(0);
+      }
+    };
+    auto store_u = [&](T* Us) {
+#pragma unroll
+      for (int t = 0; t < UPT; ++t) {
+        const int e = tid + t * kLuThreads;
+        const int k = e / CB, j = e % CB;
+        Us[j * LDK + kperm<T>(k)] = ur[t];
+      }
+    };
+    __syncthreads();
+    load_u(c_lo);
+    load_acc(c_lo, acc);
+#pragma unroll 8
+    for (int e = tid; e < RB * NBO; e += kLuThreads) {
+      const int i = e / NBO, k = e % NBO;
+      Ls[i * LDK + kperm<T>(k)] = (i < nr && k < K) ? A[(int64_t)(rb + i) * w + k0 + k] : T(0);
+    }
+    store_u(Us0);
+    __syncthreads();
+    int buf = 0;
+    for (int cb = c_lo; cb < c_hi; cb += CB) {
+      const int nc = min(CB, c_hi - cb);
+      const bool more = cb + CB < c_hi;
+      v4 nxt[MR][MC];
+      if (more) {  // successor tile in flight while this one runs on the matrix cores
+        load_u(cb + CB);
+        load_acc(cb + CB, nxt);
+      }
+      const T* Us = Us0 + buf * CB * LDK;
+      for (int kc = 0; kc < kchunks; ++kc) {
+        VT av[MR], bv[MC];
+#pragma unroll
+        for (int x = 0; x < MR; ++x)
+          av[x] = *reinterpret_cast<const VT*>(Ls + (wr + 16 * x + li) * LDK + lk * Q + kc * PER);
+#pragma unroll
+        for (int y = 0; y < MC; ++y)
+          bv[y] = *reinterpret_cast<const VT*>(Us + (wc + 16 * y + li) * LDK + lk * Q + kc * PER);
+#pragma unroll
+        for (int p = 0; p < PER; ++p)
+#pragma unroll
+          for (int x = 0; x < MR; ++x)
+#pragma unroll
+            for (int y = 0; y < MC; ++y) {
+              const T a = -reinterpret_cast<const T*>(&av[x])[p];
+              const T b = reinterpret_cast<const T*>(&bv[y])[p];
+              acc[x][y] = Mfma<T>::op(a, b, acc[x][y]);
+            }
+      }
+#pragma unroll
+      for (int x = 0; x < MR; ++x)
+#pragma unroll
+        for (int y = 0; y < MC; ++y)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int row = wr + 16 * x + Mfma<T>::row(lk, r);
+            const int col = wc + 16 * y + li;
+            if (row < nr && col < nc) A[(int64_t)(rb + row) * w + cb + col] = acc[x][y][r];
+          }
+      if (more) {
+        store_u(Us0 + (buf ^ 1) * CB * LDK);
+#pragma unroll
+        for (int x = 0; x < MR; ++x)
+#pragma unroll
+          for (int y = 0; y < MC; ++y) acc[x][y] = nxt[x][y];
+      }
+      buf ^= 1;
+      __syncthreads();
+    }
+  }
+}
+
+// Row interchanges piv[0..n) (step i swaps rows base+i and piv[i] >= base+i),
+// composed into a list of moves "row dst receives the old content of row src"
+// (thread 0, in LDS), then applied to the columns [c_lo, c_hi) outside
+// [skip_lo, skip_hi) by staging the source row segments through LDS with
+// coalesced loads and stores.  Uses s_mv (>= 7 n ints).
+template <typename T>
+__device__ __forceinline__ void permute_rows(T* __restrict__ A, int w, int base, int n, const int32_t* __restrict__ piv, int c_lo,
+                             int c_hi, int skip_lo, int skip_hi, T* __restrict__ pool, int32_t* __restrict__ s_mv,
+                             int32_t* s_nmoves) {
+  constexpr int CHW = LuCfg<T>::CHW;
+  const int tid = threadIdx.x;
+  int32_t* cin = s_mv;            // content of rows base..base+n-1
+  int32_t* orow = s_mv + n;       // rows outside the range that were touched
+  int32_t* ocon = s_mv + 2 * n;   // their content
+  int32_t* msrc = s_mv + 3 * n;   // moves (src packed with dst: dst in cin-reuse)
+  if (tid == 0) {
+    int m = 0;
+    for (int i = 0; i < n; ++i) cin[i] = base + i;
+    for (int i = 0; i < n; ++i) {
+      const int r = base + i, p = piv[i];
+      if (p == r) continue;
+      if (p < base + n) {
+        const int t = cin[i];
+        cin[i] = cin[p - base];
+        cin[p - base] = t;
+      } else {
+        int j = 0;
+        while (j < m && orow[j] != p) ++j;
+        if (j == m) { orow[m] = p; ocon[m] = p; ++m; }
+        const int t = cin[i];
+        cin[i] = ocon[j];
+        ocon[j] = t;
+      }
+    }
+    // moves: rows inside first (dst = base + i), then outside rows
+    int nm = 0;
+    for (int i = 0; i < n; ++i)
+      if (cin[i] != base + i) { msrc[2 * nm] = cin[i]; msrc[2 * nm + 1] = base + i; ++nm; }
+    for (int j = 0; j < m; ++j)
+      if (ocon[j] != orow[j]) { msrc[2 * nm] = ocon[j]; msrc[2 * nm + 1] = orow[j]; ++nm; }
+    *s_nmoves = nm;
+  }
+  __syncthreads();
+  const int nm = *s_nmoves;
+  if (nm == 0) return;
+  for (int cb = c_lo; cb < c_hi; cb += CHW) {
+    if (cb + CHW > skip_lo && cb < skip_hi && cb >= skip_lo && cb + CHW <= skip_hi) continue;
+    for (int e = tid; e < nm * CHW; e += kLuThreads) {
+      const int t = e / CHW, j = e % CHW;
+      const int col = cb + j;
+      if (col < c_hi && (col < skip_lo || col >= skip_hi)) pool[t * CHW + j] = A[(int64_t)msrc[2 * t] * w + col];
+    }
+    __syncthreads();
+    for (int e = tid; e < nm * CHW; e += kLuThreads) {
+      const int t = e / CHW, j = e % CHW;
+      const int col = cb + j;
+      if (col < c_hi && (col < skip_lo || col >= skip_hi)) A[(int64_t)msrc[2 * t + 1] * w + col] = pool[t * CHW + j];
+    }
+    __syncthreads();
+  }
+}
+
+// Rows [r0, r0 + n) <- L^{-1} rows for the columns [c_lo, c_hi), L the unit
+// lower n x n block at A[r0.., r0..] (n <= NMAX <= 32).  Column chunks are
+// staged through LDS with coalesced row-segment loads; each thread then
+// substitutes down one column in LDS; the chunk is stored back coalesced.
+template <typename T, int NMAX>
+__device__ __forceinline__ void block_row_solve(T* __restrict__ A, int w, int r0, int n, int c_lo, int c_hi,
+                                                T* __restrict__ Ls, T* __restrict__ pool) {
+  constexpr int CW = (64 * 1024) / (sizeof(T) * NMAX) < kLuThreads ? (64 * 1024) / (sizeof(T) * NMAX) : kLuThreads;
+  const int tid = threadIdx.x;
+  for (int e = tid; e < n * n; e += kLuThreads) {
+    const int i = e / n, k = e % n;
+    Ls[i * NMAX + k] = A[(int64_t)(r0 + i) * w + r0 + k];
+  }
+  for (int cb = c_lo; cb < c_hi; cb += CW) {
+    const int nc = min(CW, c_hi - cb);
+    __syncthreads();
+#pragma unroll 4
+    for (int e = tid; e < n * CW; e += kLuThreads) {
+      const int i = e / CW, j = e % CW;
+      if (j < nc) pool[i * CW + j] = A[(int64_t)(r0 + i) * w + cb + j];
+    }
+    __syncthreads();
+    if (tid < nc) {
+      for (int c = 1; c < n; ++c) {
+        T acc = pool[c * CW + tid];
+        for (int k = 0; k < c; ++k) acc -= Ls[c * NMAX + k] * pool[k * CW + tid];
+        pool[c * CW + tid] = acc;
+      }
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int e = tid; e < n * CW; e += kLuThreads) {
+      const int i = e / CW, j = e % CW;
+      if (j < nc) A[(int64_t)(r0 + i) * w + cb + j] = pool[i * CW + j];
+    }
+  }
+  __syncthreads();
+}
+
+// One workgroup factors one query at a time (persistent, work queue).  Row r of
+// the query is owned by thread r % 512 in register slot r / 512 (R slots) while
+// its sub-panel is factored.  Pivoting is LAPACK-style partial pivoting; P[i]
+// receives the row swapped with row i at step i.  Interchanges are applied
+// inside the current outer block and to the columns right of it; columns left
+// of the block are never swapped, so the solve interleaves each block's
+// interchanges with its forward-substitution step.
+template <typename T, int R, int NBI>
+__global__ __launch_bounds__(kLuThreads) void lu_kernel(int32_t n_q, Plan plan, T* __restrict__ mats,
+                                                        int32_t* __restrict__ piv) {
+  using C = LuCfg<T>;
+  constexpr int NBO = C::NBO;
+  constexpr int BLOCK = kLuThreads, NW = kLuWaves;
+  static_assert(NBO % NBI == 0 && NBI <= 32, "block shape");
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  T* pool = reinterpret_cast<T*>(lds_raw);
+  __shared__ T s_urow[2][NBI];
+  __shared__ T s_xrow[2][NBI];
+  __shared__ T s_umask[2][NBI];
   __shared__ T s_redv[2][NW];
   __shared__ int32_t s_redr[2][NW];
-  __shared__ T s_L11[NB * NB];
-  __shared__ int32_t s_piv[NB];
-  __shared__ int32_t s_perm[R * BLOCK];  // composed row permutation of the current query
+  __shared__ int32_t s_piv[NBO];
+  __shared__ int32_t s_mv[7 * NBO + 8];  // permute_rows: 3 n bookkeeping + up to 2 n moves (src, dst)
+  __shared__ int32_t s_nm;
+  __shared__ T s_L[32 * 32];
   __shared__ int32_t s_q;
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
@@ -72,41 +364,43 @@ __global__ __launch_bounds__(BLOCK) void lu_kernel(int32_t n_q, Plan plan, T* __
     T* A = mats + plan.mat_off[q];
     int32_t* P = piv + plan.coeff_off[q];
     int32_t zero_piv = 0;
-    for (int i = tid; i < w; i += BLOCK) s_perm[i] = i;
 
-    for (int p0 = 0; p0 < w; p0 += NB) {
-      const int nb = min(NB, w - p0);
-      // ---------------- panel: rows p0.., columns p0..p0+nb, in registers
-      T v[R][NB];
+    for (int p0 = 0; p0 < w; p0 += NBO) {
+      const int nbo = min(NBO, w - p0);
+      // ===================== factor the outer block, one sub-panel at a time
+      for (int i0 = p0; i0 < p0 + nbo; i0 += NBI) {
+        const int nbi = min(NBI, p0 + nbo - i0);
+        T v[R][NBI];
 #pragma unroll
-      for (int s = 0; s < R; ++s) {
-        const int r = p0 + tid + s * BLOCK;
+        for (int s = 0; s < R; ++s) {
+          const int r = tid + s * BLOCK;
+          const bool live = r >= i0 && r < w;
 #pragma unroll
-        for (int c = 0; c < NB; ++c) v[s][c] = (r < w && c < nb) ? A[(int64_t)r * w + p0 + c] : T(0);
-      }
-#pragma unroll
-      for (int c = 0; c < NB; ++c) {
-        if (c < nb) {
+          for (int c = 0; c < NBI; ++c) v[s][c] = (live && c < nbi) ? A[(int64_t)r * w + i0 + c] : T(0);
+        }
+        // Column steps with a rotating register row: before step c, slot k of
+        // a row holds sub-panel column (c + k) mod NBI, so the pivot column is
+        // always slot 0 and every register index is a compile-time constant.
+        // After the step the row rotates left by one; the eliminated value (the
+        // L multiplier, or the U entry of a pivot row) moves to the end, so after
+        // NBI rotations every row is back in column order.  Rows exchange whole
+        // register rows, i.e. the full sub-panel row as in LAPACK.
+        for (int c = 0; c < nbi; ++c) {
           const int buf = c & 1;
-          const int diag = p0 + c;
-          // pivot search: largest |v| in column c among rows >= diag, lowest row on ties
+          const int diag = i0 + c;
           T best = T(-1);
           int32_t brow = 0x7fffffff;
 #pragma unroll
           for (int s = 0; s < R; ++s) {
-            const int r = p0 + tid + s * BLOCK;
+            const int r = tid + s * BLOCK;
             if (r >= diag && r < w) {
-              const T a = v[s][c] < T(0) ? -v[s][c] : v[s][c];
+              const T a = v[s][0] < T(0) ? -v[s][0] : v[s][0];
               if (a > best) { best = a; brow = r; }
             }
           }
-#pragma unroll
-          for (int m = 32; m > 0; m >>= 1) {
-            const T ob = wave_shfl_xor(best, m);
-            const int32_t orow = __shfl_xor(brow, m);
-            if (ob > best || (ob == best && orow < brow)) { best = ob; brow = orow; }
-          }
-          if (lane == 0) { s_redv[buf][wave] = best; s_redr[buf][wave] = brow; }
+          const T wbest = wave_max(best);
+          const int32_t wrow = __ockl_wfred_min_i32(best == wbest ? brow : 0x7fffffff);
+          if (lane == 0) { s_redv[buf][wave] = wbest; s_redr[buf][wave] = wrow; }
           __syncthreads();
           best = s_redv[buf][0];
           brow = s_redr[buf][0];
@@ -121,145 +415,155 @@ __global__ __launch_bounds__(BLOCK) void lu_kernel(int32_t n_q, Plan plan, T* __
             prow = diag;
             if (zero_piv == 0) zero_piv = diag + 1;
           }
-          // exchange rows diag and prow inside the panel; every thread gets the pivot row
-          const int tp = (prow - p0) % BLOCK, sp = (prow - p0) / BLOCK;
-          if (tid == tp) {
-#pragma unroll
-            for (int s = 0; s < R; ++s)
-              if (s == sp) {
-#pragma unroll
-                for (int cc = 0; cc < NB; ++cc) s_urow[buf][cc] = v[s][cc];
-              }
-          }
-          if (tid == c) {
-#pragma unroll
-            for (int cc = 0; cc < NB; ++cc) s_xrow[buf][cc] = v[0][cc];
-          }
-          __syncthreads();
-          if (tid == c) {
-#pragma unroll
-            for (int cc = 0; cc < NB; ++cc) v[0][cc] = s_urow[buf][cc];
-          }
-          if (tid == tp && prow != diag) {
-#pragma unroll
-            for (int s = 0; s < R; ++s)
-              if (s == sp) {
-#pragma unroll
-                for (int cc = 0; cc < NB; ++cc) v[s][cc] = s_xrow[buf][cc];
-              }
-          }
-          if (tid == 0) {
-            s_piv[c] = prow;
-            const int32_t t = s_perm[diag];
-            s_perm[diag] = s_perm[prow];
-            s_perm[prow] = t;
-          }
-          const T d = s_urow[buf][c];
-          const T inv = (d != T(0)) ? T(1) / d : T(0);
+          const int live = nbi - c;  // slots 0..live-1 hold columns not yet eliminated
 #pragma unroll
           for (int s = 0; s < R; ++s) {
-            const int r = p0 + tid + s * BLOCK;
-            if (r > diag && r < w) {
-              const T l = v[s][c] * inv;
-              v[s][c] = l;
+            const int r = tid + s * BLOCK;
+            if (r == prow) {
 #pragma unroll
-              for (int cc = c + 1; cc < NB; ++cc) v[s][cc] -= l * s_urow[buf][cc];
+              for (int k = 0; k < NBI; ++k) {
+                s_urow[buf][k] = v[s][k];
+                s_umask[buf][k] = k < live ? v[s][k] : T(0);
+              }
+            }
+            if (r == diag) {
+#pragma unroll
+              for (int k = 0; k < NBI; ++k) s_xrow[buf][k] = v[s][k];
+            }
+          }
+          __syncthreads();
+#pragma unroll
+          for (int s = 0; s < R; ++s) {
+            const int r = tid + s * BLOCK;
+            if (r == diag) {
+#pragma unroll
+              for (int k = 0; k < NBI; ++k) v[s][k] = s_urow[buf][k];
+            } else if (r == prow) {
+#pragma unroll
+              for (int k = 0; k < NBI; ++k) v[s][k] = s_xrow[buf][k];
+            }
+          }
+          if (tid == 0) {
+            s_piv[diag - p0] = prow;
+            P[diag] = prow;
+          }
+          const T d = s_urow[buf][0];
+          const T inv = (d != T(0)) ? T(1) / d : T(0);
+          T um[NBI];
+#pragma unroll
+          for (int k = 1; k < NBI; ++k) um[k] = s_umask[buf][k];
+#pragma unroll
+          for (int s = 0; s < R; ++s) {
+            if (s * BLOCK >= w) continue;  // slot empty for every thread (uniform)
+            const int r = tid + s * BLOCK;
+            if (r > diag && r < w) {
+              const T l = v[s][0] * inv;
+              v[s][0] = l;
+#pragma unroll
+              for (int k = 1; k < NBI; ++k) v[s][k] -= l * um[k];
+            }
+#pragma unroll
+            for (int k = 0; k + 1 < NBI; ++k) {
+              const T t = v[s][k];
+              v[s][k] = v[s][k + 1];
+              v[s][k + 1] = t;
             }
           }
         }
-      }
-      // write the factored panel back
+        // complete the NBI rotations when the sub-panel is narrower than NBI
+        for (int c = nbi; c < NBI; ++c) {
 #pragma unroll
-      for (int s = 0; s < R; ++s) {
-        const int r = p0 + tid + s * BLOCK;
-        if (r < w) {
+          for (int s = 0; s < R; ++s)
 #pragma unroll
-          for (int c = 0; c < NB; ++c)
-            if (c < nb) A[(int64_t)r * w + p0 + c] = v[s][c];
+            for (int k = 0; k + 1 < NBI; ++k) {
+              const T t = v[s][k];
+              v[s][k] = v[s][k + 1];
+              v[s][k + 1] = t;
+            }
         }
-      }
-      __syncthreads();
-      // ---------------- row interchanges on the columns outside the panel (in pivot order)
-      for (int col = tid; col < w; col += BLOCK) {
-        if (col >= p0 && col < p0 + nb) continue;
-        for (int c = 0; c < nb; ++c) {
-          const int pr = s_piv[c];
-          if (pr != p0 + c) {
-            T* a = A + (int64_t)(p0 + c) * w + col;
-            T* b = A + (int64_t)pr * w + col;
-            const T t = *a;
-            *a = *b;
-            *b = t;
+#pragma unroll
+        for (int s = 0; s < R; ++s) {
+          const int r = tid + s * BLOCK;
+          if (r >= i0 && r < w) {
+#pragma unroll
+            for (int c = 0; c < NBI; ++c)
+              if (c < nbi) A[(int64_t)r * w + i0 + c] = v[s][c];
           }
         }
+        __syncthreads();
+        // this sub-panel's interchanges on the other columns of the outer block
+        permute_rows<T>(A, w, i0, nbi, s_piv + (i0 - p0), p0, p0 + nbo, i0, i0 + nbi, pool, s_mv, &s_nm);
+        const int cr = i0 + nbi;
+        if (cr < p0 + nbo) {
+          // pivot rows: solve against the sub-panel's unit lower block; rows below: rank-nbi update
+          block_row_solve<T, NBI>(A, w, i0, nbi, cr, p0 + nbo, s_L, pool);
+          tile_update<T>(A, w, cr, w, cr, p0 + nbo, i0, nbi, pool);
+        }
       }
-      const int c0 = p0 + nb;
+      const int c0 = p0 + nbo;
       if (c0 >= w) {
         __syncthreads();
         break;
       }
-      // unit lower panel block into LDS
-      for (int e = tid; e < nb * nb; e += BLOCK) {
-        const int i = e / nb, k = e % nb;
-        s_L11[i * NB + k] = A[(int64_t)(p0 + i) * w + p0 + k];
-      }
-      __syncthreads();
-      // ---------------- block row: U12 = L11^{-1} A12 (one column per thread)
-      for (int col = c0 + tid; col < w; col += BLOCK) {
-        T x[NB];
-#pragma unroll
-        for (int i = 0; i < NB; ++i) x[i] = (i < nb) ? A[(int64_t)(p0 + i) * w + col] : T(0);
-#pragma unroll
-        for (int i = 1; i < NB; ++i) {
-          T acc = x[i];
-#pragma unroll
-          for (int k = 0; k < i; ++k) acc -= s_L11[i * NB + k] * x[k];
-          x[i] = acc;
+      // ===================== the block's interchanges on the columns right of it
+      permute_rows<T>(A, w, p0, nbo, s_piv, c0, w, 0, 0, pool, s_mv, &s_nm);
+      // ===================== U12 = L11^{-1} A12: explicit inverse of the unit lower
+      // block (one column per thread, in LDS), then a triangular product on the
+      // matrix cores in 16-column strips per wave (zero blocks of the inverse skipped)
+      {
+        constexpr int LDL = NBO + 1;
+        T* L11 = pool;
+        T* Linv = pool + NBO * LDL;
+        for (int e = tid; e < nbo * nbo; e += BLOCK) {
+          const int i = e / nbo, k = e % nbo;
+          L11[i * LDL + k] = A[(int64_t)(p0 + i) * w + p0 + k];
         }
-#pragma unroll
-        for (int i = 0; i < NB; ++i)
-          if (i < nb) A[(int64_t)(p0 + i) * w + col] = x[i];
-      }
-      __syncthreads();
-      // ---------------- trailing update A22 -= L21 U12 on the matrix cores
-      const int m2 = w - c0;
-      const int tiles = (m2 + 15) / 16;
-      const int li = lane & 15, lk = lane >> 4;
-      for (int st = wave; st < tiles; st += NW) {
-        const int rb = c0 + st * 16;
-        T a[NB / 4];
-#pragma unroll
-        for (int kk = 0; kk < NB / 4; ++kk) {
-          const int k = kk * 4 + lk;
-          const int r = rb + li;
-          a[kk] = (r < w && k < nb) ? -A[(int64_t)r * w + p0 + k] : T(0);
-        }
-        for (int ct = 0; ct < tiles; ++ct) {
-          const int cb = c0 + ct * 16;
-          const int col = cb + li;
-          v4 acc;
-#pragma unroll
-          for (int rr = 0; rr < 4; ++rr) {
-            const int r = rb + Mfma<T>::row(lk, rr);
-            acc[rr] = (r < w && col < w) ? A[(int64_t)r * w + col] : T(0);
-          }
-#pragma unroll
-          for (int kk = 0; kk < NB / 4; ++kk) {
-            const int k = kk * 4 + lk;
-            const T b = (k < nb && col < w) ? A[(int64_t)(p0 + k) * w + col] : T(0);
-            acc = Mfma<T>::op(a[kk], b, acc);
-          }
-#pragma unroll
-          for (int rr = 0; rr < 4; ++rr) {
-            const int r = rb + Mfma<T>::row(lk, rr);
-            if (r < w && col < w) A[(int64_t)r * w + col] = acc[rr];
+        __syncthreads();
+        for (int j = tid; j < NBO; j += BLOCK) {
+          for (int i = 0; i < NBO; ++i) {
+            T x = T(0);
+            if (i == j) x = T(1);
+            else if (i > j && i < nbo)
+              for (int k = j; k < i; ++k) x -= L11[i * LDL + k] * Linv[k * LDL + j];
+            Linv[i * LDL + j] = x;
           }
         }
+        __syncthreads();
+        typedef typename Mfma<T>::v4 v4;
+        const int li = lane & 15, lk = lane >> 4;
+        const int n2 = w - c0;
+        // this wave's NBO x 16 strip: in the (now free) L11 area when all strips fit there,
+        // otherwise after the inverse (the pool is sized for either case)
+        constexpr bool kStripsInL11 = NW * NBO * 16 <= NBO * LDL;
+        T* Sb = (kStripsInL11 ? L11 : Linv + NBO * LDL) + wave * NBO * 16;
+        for (int st = wave; st * 16 < n2; st += NW) {
+          const int cs = c0 + st * 16;
+          for (int e = lane; e < NBO * 16; e += 64) {
+            const int k = e >> 4, j = e & 15;
+            Sb[e] = (k < nbo && cs + j < w) ? A[(int64_t)(p0 + k) * w + cs + j] : T(0);
+          }
+          __builtin_amdgcn_wave_barrier();
+          const int col = cs + li;
+#pragma unroll 1
+          for (int it = 0; it * 16 < nbo; ++it) {
+            v4 acc = {T(0), T(0), T(0), T(0)};
+            const T* Lrow = Linv + (16 * it + li) * LDL + lk;
+            const T* Bcol = Sb + lk * 16 + li;
+            const int kend = 4 * it + 4;  // the inverse is lower triangular
+            for (int kk = 0; kk < kend; ++kk) acc = Mfma<T>::op(Lrow[4 * kk], Bcol[kk * 64], acc);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              const int row = 16 * it + Mfma<T>::row(lk, r);
+              if (row < nbo && col < w) A[(int64_t)(p0 + row) * w + col] = acc[r];
+            }
+          }
+          __builtin_amdgcn_wave_barrier();
+        }
+        __syncthreads();
       }
-      __syncthreads();
+      // ===================== trailing update A22 -= L21 U12 with K = nbo
+      tile_update<T>(A, w, c0, w, c0, w, p0, nbo, pool);
     }
-    // row i of P A is row P[i] of A
-    for (int i = tid; i < w; i += BLOCK) P[i] = s_perm[i];
     if (tid == 0 && zero_piv) plan.info[q] = zero_piv;
   }
 }
@@ -278,7 +582,10 @@ __global__ __launch_bounds__(kSolveThreads) void lu_solve_kernel(int32_t n_q, Pl
                                                                  int accumulate, const int32_t* __restrict__ active) {
   extern __shared__ __align__(16) double y[];
   __shared__ double dblk[kSolveBS][kSolveBS + 1];
+  __shared__ int32_t spiv[LuCfg<T>::NBO];
   constexpr int NW = kSolveThreads / 64;
+  constexpr int NBO = LuCfg<T>::NBO;
+  static_assert(NBO % kSolveBS == 0, "solve blocks must tile the factorisation blocks");
   const int32_t q = blockIdx.x;
   if (plan.info[q] != 0) return;
   if (active && !active[q]) return;
@@ -288,11 +595,27 @@ __global__ __launch_bounds__(kSolveThreads) void lu_solve_kernel(int32_t n_q, Pl
   const T* A = mats + plan.mat_off[q];
   const int32_t* P = piv + off;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  for (int c = tid; c < w; c += kSolveThreads) y[c] = b[off + P[c]];
+  for (int c = tid; c < w; c += kSolveThreads) y[c] = b[off + c];
   __syncthreads();
-  // forward substitution, unit lower triangular
+  // forward substitution, unit lower triangular, each outer block's interchanges first
   for (int b0 = 0; b0 < w; b0 += kSolveBS) {
     const int nbk = min(kSolveBS, w - b0);
+    if (b0 % NBO == 0) {
+      const int nblk = min(NBO, w - b0);
+      for (int i = tid; i < nblk; i += kSolveThreads) spiv[i] = P[b0 + i];
+      __syncthreads();
+      if (tid == 0) {
+        for (int i = 0; i < nblk; ++i) {
+          const int p = spiv[i];
+          if (p != b0 + i) {
+            const double t = y[b0 + i];
+            y[b0 + i] = y[p];
+            y[p] = t;
+          }
+        }
+      }
+      __syncthreads();
+    }
     for (int e = tid; e < nbk * kSolveBS; e += kSolveThreads) {
       const int i = e / kSolveBS, k = e % kSolveBS;
       dblk[i][k] = (k < nbk) ? (double)A[(int64_t)(b0 + i) * w + b0 + k] : 0.0;
@@ -309,8 +632,7 @@ __global__ __launch_bounds__(kSolveThreads) void lu_solve_kernel(int32_t n_q, Pl
     __syncthreads();
     const double yl = lane < nbk ? y[b0 + lane] : 0.0;
     for (int r = b0 + nbk + wave; r < w; r += NW) {
-      double s = lane < nbk ? (double)A[(int64_t)r * w + b0 + lane] * yl : 0.0;
-      for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+      const double s = __ockl_wfred_add_f64(lane < nbk ? (double)A[(int64_t)r * w + b0 + lane] * yl : 0.0);
       if (lane == 0) y[r] -= s;
     }
     __syncthreads();
@@ -336,8 +658,7 @@ __global__ __launch_bounds__(kSolveThreads) void lu_solve_kernel(int32_t n_q, Pl
     __syncthreads();
     const double yl = lane < nbk ? y[b0 + lane] : 0.0;
     for (int r = wave; r < b0; r += NW) {
-      double s = lane < nbk ? (double)A[(int64_t)r * w + b0 + lane] * yl : 0.0;
-      for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+      const double s = __ockl_wfred_add_f64(lane < nbk ? (double)A[(int64_t)r * w + b0 + lane] * yl : 0.0);
       if (lane == 0) y[r] -= s;
     }
     __syncthreads();
@@ -359,10 +680,14 @@ int device_cus() {
   return cus;
 }
 
-template <typename T, int NB, int BLOCK, int R>
-hipError_t lu_go(int32_t n_q, Plan plan, void* mats, int32_t* piv, int per_cu, hipStream_t s) {
-  const int grid = max(1, min(n_q, device_cus() * per_cu));
-  hipLaunchKernelGGL((lu_kernel<T, NB, BLOCK, R>), dim3(grid), dim3(BLOCK), 0, s, n_q, plan, (T*)mats, piv);
+template <typename T, int R, int NBI>
+hipError_t lu_go(int32_t n_q, Plan plan, void* mats, int32_t* piv, hipStream_t s) {
+  const size_t lds = sizeof(T) * lu_pool_elems<T>();
+  hipError_t e = hipFuncSetAttribute((const void*)lu_kernel<T, R, NBI>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)lds);
+  if (e != hipSuccess) return e;
+  const int grid = max(1, min(n_q, device_cus()));
+  hipLaunchKernelGGL((lu_kernel<T, R, NBI>), dim3(grid), dim3(kLuThreads), lds, s, n_q, plan, (T*)mats, piv);
   return hipGetLastError();
 }
 
@@ -370,13 +695,13 @@ hipError_t lu_go(int32_t n_q, Plan plan, void* mats, int32_t* piv, int per_cu, h
 
 hipError_t launch_lu(int32_t n_q, Plan plan, int32_t prec, void* mats, int32_t* piv, int32_t n_max, hipStream_t s) {
   if (n_q == 0) return hipSuccess;
-  if (n_max <= 1280) {
-    if (prec == ST_F64) return lu_go<double, 16, 256, 5>(n_q, plan, mats, piv, 2, s);
-    return lu_go<float, 32, 256, 5>(n_q, plan, mats, piv, 2, s);
+  if (n_max <= 3 * kLuThreads) {
+    if (prec == ST_F64) return lu_go<double, 3, 16>(n_q, plan, mats, piv, s);
+    return lu_go<float, 3, 32>(n_q, plan, mats, piv, s);
   }
-  if (n_max <= 4096) {
-    if (prec == ST_F64) return lu_go<double, 16, 1024, 4>(n_q, plan, mats, piv, 1, s);
-    return lu_go<float, 16, 1024, 4>(n_q, plan, mats, piv, 1, s);
+  if (n_max <= 8 * kLuThreads) {
+    if (prec == ST_F64) return lu_go<double, 8, 8>(n_q, plan, mats, piv, s);
+    return lu_go<float, 8, 16>(n_q, plan, mats, piv, s);
   }
   return hipErrorInvalidValue;
 }

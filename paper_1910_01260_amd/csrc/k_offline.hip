@@ -9,6 +9,9 @@
 //     the first-step values P1.
 #include "internal.h"
 
+// wavefront sum of the device library (DPP based, all lanes active)
+extern "C" __device__ double __ockl_wfred_add_f64(double);
+
 namespace strom {
 namespace {
 
@@ -182,7 +185,7 @@ __global__ __launch_bounds__(256) void temporal_vec_kernel(const double* __restr
   for (int qf = 0; qf < Qf; ++qf) {
     double s = 0.0;
     for (int k = lane; k < N_t; k += 64) s = fma(dt[k] * (g ? g[k + (int64_t)qf * N_t] : 1.0), col[k], s);
-    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+    s = __ockl_wfred_add_f64(s);
     if (lane == 0) Wf[(int64_t)qf * n + a] = s;
   }
 }

@@ -19,6 +19,11 @@ namespace {
 
 constexpr int kOneWG = 1024;
 
+// wavefront reductions of the device library (DPP based, all lanes active)
+extern "C" __device__ double __ockl_wfred_add_f64(double);
+extern "C" __device__ double __ockl_wfred_max_f64(double);
+extern "C" __device__ int __ockl_wfred_min_i32(int);
+
 __device__ inline uint64_t mix64(uint64_t z) {
   // splitmix64 finaliser (Steele, Lea, Flood)
   z += 0x9E3779B97F4A7C15ULL;
@@ -36,7 +41,7 @@ template <typename T>
 __device__ inline T block_sum(T v, T* red) {
   // red: LDS of blockDim.x/64 entries; returns the sum to every thread
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  v = __ockl_wfred_add_f64(v);
   __syncthreads();
   if (lane == 0) red[wave] = v;
   __syncthreads();
@@ -47,7 +52,7 @@ __device__ inline T block_sum(T v, T* red) {
 
 __device__ inline double block_max(double v, double* red) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+  v = __ockl_wfred_max_f64(v);
   __syncthreads();
   if (lane == 0) red[wave] = v;
   __syncthreads();
@@ -58,7 +63,7 @@ __device__ inline double block_max(double v, double* red) {
 
 __device__ inline int block_min_i(int v, int* red) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o));
+  v = __ockl_wfred_min_i32(v);
   __syncthreads();
   if (lane == 0) red[wave] = v;
   __syncthreads();
@@ -280,7 +285,7 @@ __global__ __launch_bounds__(kOneWG) void orth_cgs2_kernel(double* X, int64_t p,
           const double* xl = X + (int64_t)l * p;
           double s = 0.0;
           for (int64_t r = lane; r < p; r += 64) s = fma(xl[r], xj[r], s);
-          for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+          s = __ockl_wfred_add_f64(s);
           if (lane == 0) coef[l] = s;
         }
         __syncthreads();
@@ -532,11 +537,9 @@ __global__ __launch_bounds__(256) void temporal_svd_kernel(const double* __restr
           be = fma(yb[k], yb[k], be);
           ga = fma(ya[k], yb[k], ga);
         }
-        for (int o = 32; o > 0; o >>= 1) {
-          al += __shfl_xor(al, o);
-          be += __shfl_xor(be, o);
-          ga += __shfl_xor(ga, o);
-        }
+        al = __ockl_wfred_add_f64(al);
+        be = __ockl_wfred_add_f64(be);
+        ga = __ockl_wfred_add_f64(ga);
         if (fabs(ga) > 1e-15 * sqrt(al * be) && fabs(ga) > 0.0) {
           const double ze = (be - al) / (2.0 * ga);
           const double tt = (ze >= 0.0 ? 1.0 : -1.0) / (fabs(ze) + sqrt(1.0 + ze * ze));
@@ -558,7 +561,7 @@ __global__ __launch_bounds__(256) void temporal_svd_kernel(const double* __restr
   for (int q = wave; q < n_mu; q += 4) {
     double s = 0.0;
     for (int k = lane; k < N_t; k += 64) s = fma(Ys[(int64_t)q * N_t + k], Ys[(int64_t)q * N_t + k], s);
-    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+    s = __ockl_wfred_add_f64(s);
     if (lane == 0) nrm[q] = sqrt(s);
   }
   __syncthreads();
@@ -598,7 +601,7 @@ __global__ __launch_bounds__(256) void temporal_svd_kernel(const double* __restr
       for (int l = wave; l < have; l += 4) {
         double s = 0.0;
         for (int k = lane; k < N_t; k += 64) s = fma(out[(int64_t)l * N_t + k], cand[k], s);
-        for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+        s = __ockl_wfred_add_f64(s);
         if (lane == 0) s_coef[l] = s;
       }
       __syncthreads();

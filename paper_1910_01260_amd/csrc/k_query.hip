@@ -17,6 +17,9 @@ constexpr int kFormThreads = 256;
 
 __device__ inline bool finite_d(double v) { return v == v && v - v == 0.0; }
 
+// wavefront sum of the device library (DPP based, all lanes active)
+extern "C" __device__ double __ockl_wfred_add_f64(double);
+
 // One workgroup.  Writes width, info, coeff_off, mat_off, order, and zeroes the counters.
 __global__ __launch_bounds__(kPlanThreads) void plan_kernel(int32_t n_q, int32_t n_s, const int32_t* __restrict__ moff,
                                                             const int32_t* __restrict__ nt_q,
@@ -238,7 +241,7 @@ __global__ __launch_bounds__(kFormThreads) void residual_kernel(RomView rom, int
       if (ic == ir) v += Kr[(int64_t)(gc - rom.moff[ic]) * ntr];
       acc = fma(v, xs[c], acc);
     }
-    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+    acc = __ockl_wfred_add_f64(acc);
     if (lane == 0) r[off + row] = rhs[off + row] - acc;
   }
 }
