@@ -40,6 +40,7 @@
  *           query's coefficients are set to NaN
  *       -1  iterative refinement did not reach ir_tol in ir_max steps (the
  *           last iterate is returned)
+ *       -2  not solved: skipped on request (st_solve's skip mask)
  *       -3  the query did not fit in the coefficient or workspace capacity
  *       -4  invalid per-query temporal profile (nt_q out of range)
  *       -5  non-finite parameter coefficient
@@ -253,6 +254,10 @@ st_status st_form(const st_rom_desc* d, const void* rom, int32_t n_q, const doub
  * The final relative residual ||b - Ahat_st x|| / ||b|| (FP64) is written
  * to relres in both cases.
  *
+ * skip     [dev] n_q int32 or NULL: a query with skip[q] != 0 is not solved
+ *          (info = -2); it keeps its place in coeff (whatever the caller put
+ *          there, e.g. certified surrogate coefficients) and its relres entry,
+ *          and takes no matrix workspace.
  * coeff    [dev] coeff_cap doubles: query q's solution at coeff_off[q].
  * coeff_off [dev] n_q + 1 int64 outputs.
  * relres   [dev] n_q doubles; info [dev] n_q int32; iters [dev] n_q int32
@@ -265,9 +270,57 @@ st_status st_form(const st_rom_desc* d, const void* rom, int32_t n_q, const doub
 size_t st_solve_workspace(const st_rom_desc* d, int32_t n_q, int64_t sum_w, int64_t sum_w2, int32_t lu_prec);
 
 st_status st_solve(const st_rom_desc* d, const void* rom, int32_t n_q, const double* theta_A,
-                   const double* theta_f, const double* theta_0, const int32_t* nt_q, int32_t lu_prec,
-                   double ir_tol, int32_t ir_max, double* coeff, int64_t coeff_cap, int64_t* coeff_off,
-                   double* relres, int32_t* info, int32_t* iters, void* ws, size_t ws_bytes, void* stream);
+                   const double* theta_f, const double* theta_0, const int32_t* nt_q, const int32_t* skip,
+                   int32_t lu_prec, double ir_tol, int32_t ir_max, double* coeff, int64_t coeff_cap,
+                   int64_t* coeff_off, double* relres, int32_t* info, int32_t* iters, void* ws, size_t ws_bytes,
+                   void* stream);
+
+/* ========================================================================
+ * Surrogate network (not part of the paper).  A multilayer perceptron maps a
+ * (scaled) parameter vector to standardized reduced space-time coefficients:
+ * x (d_in) -> [Linear + GELU] x n_hidden -> Linear -> y (d_out), GELU in its
+ * erf form.  Products run on the matrix cores in BF16 with FP32 accumulation;
+ * parameters, gradients and Adam moments are FP32.  Samples are rows of
+ * row-major [dev] arrays.  Parameters are one flat array: for each layer l,
+ * W_l (out_l x in_l, row-major) then b_l (out_l).
+ * ====================================================================== */
+typedef struct {
+  int32_t d_in, width, n_hidden, d_out;
+} st_mlp_shape;
+
+int64_t st_mlp_param_count(const st_mlp_shape* s);
+size_t st_mlp_workspace(const st_mlp_shape* s, int32_t batch);
+
+/* Y (batch x d_out) = network(X (batch x d_in)). */
+st_status st_mlp_forward(const st_mlp_shape* s, const float* params, int32_t batch, const float* X, float* Y,
+                         void* ws, size_t ws_bytes, void* stream);
+
+/* Mean squared error of network(X) against T (batch x d_out), averaged over all
+ * outputs, written to *loss [dev]; its gradient with respect to every
+ * parameter written to grads [dev] (same layout as params). */
+st_status st_mlp_grad(const st_mlp_shape* s, const float* params, int32_t batch, const float* X, const float* T,
+                      float* grads, float* loss, void* ws, size_t ws_bytes, void* stream);
+
+/* One Adam step (bias-corrected, step number `step` >= 1) on n parameters. */
+st_status st_mlp_adam(int64_t n, float* params, const float* grads, float* m, float* v, int32_t step, float lr,
+                      float beta1, float beta2, float eps, void* stream);
+
+/* Residual certificate of surrogate coefficients for full-width queries:
+ * c = mean + scale * y (FP64; y = row q of Y, n outputs), r = b(mu) -
+ * Ahat_st(mu) c in FP64 from the ROM pieces (Sec. 5.2, Eq. (stresidual) in
+ * reduced form), cert = e / (1 - e) with e = ||r||_2 / (gamma ||c||_2) (inf if
+ * e >= 1).  When gamma lower-bounds lambda_min(sym Ahat_st(mu)) - e.g.
+ * 1 - cos(pi / (N_t + 1)) whenever sym(A(mu)) <= 0 - cert bounds the relative
+ * error of c against the exact reduced solution.  accept[q] = cert <= tol.
+ * coeff [dev] n_q * n doubles, packed as st_solve packs the same full-width
+ * queries (query q at q * n when every query is valid; a query with a
+ * non-finite parameter coefficient takes no space and is never accepted),
+ * cert [dev] n_q, accept [dev] n_q. */
+size_t st_surrogate_check_workspace(const st_rom_desc* d, int32_t n_q);
+st_status st_surrogate_check(const st_rom_desc* d, const void* rom, int32_t n_q, const double* theta_A,
+                             const double* theta_f, const double* theta_0, const float* Y, const double* mean,
+                             const double* scale, double gamma, double tol, double* coeff, double* cert,
+                             int32_t* accept, void* ws, size_t ws_bytes, void* stream);
 
 /* ========================================================================
  * Phase timing (measurement tools).  After st_timing_enable(1), every st_solve

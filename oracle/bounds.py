@@ -52,3 +52,28 @@ def theorem3_bound(A_st, f_st, u0_st, u_st_approx, N):
     inv_norm = 1.0 / np.linalg.svd(A_st, compute_uv=False)[-1]
     r = A_st @ u_st_approx - f_st - u0_st
     return np.sqrt(Nt) * inv_norm * st_inf_norm(r, N)
+
+
+def coercivity_floor(N_t):
+    """Lower bound of lambda_min(sym Ahat_st) when sym(A) <= 0.
+
+    The backward-Euler space-time matrix of Sec. 2 has blocks I - dt_k A on
+    the diagonal and -I below it.  With sym(A) <= 0 its symmetric part
+    dominates the tridiagonal Toeplitz matrix (1 on the diagonal, -1/2 beside
+    it) Kronecker I, whose smallest eigenvalue is 1 - cos(pi / (N_t + 1)); the
+    Galerkin projection with orthonormal Phi_st (Sec. 3.2) keeps the bound."""
+    return 1.0 - np.cos(np.pi / (N_t + 1))
+
+
+def certificate(M, rhs, c, gamma):
+    """Relative error certificate of an approximate reduced solution c.
+
+    Coercivity gives ||c - c*|| <= ||rhs - M c|| / gamma =: delta, and so
+    ||c - c*|| / ||c*|| <= e / (1 - e) with e = delta / ||c|| (infinite when
+    e >= 1 or c = 0).  The residual is that of the reduced system Eq. (st-galerkin)."""
+    r = rhs - M @ c
+    cn = np.linalg.norm(c)
+    if cn == 0.0:
+        return np.inf
+    e = np.linalg.norm(r) / (gamma * cn)
+    return e / (1.0 - e) if e < 1.0 else np.inf

@@ -224,8 +224,8 @@ st_status st_form(const st_rom_desc* d, const void* rom, int32_t n_q, const doub
   plan.mat_off = mat_off;
   plan.coeff_off = coeff_off;
   plan.info = info;
-  ST_TRY(launch_plan(n_q, d->n_s, rv.moff, nt_q, theta_A, theta_f, theta_0, d->Q, d->Qf, d->Q0, coeff_cap, mats_cap,
-                     plan, s));
+  ST_TRY(launch_plan(n_q, d->n_s, rv.moff, nt_q, nullptr, theta_A, theta_f, theta_0, d->Q, d->Qf, d->Q0, coeff_cap,
+                     mats_cap, plan, s));
   ST_TRY(launch_form(rv, n_q, theta_A, theta_f, theta_0, nt_q, plan, out_prec, mats, rhs, (int32_t)n, s));
   return ST_OK;
 }
@@ -285,7 +285,8 @@ size_t st_solve_workspace(const st_rom_desc* d, int32_t n_q, int64_t sum_w, int6
 }
 
 st_status st_solve(const st_rom_desc* d, const void* rom, int32_t n_q, const double* theta_A, const double* theta_f,
-                   const double* theta_0, const int32_t* nt_q, int32_t lu_prec, double ir_tol, int32_t ir_max,
+                   const double* theta_0, const int32_t* nt_q, const int32_t* skip, int32_t lu_prec, double ir_tol,
+                   int32_t ir_max,
                    double* coeff, int64_t coeff_cap, int64_t* coeff_off, double* relres, int32_t* info,
                    int32_t* iters, void* ws, size_t ws_bytes, void* stream) {
   if (!query_args_ok(d, rom, n_q, theta_A, theta_f, theta_0)) return ST_EINVAL;
@@ -321,8 +322,8 @@ st_status st_solve(const st_rom_desc* d, const void* rom, int32_t n_q, const dou
   const int32_t n_max = (int32_t)n;
 
   ST_TRY(mark(0, s));
-  ST_TRY(launch_plan(n_q, d->n_s, rv.moff, nt_q, theta_A, theta_f, theta_0, d->Q, d->Qf, d->Q0, coeff_cap, mats_cap,
-                     plan, s));
+  ST_TRY(launch_plan(n_q, d->n_s, rv.moff, nt_q, skip, theta_A, theta_f, theta_0, d->Q, d->Qf, d->Q0, coeff_cap,
+                     mats_cap, plan, s));
   ST_TRY(mark(1, s));
   ST_TRY(launch_form(rv, n_q, theta_A, theta_f, theta_0, nt_q, plan, lu_prec, mats, b, n_max, s));
   ST_TRY(mark(2, s));
@@ -510,6 +511,133 @@ st_status st_build_bases(const void* U, int32_t U_prec, int64_t ldU, int64_t N_s
   for (int i = 0; i < ns; ++i) mt.nt[i] = n_t[i];
   ST_TRY(launch_mode_offsets(mt, w.moff, s));
   ST_TRY(launch_temporal_svd(w.V, d.m, N_t, n_mu, ns, w.moff, tau_t, Phi_t, rank_t, s));
+  return ST_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// surrogate network and residual certificate
+// ---------------------------------------------------------------------------
+namespace {
+bool mlp_ok(const st_mlp_shape* s) {
+  return s && s->d_in >= 1 && s->width >= 1 && s->n_hidden >= 1 && s->n_hidden <= 62 && s->d_out >= 1 &&
+         s->d_in <= 65536 && s->width <= 65536 && s->d_out <= 65536;
+}
+
+struct MlpWs {
+  float *acts, *dY, *tmp0, *tmp1, *partial;
+  size_t total;
+};
+
+MlpWs mlp_ws(const st_mlp_shape& s, int32_t batch, void* base) {
+  Carver c(base);
+  MlpWs w;
+  w.acts = c.take<float>(mlp_act_elems(s, batch));
+  w.dY = c.take<float>((size_t)batch * s.d_out);
+  w.tmp0 = c.take<float>((size_t)batch * s.width);
+  w.tmp1 = c.take<float>((size_t)batch * s.width);
+  w.partial = c.take<float>(mlp_mse_partials((int64_t)batch * s.d_out) + 1);
+  w.total = c.used;
+  return w;
+}
+}  // namespace
+
+extern "C" {
+
+int64_t st_mlp_param_count(const st_mlp_shape* s) {
+  if (!mlp_ok(s)) return -1;
+  return (int64_t)mlp_param_offset(*s, mlp_layers(*s));
+}
+
+size_t st_mlp_workspace(const st_mlp_shape* s, int32_t batch) {
+  if (!mlp_ok(s) || batch < 0) return 0;
+  return mlp_ws(*s, batch, nullptr).total;
+}
+
+st_status st_mlp_forward(const st_mlp_shape* s, const float* params, int32_t batch, const float* X, float* Y,
+                         void* ws, size_t ws_bytes, void* stream) {
+  if (!mlp_ok(s) || batch < 0) return ST_EINVAL;
+  if (batch == 0) return ST_OK;
+  if (!params || !X || !Y || !ws) return ST_EINVAL;
+  if (ws_bytes < st_mlp_workspace(s, batch)) return ST_EWORKSPACE;
+  MlpWs w = mlp_ws(*s, batch, ws);
+  ST_TRY(mlp_forward(*s, params, batch, X, w.acts, Y, static_cast<hipStream_t>(stream)));
+  return ST_OK;
+}
+
+st_status st_mlp_grad(const st_mlp_shape* s, const float* params, int32_t batch, const float* X, const float* T,
+                      float* grads, float* loss, void* ws, size_t ws_bytes, void* stream) {
+  if (!mlp_ok(s) || batch < 1 || !params || !X || !T || !grads || !loss || !ws) return ST_EINVAL;
+  if (ws_bytes < st_mlp_workspace(s, batch)) return ST_EWORKSPACE;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  MlpWs w = mlp_ws(*s, batch, ws);
+  // forward into a scratch output (the last layer's Z slot of the activations)
+  float* Y = w.acts + mlp_act_elems(*s, batch) - 2 * (size_t)batch * s->d_out;
+  ST_TRY(mlp_forward(*s, params, batch, X, w.acts, Y, st));
+  ST_TRY(mlp_mse((int64_t)batch * s->d_out, Y, T, w.dY, w.partial, loss, st));
+  ST_TRY(mlp_backward(*s, params, batch, X, w.acts, w.dY, grads, w.tmp0, w.tmp1, st));
+  return ST_OK;
+}
+
+st_status st_mlp_adam(int64_t n, float* params, const float* grads, float* m, float* v, int32_t step, float lr,
+                      float beta1, float beta2, float eps, void* stream) {
+  if (n < 0 || step < 1 || !(lr >= 0.f) || !(beta1 >= 0.f && beta1 < 1.f) || !(beta2 >= 0.f && beta2 < 1.f) ||
+      !(eps > 0.f))
+    return ST_EINVAL;
+  if (n == 0) return ST_OK;
+  if (!params || !grads || !m || !v) return ST_EINVAL;
+  ST_TRY(adam(n, params, grads, m, v, step, lr, beta1, beta2, eps, static_cast<hipStream_t>(stream)));
+  return ST_OK;
+}
+
+size_t st_surrogate_check_workspace(const st_rom_desc* d, int32_t n_q) {
+  if (!desc_ok(d) || n_q < 0) return 0;
+  const size_t n = (size_t)total_nt(d);
+  size_t o = plan_bytes(n_q);
+  o = align_up(o + sizeof(int64_t) * (n_q + 1));  // coeff offsets
+  o = align_up(o + sizeof(int64_t) * (n_q + 1));  // matrix offsets (unused)
+  o = align_up(o + sizeof(int32_t) * n_q);        // info
+  o = align_up(o + sizeof(double) * n_q);         // ||r||
+  o = align_up(o + sizeof(double) * n_q);         // ||c||
+  o = align_up(o + sizeof(double) * n_q * n);     // b
+  o = align_up(o + sizeof(double) * n_q * n);     // r
+  return o;
+}
+
+st_status st_surrogate_check(const st_rom_desc* d, const void* rom, int32_t n_q, const double* theta_A,
+                             const double* theta_f, const double* theta_0, const float* Y, const double* mean,
+                             const double* scale, double gamma, double tol, double* coeff, double* cert,
+                             int32_t* accept, void* ws, size_t ws_bytes, void* stream) {
+  if (!query_args_ok(d, rom, n_q, theta_A, theta_f, theta_0)) return ST_EINVAL;
+  if (!(gamma > 0.0) || !(tol >= 0.0)) return ST_EINVAL;
+  if (d->n_s > kMaxFormModes) return ST_EUNSUPPORTED;
+  if (n_q == 0) return ST_OK;
+  if (!Y || !mean || !scale || !coeff || !cert || !accept || !ws) return ST_EINVAL;
+  const int64_t n = total_nt(d);
+  if (n > kMaxWidth) return ST_EUNSUPPORTED;
+  if (ws_bytes < st_surrogate_check_workspace(d, n_q)) return ST_EWORKSPACE;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  RomView rv = view_of(d, rom);
+  Carver c(ws);
+  Plan plan;
+  plan.width = c.take<int32_t>(n_q);
+  plan.order = c.take<int32_t>(n_q);
+  plan.counter = c.take<int32_t>(4);
+  plan.coeff_off = c.take<int64_t>(n_q + 1);
+  plan.mat_off = c.take<int64_t>(n_q + 1);
+  plan.info = c.take<int32_t>(n_q);
+  double* rnorm = c.take<double>(n_q);
+  double* cnorm = c.take<double>(n_q);
+  double* b = c.take<double>((size_t)n_q * n);
+  double* r = c.take<double>((size_t)n_q * n);
+  ST_TRY(launch_plan(n_q, d->n_s, rv.moff, nullptr, nullptr, theta_A, theta_f, theta_0, d->Q, d->Qf, d->Q0,
+                     (int64_t)n_q * n, (int64_t)1 << 62, plan, s));
+  ST_TRY(launch_destandardize(n_q, (int32_t)n, Y, mean, scale, plan, coeff, s));
+  ST_TRY(launch_rhs(rv, n_q, theta_f, theta_0, nullptr, plan, b, (int32_t)n, s));
+  ST_TRY(launch_residual(rv, n_q, theta_A, nullptr, plan, b, coeff, r, rnorm, nullptr, (int32_t)n, s));
+  ST_TRY(launch_vec_norms(n_q, plan, coeff, cnorm, s));
+  ST_TRY(launch_certificate(n_q, plan, rnorm, cnorm, gamma, tol, cert, accept, s));
   return ST_OK;
 }
 

@@ -94,9 +94,15 @@ hipError_t launch_temporal_svd(const double* V, int64_t ldV, int N_t, int n_mu, 
                                double tau_t, double* Phi_t, int32_t* rank_out, hipStream_t s);
 
 // k_query.hip: plan (per-query offsets), assembly (a7), residual
-hipError_t launch_plan(int32_t n_q, int32_t n_s, const int32_t* full_nt_dev, const int32_t* nt_q, const double* thA,
-                       const double* thf, const double* th0, int32_t Q, int32_t Qf, int32_t Q0, int64_t coeff_cap,
-                       int64_t mat_cap, Plan plan, hipStream_t s);
+hipError_t launch_plan(int32_t n_q, int32_t n_s, const int32_t* full_nt_dev, const int32_t* nt_q, const int32_t* skip,
+                       const double* thA, const double* thf, const double* th0, int32_t Q, int32_t Qf, int32_t Q0,
+                       int64_t coeff_cap, int64_t mat_cap, Plan plan, hipStream_t s);
+hipError_t launch_rhs(const RomView& rom, int32_t n_q, const double* thf, const double* th0, const int32_t* nt_q,
+                      Plan plan, double* rhs, int32_t n_max, hipStream_t s);
+hipError_t launch_destandardize(int32_t n_q, int32_t n, const float* Y, const double* mean, const double* scale,
+                                Plan plan, double* coeff, hipStream_t s);
+hipError_t launch_certificate(int32_t n_q, Plan plan, const double* rnorm, const double* cnorm, double gamma, double tol,
+                              double* cert, int32_t* accept, hipStream_t s);
 hipError_t launch_form(const RomView& rom, int32_t n_q, const double* thA, const double* thf, const double* th0,
                        const int32_t* nt_q, Plan plan, int32_t out_prec, void* mats, double* rhs, int32_t n_max,
                        hipStream_t s);
@@ -115,5 +121,20 @@ hipError_t launch_ir_check(int32_t n_q, Plan plan, const double* rnorm, const do
 hipError_t launch_vec_norms(int32_t n_q, Plan plan, const double* v, double* norms, hipStream_t s);
 hipError_t launch_finalize(int32_t n_q, Plan plan, double* coeff, int32_t* info_out, hipStream_t s);
 hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
+
+// k_mlp.hip: surrogate network
+int mlp_layers(const st_mlp_shape& s);
+int mlp_in(const st_mlp_shape& s, int l);
+int mlp_out(const st_mlp_shape& s, int l);
+size_t mlp_param_offset(const st_mlp_shape& s, int l);
+size_t mlp_act_elems(const st_mlp_shape& s, int32_t batch);
+size_t mlp_mse_partials(int64_t n);
+hipError_t mlp_forward(const st_mlp_shape& s, const float* params, int32_t batch, const float* X, float* acts,
+                       float* Y, hipStream_t st);
+hipError_t mlp_backward(const st_mlp_shape& s, const float* params, int32_t batch, const float* X, const float* acts,
+                        float* dY, float* grads, float* tmp0, float* tmp1, hipStream_t st);
+hipError_t mlp_mse(int64_t n, const float* Y, const float* T, float* dY, float* partial, float* loss, hipStream_t st);
+hipError_t adam(int64_t n, float* p, const float* g, float* m, float* v, int32_t t, float lr, float b1, float b2,
+                float eps, hipStream_t st);
 
 }  // namespace strom

@@ -23,6 +23,7 @@ extern "C" __device__ double __ockl_wfred_add_f64(double);
 // One workgroup.  Writes width, info, coeff_off, mat_off, order, and zeroes the counters.
 __global__ __launch_bounds__(kPlanThreads) void plan_kernel(int32_t n_q, int32_t n_s, const int32_t* __restrict__ moff,
                                                             const int32_t* __restrict__ nt_q,
+                                                            const int32_t* __restrict__ skip,
                                                             const double* __restrict__ thA,
                                                             const double* __restrict__ thf,
                                                             const double* __restrict__ th0, int32_t Q, int32_t Qf,
@@ -45,8 +46,9 @@ __global__ __launch_bounds__(kPlanThreads) void plan_kernel(int32_t n_q, int32_t
     for (int k = 0; k < Qf; ++k) if (!finite_d(thf[(int64_t)q * Qf + k])) code = code ? code : -5;
     for (int k = 0; k < Q0; ++k) if (!finite_d(th0[(int64_t)q * Q0 + k])) code = code ? code : -5;
     if (w > kMaxWidth) code = code ? code : -3;
+    if (code == 0 && skip && skip[q]) code = -2;  // keeps its coefficient slot, takes no matrix space
     plan.info[q] = code;
-    plan.width[q] = code ? 0 : (int32_t)w;
+    plan.width[q] = (code == 0 || code == -2) ? (int32_t)w : 0;
   }
   __syncthreads();
   // 2. exclusive prefix sums of w and w^2 over contiguous chunks
@@ -56,7 +58,7 @@ __global__ __launch_bounds__(kPlanThreads) void plan_kernel(int32_t n_q, int32_t
   for (int q = qb; q < qe; ++q) {
     const int64_t w = plan.width[q];
     sw += w;
-    sw2 += w * w;
+    if (plan.info[q] == 0) sw2 += w * w;
   }
   s_w[tid] = sw;
   s_w2[tid] = sw2;
@@ -75,8 +77,9 @@ __global__ __launch_bounds__(kPlanThreads) void plan_kernel(int32_t n_q, int32_t
     plan.coeff_off[q] = cw;
     plan.mat_off[q] = cw2;
     cw += w;
-    cw2 += w * w;
-    if (plan.info[q] == 0 && (cw > coeff_cap || cw2 > mat_cap)) plan.info[q] = -3;
+    if (plan.info[q] == 0) cw2 += w * w;
+    if ((plan.info[q] == 0 || plan.info[q] == -2) && cw > coeff_cap) plan.info[q] = -3;
+    if (plan.info[q] == 0 && cw2 > mat_cap) plan.info[q] = -3;
   }
   if (tid == kPlanThreads - 1) {
     plan.coeff_off[n_q] = s_w[tid];
@@ -272,7 +275,7 @@ __global__ void ir_check_kernel(int32_t n_q, Plan plan, const double* __restrict
   const int32_t q = blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= n_q) return;
   if (plan.info[q] != 0) {
-    if (last) relres[q] = __longlong_as_double(0x7ff8000000000000LL);
+    if (last && plan.info[q] != -2) relres[q] = __longlong_as_double(0x7ff8000000000000LL);
     return;
   }
   const double bn = bnorm[q];
@@ -299,6 +302,49 @@ __global__ void finalize_kernel(int32_t n_q, Plan plan, double* __restrict__ coe
     coeff[off + c] = __longlong_as_double(0x7ff8000000000000LL);
 }
 
+// right-hand side only (see form_kernel), one thread per reduced index of a query
+__global__ __launch_bounds__(256) void rhs_kernel(RomView rom, int32_t n_q, const double* __restrict__ thf,
+                                                  const double* __restrict__ th0, Plan plan, double* __restrict__ rhs) {
+  const int32_t q = blockIdx.y;
+  if (plan.info[q] != 0) return;
+  const int32_t w = plan.width[q];
+  const int a = blockIdx.x * 256 + threadIdx.x;
+  if (a >= w) return;  // full-width queries: local index = global index
+  const int i = rom.mode[a];
+  double b = 0.0;
+  for (int k = 0; k < rom.Qf; ++k)
+    b = fma(thf[(int64_t)q * rom.Qf + k] * rom.Wf[(int64_t)k * rom.n + a], rom.bhat[(int64_t)k * rom.n_s + i], b);
+  double u0 = 0.0;
+  for (int k = 0; k < rom.Q0; ++k) u0 = fma(th0[(int64_t)q * rom.Q0 + k], rom.u0hat[(int64_t)k * rom.n_s + i], u0);
+  rhs[plan.coeff_off[q] + a] = fma(rom.P1[a], u0, b);
+}
+
+// coeff[coeff_off[q] + a] = mean[a] + scale[a] * Y[q * n + a] for valid queries
+__global__ void destandardize_kernel(int64_t total, int32_t n, const float* __restrict__ Y,
+                                     const double* __restrict__ mean, const double* __restrict__ scale, Plan plan,
+                                     double* __restrict__ coeff) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= total) return;
+  const int32_t q = (int32_t)(e / n);
+  const int a = (int)(e % n);
+  if (plan.info[q] != 0 || a >= plan.width[q]) return;
+  coeff[plan.coeff_off[q] + a] = fma(scale[a], (double)Y[e], mean[a]);
+}
+
+__global__ void certificate_kernel(int32_t n_q, Plan plan, const double* __restrict__ rnorm,
+                                   const double* __restrict__ cnorm, double gamma, double tol, double* __restrict__ cert,
+                                   int32_t* __restrict__ accept) {
+  const int32_t q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= n_q) return;
+  double c = __longlong_as_double(0x7ff0000000000000LL);  // +inf
+  if (plan.info[q] == 0 && cnorm[q] > 0.0) {
+    const double e = rnorm[q] / (gamma * cnorm[q]);
+    if (e < 1.0) c = e / (1.0 - e);
+  }
+  cert[q] = c;
+  accept[q] = (c <= tol) ? 1 : 0;
+}
+
 __global__ void fill_i32_kernel(int32_t* p, int64_t n, int32_t v) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = v;
@@ -306,11 +352,36 @@ __global__ void fill_i32_kernel(int32_t* p, int64_t n, int32_t v) {
 
 }  // namespace
 
-hipError_t launch_plan(int32_t n_q, int32_t n_s, const int32_t* moff, const int32_t* nt_q, const double* thA,
-                       const double* thf, const double* th0, int32_t Q, int32_t Qf, int32_t Q0, int64_t coeff_cap,
-                       int64_t mat_cap, Plan plan, hipStream_t s) {
-  hipLaunchKernelGGL(plan_kernel, dim3(1), dim3(kPlanThreads), 0, s, n_q, n_s, moff, nt_q, thA, thf, th0, Q, Qf, Q0,
-                     coeff_cap, mat_cap, plan);
+hipError_t launch_plan(int32_t n_q, int32_t n_s, const int32_t* moff, const int32_t* nt_q, const int32_t* skip,
+                       const double* thA, const double* thf, const double* th0, int32_t Q, int32_t Qf, int32_t Q0,
+                       int64_t coeff_cap, int64_t mat_cap, Plan plan, hipStream_t s) {
+  hipLaunchKernelGGL(plan_kernel, dim3(1), dim3(kPlanThreads), 0, s, n_q, n_s, moff, nt_q, skip, thA, thf, th0, Q, Qf,
+                     Q0, coeff_cap, mat_cap, plan);
+  return hipGetLastError();
+}
+
+hipError_t launch_rhs(const RomView& rom, int32_t n_q, const double* thf, const double* th0, const int32_t* nt_q,
+                      Plan plan, double* rhs, int32_t n_max, hipStream_t s) {
+  if (nt_q) return hipErrorInvalidValue;  // full-width queries only
+  if (n_q == 0 || n_max == 0) return hipSuccess;
+  hipLaunchKernelGGL(rhs_kernel, dim3((n_max + 255) / 256, n_q), dim3(256), 0, s, rom, n_q, thf, th0, plan, rhs);
+  return hipGetLastError();
+}
+
+hipError_t launch_destandardize(int32_t n_q, int32_t n, const float* Y, const double* mean, const double* scale,
+                                Plan plan, double* coeff, hipStream_t s) {
+  const int64_t total = (int64_t)n_q * n;
+  if (total == 0) return hipSuccess;
+  hipLaunchKernelGGL(destandardize_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, total, n, Y, mean,
+                     scale, plan, coeff);
+  return hipGetLastError();
+}
+
+hipError_t launch_certificate(int32_t n_q, Plan plan, const double* rnorm, const double* cnorm, double gamma, double tol,
+                              double* cert, int32_t* accept, hipStream_t s) {
+  if (n_q == 0) return hipSuccess;
+  hipLaunchKernelGGL(certificate_kernel, dim3((n_q + 255) / 256), dim3(256), 0, s, n_q, plan, rnorm, cnorm, gamma, tol,
+                     cert, accept);
   return hipGetLastError();
 }
 

@@ -64,8 +64,17 @@ _SIGNATURES = {
     "st_form": (_I32, [ctypes.POINTER(st_rom_desc), _P, _I32, _P, _P, _P, _P, _I32, _P, _I64, _P, _I64, _P, _P, _P,
                        _P, _SZ, _P]),
     "st_solve_workspace": (_SZ, [ctypes.POINTER(st_rom_desc), _I32, _I64, _I64, _I32]),
-    "st_solve": (_I32, [ctypes.POINTER(st_rom_desc), _P, _I32, _P, _P, _P, _P, _I32, _D, _I32, _P, _I64, _P, _P, _P,
-                        _P, _P, _SZ, _P]),
+    "st_solve": (_I32, [ctypes.POINTER(st_rom_desc), _P, _I32, _P, _P, _P, _P, _P, _I32, _D, _I32, _P, _I64, _P, _P,
+                        _P, _P, _P, _SZ, _P]),
+    "st_mlp_param_count": (_I64, [_P]),
+    "st_mlp_workspace": (_SZ, [_P, _I32]),
+    "st_mlp_forward": (_I32, [_P, _P, _I32, _P, _P, _P, _SZ, _P]),
+    "st_mlp_grad": (_I32, [_P, _P, _I32, _P, _P, _P, _P, _P, _SZ, _P]),
+    "st_mlp_adam": (_I32, [_I64, _P, _P, _P, _P, _I32, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                           _P]),
+    "st_surrogate_check_workspace": (_SZ, [ctypes.POINTER(st_rom_desc), _I32]),
+    "st_surrogate_check": (_I32, [ctypes.POINTER(st_rom_desc), _P, _I32, _P, _P, _P, _P, _P, _P, _D, _D, _P, _P, _P,
+                                  _P, _SZ, _P]),
     "st_timing_enable": (_I32, [_I32]),
     "st_timing_read": (_I32, [ctypes.POINTER(ctypes.c_double), _I32]),
 }
@@ -264,7 +273,7 @@ class SolveBuffers:
 def st_solve(desc: RomDesc, rom: torch.Tensor, theta_A: torch.Tensor, theta_f: Optional[torch.Tensor] = None,
              theta_0: Optional[torch.Tensor] = None, nt_q: Optional[torch.Tensor] = None, lu_prec: int = ST_F64,
              ir_tol: float = 0.0, ir_max: int = 0, bufs: Optional[SolveBuffers] = None,
-             widths: Optional[np.ndarray] = None) -> SolveBuffers:
+             widths: Optional[np.ndarray] = None, skip: Optional[torch.Tensor] = None) -> SolveBuffers:
     """Batched reduced solve; returns the SolveBuffers holding coeff, coeff_off,
     relres, info, iters."""
     n_q = int(theta_A.shape[0])
@@ -273,7 +282,7 @@ def st_solve(desc: RomDesc, rom: torch.Tensor, theta_A: torch.Tensor, theta_f: O
             widths = query_widths(desc, None if nt_q is None else nt_q.cpu().numpy(), n_q)
         bufs = SolveBuffers(desc, n_q, widths, lu_prec, theta_A.device)
     _check(lib().st_solve(desc.ref(), _ptr(rom), n_q, _ptr(theta_A), _ptr(theta_f), _ptr(theta_0), _ptr(nt_q),
-                          lu_prec, float(ir_tol), int(ir_max), _ptr(bufs.coeff), bufs.sum_w, _ptr(bufs.coeff_off),
+                          _ptr(skip), lu_prec, float(ir_tol), int(ir_max), _ptr(bufs.coeff), bufs.sum_w, _ptr(bufs.coeff_off),
                           _ptr(bufs.relres), _ptr(bufs.info), _ptr(bufs.iters), _ptr(bufs.ws), bufs.ws_bytes,
                           _stream()), "st_solve")
     return bufs
@@ -290,3 +299,64 @@ def st_timing_read() -> dict:
     if n < 0:
         raise StromError(n, "st_timing_read")
     return {k: float(buf[i]) for i, k in enumerate(TIMING_PHASES)}
+
+
+# ----------------------------------------------------------------------------
+# surrogate network
+# ----------------------------------------------------------------------------
+
+class st_mlp_shape(ctypes.Structure):
+    _fields_ = [("d_in", ctypes.c_int32), ("width", ctypes.c_int32), ("n_hidden", ctypes.c_int32),
+                ("d_out", ctypes.c_int32)]
+
+
+def mlp_shape(d_in: int, width: int, n_hidden: int, d_out: int) -> st_mlp_shape:
+    return st_mlp_shape(int(d_in), int(width), int(n_hidden), int(d_out))
+
+
+def st_mlp_param_count(shape: st_mlp_shape) -> int:
+    n = int(lib().st_mlp_param_count(ctypes.byref(shape)))
+    if n < 0:
+        raise StromError(-1, "st_mlp_param_count")
+    return n
+
+
+def _mlp_ws(shape, batch, device):
+    nb = lib().st_mlp_workspace(ctypes.byref(shape), int(batch))
+    return torch.empty(max(nb, 1), dtype=torch.uint8, device=device), nb
+
+
+def st_mlp_forward(shape: st_mlp_shape, params: torch.Tensor, X: torch.Tensor, ws=None) -> torch.Tensor:
+    batch = int(X.shape[0])
+    Y = torch.empty((batch, shape.d_out), dtype=torch.float32, device=X.device)
+    if ws is None:
+        ws = _mlp_ws(shape, batch, X.device)
+    _check(lib().st_mlp_forward(ctypes.byref(shape), _ptr(params), batch, _ptr(X), _ptr(Y), _ptr(ws[0]), ws[1],
+                                _stream()), "st_mlp_forward")
+    return Y
+
+
+def st_mlp_grad(shape: st_mlp_shape, params: torch.Tensor, X: torch.Tensor, T: torch.Tensor, grads: torch.Tensor,
+                loss: torch.Tensor, ws=None):
+    batch = int(X.shape[0])
+    if ws is None:
+        ws = _mlp_ws(shape, batch, X.device)
+    _check(lib().st_mlp_grad(ctypes.byref(shape), _ptr(params), batch, _ptr(X), _ptr(T), _ptr(grads), _ptr(loss),
+                             _ptr(ws[0]), ws[1], _stream()), "st_mlp_grad")
+
+
+def st_mlp_adam(params: torch.Tensor, grads: torch.Tensor, m: torch.Tensor, v: torch.Tensor, step: int, lr: float,
+                beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8):
+    _check(lib().st_mlp_adam(int(params.numel()), _ptr(params), _ptr(grads), _ptr(m), _ptr(v), int(step), float(lr),
+                             float(beta1), float(beta2), float(eps), _stream()), "st_mlp_adam")
+
+
+def st_surrogate_check(desc: RomDesc, rom: torch.Tensor, theta_A: torch.Tensor, theta_f, theta_0, Y: torch.Tensor,
+                       mean: torch.Tensor, scale: torch.Tensor, gamma: float, tol: float, coeff: torch.Tensor,
+                       cert: torch.Tensor, accept: torch.Tensor):
+    n_q = int(theta_A.shape[0])
+    nb = lib().st_surrogate_check_workspace(desc.ref(), n_q)
+    ws = torch.empty(max(nb, 1), dtype=torch.uint8, device=theta_A.device)
+    _check(lib().st_surrogate_check(desc.ref(), _ptr(rom), n_q, _ptr(theta_A), _ptr(theta_f), _ptr(theta_0), _ptr(Y),
+                                    _ptr(mean), _ptr(scale), float(gamma), float(tol), _ptr(coeff), _ptr(cert),
+                                    _ptr(accept), _ptr(ws), nb, _stream()), "st_surrogate_check")

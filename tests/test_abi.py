@@ -77,7 +77,7 @@ def test_host_validation_rejects_bad_arguments():
                                   iters=None, ws=fake, wsb=1 << 20, stream=None), **kw)
 
     def call(a):
-        return L.st_solve(a["d"], a["rom"], a["n_q"], a["thA"], a["thf"], a["th0"], a["nt"], a["prec"], a["tol"],
+        return L.st_solve(a["d"], a["rom"], a["n_q"], a["thA"], a["thf"], a["th0"], a["nt"], None, a["prec"], a["tol"],
                           a["irmax"], a["coeff"], a["cap"], a["coff"], a["relres"], a["info"], a["iters"], a["ws"],
                           a["wsb"], a["stream"])
 
@@ -111,3 +111,39 @@ def test_workspace_sizes_with_empty_term_lists():
         assert L.st_assemble_workspace(d.ref(), 256) >= 2 * 8 * 256 * 8
         assert L.st_form_workspace(d.ref(), 10) > 0
         assert L.st_solve_workspace(d.ref(), 10, 640, 40960, 0) > 40960 * 8
+
+
+def test_mlp_and_certificate_host_validation():
+    """Surrogate entry points reject bad shapes and arguments before any launch."""
+    L = strom.lib()
+    fake = ctypes.c_void_p(0x1000)
+    ok = strom.mlp_shape(3, 512, 4, 1200)
+    assert strom.st_mlp_param_count(ok) == 3 * 512 + 512 + 3 * (512 * 512 + 512) + 512 * 1200 + 1200
+    assert L.st_mlp_workspace(ctypes.byref(ok), 4096) > 4096 * 1200 * 4
+    for bad in (strom.mlp_shape(0, 8, 1, 1), strom.mlp_shape(3, 8, 0, 1), strom.mlp_shape(3, 8, 1, 0),
+                strom.mlp_shape(3, 8, 63, 1)):
+        assert L.st_mlp_param_count(ctypes.byref(bad)) < 0
+        assert L.st_mlp_workspace(ctypes.byref(bad), 10) == 0
+        assert L.st_mlp_forward(ctypes.byref(bad), fake, 10, fake, fake, fake, 1 << 30, None) == -1
+    assert L.st_mlp_forward(None, fake, 10, fake, fake, fake, 1 << 30, None) == -1
+    # batch 0 is a no-op; null buffers and short workspaces are rejected
+    assert L.st_mlp_forward(ctypes.byref(ok), None, 0, None, None, None, 0, None) == 0
+    assert L.st_mlp_forward(ctypes.byref(ok), fake, 10, None, fake, fake, 1 << 30, None) == -1
+    assert L.st_mlp_forward(ctypes.byref(ok), fake, 10, fake, fake, fake, 16, None) == -3
+    assert L.st_mlp_grad(ctypes.byref(ok), fake, 0, fake, fake, fake, fake, fake, 1 << 30, None) == -1
+    assert L.st_mlp_grad(ctypes.byref(ok), fake, 10, fake, fake, fake, fake, fake, 16, None) == -3
+    f = ctypes.c_float
+    assert L.st_mlp_adam(10, fake, fake, fake, fake, 0, f(1e-3), f(0.9), f(0.999), f(1e-8), None) == -1
+    assert L.st_mlp_adam(10, fake, fake, fake, fake, 1, f(1e-3), f(1.0), f(0.999), f(1e-8), None) == -1
+    assert L.st_mlp_adam(10, fake, fake, fake, fake, 1, f(1e-3), f(0.9), f(0.999), f(0.0), None) == -1
+    assert L.st_mlp_adam(0, None, None, None, None, 1, f(1e-3), f(0.9), f(0.999), f(1e-8), None) == 0
+    # certificate: gamma must be positive, tolerance non-negative
+    d = strom.RomDesc([4, 4], 8, 2, 0, 1)
+    nb = L.st_surrogate_check_workspace(d.ref(), 4)
+    assert nb > 0
+    call = lambda gamma, tol, ws=nb: L.st_surrogate_check(d.ref(), fake, 4, fake, None, fake, fake, fake, fake,
+                                                         gamma, tol, fake, fake, fake, fake, ws, None)
+    assert call(0.0, 1e-6) == -1
+    assert call(1e-3, -1.0) == -1
+    assert call(float("nan"), 1e-6) == -1
+    assert call(1e-3, 1e-6, ws=nb - 1) == -3

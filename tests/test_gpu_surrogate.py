@@ -1,0 +1,296 @@
+"""Surrogate network, residual certificate and fallback on the device.
+
+The network runs its products in BF16 with FP32 accumulation, so it is
+compared with the FP64 oracle network under the first-order probabilistic
+rounding-error bounds of tests/_bf16_model.py (inputs and weights are
+BF16-representable; every other rounding site is modelled).  The bounds are
+checked on the CPU against an emulation of that arithmetic and against
+planted mistakes in tests/test_bf16_model.py.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from oracle import bounds as obounds  # noqa: E402
+from oracle import mlp as omlp  # noqa: E402
+from oracle import rom as orom  # noqa: E402
+from paper_1910_01260_amd import strom  # noqa: E402
+from paper_1910_01260_amd import surrogate as S  # noqa: E402
+from paper_1910_01260_amd import workloads as W  # noqa: E402
+
+from . import _bf16_model as M  # noqa: E402
+from . import _cases as C  # noqa: E402
+from ._gpu import DeviceRom, thetas_device  # noqa: E402
+
+
+def _flat(params):
+    return np.concatenate([np.concatenate([W.ravel(), b]) for W, b in params]).astype(np.float32)
+
+
+def _unflat(flat, sizes):
+    out, o = [], 0
+    for a, b in zip(sizes[:-1], sizes[1:]):
+        Wm = flat[o:o + a * b].reshape(b, a)
+        o += a * b
+        out.append((Wm, flat[o:o + b]))
+        o += b
+    return out
+
+
+def _params(sizes, seed):
+    rng = np.random.default_rng(seed)
+    p = omlp.init_params(sizes, rng)
+    return [(M.bf16_round(W), (0.1 * rng.standard_normal(b.shape)).astype(np.float32).astype(np.float64))
+            for W, b in p]
+
+
+def _data(sizes, batch, seed):
+    rng = np.random.default_rng(seed)
+    X = M.bf16_round(rng.uniform(-1, 1, (batch, sizes[0])))
+    T = rng.standard_normal((batch, sizes[-1])).astype(np.float32).astype(np.float64)
+    return X, T
+
+
+def _dev(a):
+    return torch.tensor(np.asarray(a, dtype=np.float32), device="cuda")
+
+
+@pytest.mark.parametrize("sizes,batch", [([37, 70, 29], 130), ([3, 96, 96, 96, 50], 200), ([3, 64, 1], 65),
+                                         ([3, 512, 512, 512, 512, 300], 65)])
+def test_mlp_forward_within_bf16_bound(sizes, batch):
+    params = _params(sizes, seed=len(sizes) * 7 + batch)
+    X, _ = _data(sizes, batch, seed=batch)
+    shape = strom.mlp_shape(sizes[0], sizes[1], len(sizes) - 2, sizes[-1])
+    assert strom.st_mlp_param_count(shape) == _flat(params).size
+    print(f"[mlp forward] sizes={sizes} batch={batch}", flush=True)
+    Yd = strom.st_mlp_forward(shape, _dev(_flat(params)), _dev(X))
+    torch.cuda.synchronize()
+    Yd = Yd.cpu().numpy().astype(np.float64)
+    em = M.error_model(params, X)
+    r = np.abs(Yd - em["Y"]) / em["Y_bound"]
+    print(f"  max err {np.abs(Yd - em['Y']).max():.3e}, max err/bound {r.max():.3f}, "
+          f"median bound/|Y| {np.median(em['Y_bound'] / (np.abs(em['Y']) + 1e-30)):.2e}")
+    assert r.max() <= 1.0
+
+
+@pytest.mark.parametrize("sizes,batch", [([3, 64, 64, 40], 100), ([5, 33, 17], 70), ([3, 128, 128, 128, 120], 130)])
+def test_mlp_grad_within_bf16_bound(sizes, batch):
+    params = _params(sizes, seed=batch)
+    X, T = _data(sizes, batch, seed=batch + 1)
+    shape = strom.mlp_shape(sizes[0], sizes[1], len(sizes) - 2, sizes[-1])
+    p = _dev(_flat(params))
+    g = torch.empty_like(p)
+    loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+    print(f"[mlp grad] sizes={sizes} batch={batch}", flush=True)
+    strom.st_mlp_grad(shape, p, _dev(X), _dev(T), g, loss)
+    torch.cuda.synchronize()
+    gd = _unflat(g.cpu().numpy().astype(np.float64), sizes)
+    em = M.error_model(params, X, T)
+    assert abs(float(loss.item()) - em["loss"]) <= 1e-2 * em["loss"]
+    for li in range(len(params)):
+        for k in range(2):
+            err = np.abs(gd[li][k] - em["grads"][li][k])
+            r = err / em["grad_bounds"][li][k]
+            print(f"  layer {li} {'Wb'[k]}: max err {err.max():.3e}, max err/bound {r.max():.3f}")
+            assert r.max() <= 1.0, (li, k)
+
+
+def test_adam_matches_oracle_over_steps():
+    rng = np.random.default_rng(5)
+    n = 1000
+    p0 = rng.standard_normal(n).astype(np.float32)
+    gs = [rng.standard_normal(n).astype(np.float32) * s for s in (1.0, 1e-3, 10.0)]
+    p = torch.tensor(p0, device="cuda")
+    m = torch.zeros_like(p)
+    v = torch.zeros_like(p)
+    ref = [(p0.astype(np.float64)[None, :], np.zeros(1))]
+    state = {}
+    for t, g in enumerate(gs, start=1):
+        strom.st_mlp_adam(p, torch.tensor(g, device="cuda"), m, v, t, 3e-3)
+        omlp.adam_step(ref, [(g.astype(np.float64)[None, :], np.zeros(1))], state, lr=3e-3)
+    torch.cuda.synchronize()
+    np.testing.assert_allclose(p.cpu().numpy(), ref[0][0][0], rtol=1e-6, atol=1e-7)
+
+
+# ----------------------------------------------------------------------------
+# certificate and fallback on the small surrogate problem
+# ----------------------------------------------------------------------------
+
+def _cs_rom():
+    name = "cs_small"
+    prob = C.problem(name)
+    Phi_s, sigma, V, Phi_t, ranks = C.oracle_bases(name)
+    return name, prob, DeviceRom(prob, Phi_s, Phi_t)
+
+
+def _oracle_solutions(name, tA, tf, t0):
+    out = []
+    for q in range(tA.shape[0]):
+        M, b = C.oracle_system(name, tA[q], tf[q], t0[q])
+        out.append((M, b, orom.solve(M, b)))
+    return out
+
+
+def test_surrogate_check_matches_oracle_certificate():
+    name, prob, dr = _cs_rom()
+    n = dr.desc.n
+    n_q = 48
+    mus = W.sample_params(prob, n_q, seed=31)
+    (tA, tf, t0), (dA, df, d0) = thetas_device(prob, mus)
+    ref = _oracle_solutions(name, tA, tf, t0)
+    rng = np.random.default_rng(32)
+    mean = rng.standard_normal(n)
+    scale = rng.uniform(0.5, 2.0, n)
+    Y = np.empty((n_q, n), dtype=np.float32)
+    for q in range(n_q):
+        noise = [0.0, 1e-6, 1e-3, 1e-1][q % 4]
+        c = ref[q][2] * (1 + noise * rng.standard_normal(n))
+        Y[q] = ((c - mean) / scale).astype(np.float32)
+    coeff = torch.empty(n_q * n, dtype=torch.float64, device="cuda")
+    cert = torch.empty(n_q, dtype=torch.float64, device="cuda")
+    acc = torch.empty(n_q, dtype=torch.int32, device="cuda")
+    gamma = S.coercivity_floor(prob.N_t)
+    tol = 1e-1
+    print(f"[surrogate check] cs_small n={n} n_q={n_q} gamma={gamma:.3e}", flush=True)
+    strom.st_surrogate_check(dr.desc, dr.rom, dA, df, d0, torch.tensor(Y, device="cuda"),
+                             torch.tensor(mean, device="cuda"), torch.tensor(scale, device="cuda"), gamma, tol,
+                             coeff, cert, acc)
+    torch.cuda.synchronize()
+    cd = coeff.cpu().numpy().reshape(n_q, n)
+    certd = cert.cpu().numpy()
+    accd = acc.cpu().numpy()
+    n_acc = 0
+    for q in range(n_q):
+        M, b, cstar = ref[q]
+        c = cd[q]
+        sy = scale * Y[q].astype(np.float64)
+        assert np.all(np.abs(c - (mean + sy)) <= 2.0 ** -52 * (np.abs(mean) + np.abs(sy)))
+        cr = obounds.certificate(M, b, c, gamma)
+        if np.isinf(cr):
+            assert np.isinf(certd[q]) and accd[q] == 0
+            continue
+        # FP64 residual error: |dr| <= n eps (|b| + |M||c|)
+        dres = n * 2.0 ** -53 * np.linalg.norm(np.abs(b) + np.abs(M) @ np.abs(c))
+        de = dres / (gamma * np.linalg.norm(c))
+        e = cr / (1 + cr)
+        assert abs(certd[q] - cr) <= (de + 1e-13 * e) / (1 - e - de) ** 2, (q, certd[q], cr)
+        assert accd[q] == int(certd[q] <= tol)
+        n_acc += accd[q]
+        true = np.linalg.norm(c - cstar) / np.linalg.norm(cstar)
+        assert true <= certd[q] * (1 + 1e-9)
+    assert 0 < n_acc < n_q
+
+
+def test_surrogate_check_nonfinite_parameter_rejected():
+    name, prob, dr = _cs_rom()
+    n = dr.desc.n
+    mus = W.sample_params(prob, 3, seed=33)
+    (tA, tf, t0), _ = thetas_device(prob, mus)
+    tA = tA.copy()
+    tA[1, 0] = np.nan
+    dA = torch.tensor(tA, device="cuda")
+    df = torch.tensor(tf, device="cuda")
+    d0 = torch.tensor(t0, device="cuda") if t0.shape[1] else None
+    Y = torch.zeros((3, n), dtype=torch.float32, device="cuda")
+    mean = torch.ones(n, dtype=torch.float64, device="cuda")
+    scale = torch.ones(n, dtype=torch.float64, device="cuda")
+    coeff = torch.full((3 * n,), -7.0, dtype=torch.float64, device="cuda")
+    cert = torch.empty(3, dtype=torch.float64, device="cuda")
+    acc = torch.empty(3, dtype=torch.int32, device="cuda")
+    strom.st_surrogate_check(dr.desc, dr.rom, dA, df, d0, Y, mean, scale, 1e-3, 1e30, coeff, cert, acc)
+    torch.cuda.synchronize()
+    assert np.isinf(cert[1].item()) and acc[1].item() == 0
+    cd = coeff.cpu().numpy()
+    # query 1 takes no slot: query 2 follows query 0
+    np.testing.assert_array_equal(cd[:2 * n], 1.0)
+    np.testing.assert_array_equal(cd[2 * n:], -7.0)
+
+
+def test_skip_mask_fallback_keeps_accepted_and_solves_rest():
+    name, prob, dr = _cs_rom()
+    n = dr.desc.n
+    n_q = 24
+    mus = W.sample_params(prob, n_q, seed=34)
+    (tA, tf, t0), (dA, df, d0) = thetas_device(prob, mus)
+    ref = _oracle_solutions(name, tA, tf, t0)
+    rng = np.random.default_rng(35)
+    skip = (rng.uniform(size=n_q) < 0.5).astype(np.int32)
+    bufs = strom.SolveBuffers(dr.desc, n_q, np.full(n_q, n), strom.ST_F64, "cuda")
+    sentinel = rng.standard_normal(n_q * n)
+    bufs.coeff.copy_(torch.tensor(sentinel, device="cuda"))
+    bufs.relres.fill_(-1.0)
+    print(f"[skip fallback] cs_small n_q={n_q} skipped={skip.sum()}", flush=True)
+    strom.st_solve(dr.desc, dr.rom, dA, df, d0, None, strom.ST_F64, bufs=bufs,
+                   skip=torch.tensor(skip, device="cuda"))
+    torch.cuda.synchronize()
+    cd = bufs.coeff.cpu().numpy().reshape(n_q, n)
+    info = bufs.info.cpu().numpy()[:n_q]
+    relres = bufs.relres.cpu().numpy()[:n_q]
+    np.testing.assert_array_equal(bufs.coeff_off.cpu().numpy(), np.arange(n_q + 1) * n)
+    for q in range(n_q):
+        if skip[q]:
+            assert info[q] == -2 and relres[q] == -1.0
+            np.testing.assert_array_equal(cd[q], sentinel[q * n:(q + 1) * n])
+        else:
+            assert info[q] == 0
+            cs = ref[q][2]
+            assert np.linalg.norm(cd[q] - cs) <= 1e-10 * np.linalg.norm(cs)
+
+
+def test_surrogate_train_certify_and_fall_back():
+    """End to end on the small problem: data from batched FP64 solves, a few
+    hundred Adam steps, then certificate + fallback.  Accepted predictions
+    are within their certificate; rejected ones equal the plain solve."""
+    name, prob, dr = _cs_rom()
+    n = dr.desc.n
+    n_train, n_test = 2048, 256
+    mus = W.sample_params(prob, n_train + n_test, seed=36)
+    (tA, tf, t0), (dA, df, d0) = thetas_device(prob, mus)
+    print(f"[surrogate e2e] cs_small n={n} training solves={n_train}", flush=True)
+    out = strom.st_solve(dr.desc, dr.rom, dA, df, d0, None, strom.ST_F64)
+    torch.cuda.synchronize()
+    assert np.all(out.info.cpu().numpy()[:n_train + n_test] == 0)
+    Call = out.coeff.cpu().numpy().reshape(-1, n)
+    X = S.scaled_inputs(prob.box_lo, prob.box_hi, mus)
+    net = S.Surrogate(X.shape[1], n, width=128, n_hidden=2, seed=37)
+    hist = net.fit(X[:n_train], Call[:n_train], steps=400, batch=256, lr=2e-3, lr_final=1e-5)
+    print("  history (step, train, val):", [(s, f"{a:.2e}", f"{b:.2e}") for s, a, b in hist[::4]])
+    assert hist[-1][2] < 0.1 * hist[0][2]
+    # test queries
+    sl = slice(n_train, n_train + n_test)
+    dAt, dft = dA[sl].contiguous(), df[sl].contiguous()
+    d0t = d0[sl].contiguous() if d0 is not None else None
+    Xt = torch.tensor(X[sl], device="cuda")
+    gamma = S.coercivity_floor(prob.N_t)
+    ref = Call[sl]
+    for tol in (1e30, 1e-1, 0.0):
+        bufs = strom.SolveBuffers(dr.desc, n_test, np.full(n_test, n), strom.ST_F64, "cuda")
+        bufs, cert, acc = net.solve(dr.desc, dr.rom, dAt, dft, d0t, Xt, gamma, tol, bufs)
+        torch.cuda.synchronize()
+        cd = bufs.coeff.cpu().numpy().reshape(n_test, n)
+        certd, accd = cert.cpu().numpy(), acc.cpu().numpy()
+        info = bufs.info.cpu().numpy()[:n_test]
+        rel = np.linalg.norm(cd - ref, axis=1) / np.linalg.norm(ref, axis=1)
+        print(f"  tol={tol:g}: accepted {accd.sum()}/{n_test}, surrogate rel err p50 "
+              f"{np.median(rel[accd == 1]) if accd.any() else float('nan'):.2e}, "
+              f"cert p50 {np.median(certd):.2e}")
+        for q in range(n_test):
+            if accd[q]:
+                assert info[q] == -2
+                assert rel[q] <= certd[q] * (1 + 1e-9) + 1e-15
+            else:
+                assert info[q] == 0
+                assert rel[q] <= 1e-12
+        if tol == 0.0:
+            assert accd.sum() == 0
+    # the trained network is a useful predictor on unseen parameters
+    Y = net.predict(Xt)
+    coeff = torch.empty(n_test * n, dtype=torch.float64, device="cuda")
+    net.check(dr.desc, dr.rom, dAt, dft, d0t, Y, gamma, 0.0, coeff)
+    torch.cuda.synchronize()
+    pred = coeff.cpu().numpy().reshape(n_test, n)
+    rel = np.linalg.norm(pred - ref, axis=1) / np.linalg.norm(ref, axis=1)
+    print(f"  prediction rel err p50 {np.median(rel):.2e} max {rel.max():.2e}")
+    assert np.median(rel) < 0.05

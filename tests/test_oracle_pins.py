@@ -370,6 +370,37 @@ def test_symmetric_part_positive_definite(problem):
         assert lam >= (1 - math.cos(math.pi / (prob.N_t + 1))) * (1 - 1e-10)
 
 
+def test_certificate_bounds_true_error():
+    """The residual certificate is an upper bound of the true relative error of
+    perturbed reduced solutions, and is not vacuous for small perturbations."""
+    prob = _tiny_transport(nx=8)
+    U, Phi_s, s, V, Phi_t, _ = _bases(prob, 4, [4, 3, 3, 2])
+    gamma = bounds.coercivity_floor(prob.N_t)
+    rng = np.random.default_rng(12)
+    tight = []
+    for mu in W.sample_params(prob, 3, seed=13):
+        M, b = _system(prob, Phi_s, Phi_t, mu)
+        c = np.linalg.solve(M, b)
+        lam = np.linalg.eigvalsh(0.5 * (M + M.T)).min()
+        assert lam >= gamma * (1 - 1e-10)
+        for eps in (1e-8, 1e-5, 1e-3):
+            d = rng.standard_normal(c.shape)
+            ct = c + eps * np.linalg.norm(c) * d / np.linalg.norm(d)
+            true = np.linalg.norm(ct - c) / np.linalg.norm(c)
+            cert = bounds.certificate(M, b, ct, gamma)
+            assert cert >= true * (1 - 1e-9)
+            tight.append(cert / true)
+        assert bounds.certificate(M, b, np.zeros_like(c), gamma) == np.inf
+    assert min(tight) < 1e4  # a usable bound, not infinity
+
+
+def test_coercivity_floor_is_toeplitz_minimum():
+    """1 - cos(pi/(N+1)) is the smallest eigenvalue of tridiag(-1/2, 1, -1/2)."""
+    for N in (1, 2, 7, 50):
+        T = np.eye(N) - 0.5 * (np.eye(N, k=1) + np.eye(N, k=-1))
+        assert abs(np.linalg.eigvalsh(T).min() - bounds.coercivity_floor(N)) <= 1e-14
+
+
 # ----------------------------------------------------------------------------
 # surrogate reference network
 # ----------------------------------------------------------------------------
