@@ -43,6 +43,9 @@ def parse():
     ap.add_argument("--queries", type=int, default=4096)
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the oracle baseline leg")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration-gib", type=float, default=0.0,
+                    help="before the steps, copy a buffer of this size once (device to device) so that a "
+                         "hardware-counter run can scale byte counters against a kernel of known traffic")
     return ap.parse_args()
 
 
@@ -98,6 +101,17 @@ def main():
     b32 = strom.SolveBuffers(desc, nq, widths, strom.ST_F32, dev)
     b64 = strom.SolveBuffers(desc, nq, widths, strom.ST_F64, dev)
     torch.cuda.synchronize()
+
+    if args.copy_calibration_gib > 0:
+        n_cal = int(args.copy_calibration_gib * (1 << 30)) // 4
+        src = torch.ones(n_cal, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"[bench] calibration copy: {4 * n_cal} bytes read, {4 * n_cal} bytes written", file=sys.stderr,
+              flush=True)
+        del src, dst
 
     state = {}
 
