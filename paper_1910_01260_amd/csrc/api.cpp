@@ -340,7 +340,8 @@ st_status st_solve(const st_rom_desc* d, const void* rom, int32_t n_q, const dou
     ST_TRY(launch_lu_solve(n_q, plan, lu_prec, mats, perm, r, coeff, 1, active, n_max, s));
   }
   ST_TRY(mark(6, s));
-  ST_TRY(launch_residual(rv, n_q, theta_A, nt_q, plan, b, coeff, r, rnorm, nullptr, n_max, s));
+  // final residual of the queries still active (all of them without refinement)
+  ST_TRY(launch_residual(rv, n_q, theta_A, nt_q, plan, b, coeff, r, rnorm, active, n_max, s));
   const int flag = (lu_prec == ST_F32 || ir_max > 0) ? 2 : 1;
   ST_TRY(launch_ir_check(n_q, plan, rnorm, bnorm, ir_tol, ir_max, flag, active, relres, iters, s));
   ST_TRY(launch_finalize(n_q, plan, coeff, info, s));

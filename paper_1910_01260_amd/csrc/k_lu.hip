@@ -573,7 +573,39 @@ __global__ __launch_bounds__(kLuThreads) void lu_kernel(int32_t n_q, Plan plan, 
 // factor, in 64-row blocks (diagonal block by one wave, the rest as wave-wide
 // coalesced row dot products).  Accumulation in FP64 whatever T is.
 constexpr int kSolveBS = 64;
-constexpr int kSolveThreads = 256;
+constexpr int kSolveThreads = 512;
+
+// Value of a double in lane k (k uniform across the wave): two v_readlane, no LDS round trip.
+__device__ __forceinline__ double readlane_d(double v, int k) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), k);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), k);
+  return __hiloint2double(hi, lo);
+}
+constexpr int kSolveRowsInFlight = 8;  // rows whose loads one wave issues before reducing them
+
+// y[r] -= A[r, b0 : b0 + 64] . y[b0 : b0 + 64] for the rows r in [r_begin, r_end) owned by
+// this wave (groups of kSolveRowsInFlight rows, strided by the workgroup); lane l holds
+// column b0 + l (inactive lanes pass lane_ok = false).  All loads of a group are issued
+// before any of its reductions, so a wave keeps that many rows in flight.
+template <typename T>
+__device__ __forceinline__ void solve_rows_update(const T* __restrict__ A, int w, int b0, bool lane_ok, double yl,
+                                                  int r_begin, int r_end, double* y) {
+  constexpr int NW = kSolveThreads / 64;
+  const int lane = threadIdx.x & 63;
+  for (int r = r_begin; r < r_end; r += NW * kSolveRowsInFlight) {
+    double a[kSolveRowsInFlight];
+#pragma unroll
+    for (int u = 0; u < kSolveRowsInFlight; ++u) {
+      const int rr = r + u;
+      a[u] = (lane_ok && rr < r_end) ? (double)A[(int64_t)rr * w + b0 + lane] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < kSolveRowsInFlight; ++u) {
+      const double s = __ockl_wfred_add_f64(a[u] * yl);
+      if (lane == 0 && r + u < r_end) y[r + u] -= s;
+    }
+  }
+}
 
 template <typename T>
 __global__ __launch_bounds__(kSolveThreads) void lu_solve_kernel(int32_t n_q, Plan plan, const T* __restrict__ mats,
@@ -583,7 +615,6 @@ __global__ __launch_bounds__(kSolveThreads) void lu_solve_kernel(int32_t n_q, Pl
   extern __shared__ __align__(16) double y[];
   __shared__ double dblk[kSolveBS][kSolveBS + 1];
   __shared__ int32_t spiv[LuCfg<T>::NBO];
-  constexpr int NW = kSolveThreads / 64;
   constexpr int NBO = LuCfg<T>::NBO;
   static_assert(NBO % kSolveBS == 0, "solve blocks must tile the factorisation blocks");
   const int32_t q = blockIdx.x;
@@ -624,17 +655,14 @@ __global__ __launch_bounds__(kSolveThreads) void lu_solve_kernel(int32_t n_q, Pl
     if (wave == 0) {
       double yi = lane < nbk ? y[b0 + lane] : 0.0;
       for (int k = 0; k < nbk; ++k) {
-        const double yk = __shfl(yi, k);
+        const double yk = readlane_d(yi, k);
         if (lane > k && lane < nbk) yi -= dblk[lane][k] * yk;
       }
       if (lane < nbk) y[b0 + lane] = yi;
     }
     __syncthreads();
     const double yl = lane < nbk ? y[b0 + lane] : 0.0;
-    for (int r = b0 + nbk + wave; r < w; r += NW) {
-      const double s = __ockl_wfred_add_f64(lane < nbk ? (double)A[(int64_t)r * w + b0 + lane] * yl : 0.0);
-      if (lane == 0) y[r] -= s;
-    }
+    solve_rows_update(A, w, b0, lane < nbk, yl, b0 + nbk + wave * kSolveRowsInFlight, w, y);
     __syncthreads();
   }
   // back substitution, upper triangular
@@ -649,18 +677,15 @@ __global__ __launch_bounds__(kSolveThreads) void lu_solve_kernel(int32_t n_q, Pl
     if (wave == 0) {
       double yi = lane < nbk ? y[b0 + lane] : 0.0;
       for (int k = nbk - 1; k >= 0; --k) {
-        if (lane == k) yi /= dblk[k][k];
-        const double yk = __shfl(yi, k);
+        const double yk = readlane_d(yi, k) / dblk[k][k];
+        if (lane == k) yi = yk;
         if (lane < k) yi -= dblk[lane][k] * yk;
       }
       if (lane < nbk) y[b0 + lane] = yi;
     }
     __syncthreads();
     const double yl = lane < nbk ? y[b0 + lane] : 0.0;
-    for (int r = wave; r < b0; r += NW) {
-      const double s = __ockl_wfred_add_f64(lane < nbk ? (double)A[(int64_t)r * w + b0 + lane] * yl : 0.0);
-      if (lane == 0) y[r] -= s;
-    }
+    solve_rows_update(A, w, b0, lane < nbk, yl, wave * kSolveRowsInFlight, b0, y);
     __syncthreads();
   }
   for (int c = tid; c < w; c += kSolveThreads) {

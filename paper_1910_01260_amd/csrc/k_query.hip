@@ -12,8 +12,8 @@ namespace strom {
 namespace {
 
 constexpr int kPlanThreads = 1024;
-constexpr int kFormRows = 32;     // rows of one query per workgroup
 constexpr int kFormThreads = 256;
+constexpr int kColChunk = 4;      // columns per thread in flight in the form kernel
 
 __device__ inline bool finite_d(double v) { return v == v && v - v == 0.0; }
 
@@ -106,55 +106,95 @@ __global__ __launch_bounds__(kPlanThreads) void plan_kernel(int32_t n_q, int32_t
   if (tid < 4) plan.counter[tid] = 0;
 }
 
-// Shared per-query setup: local -> global reduced index, local -> mode, local mode offsets,
-// and Ahat(mu) = sum_q theta_q Ahat_q in LDS.
-struct QueryLds {
-  int32_t* gmap;   // w
-  int16_t* mmap;   // w
-  int32_t* loff;   // n_s + 1
-  double* Ah;      // n_s * n_s
+// Mode-row work items.  The assembly and residual kernels give one workgroup
+// the rows of one spatial mode i of one query (its n_t,i(q) temporal rows).  The
+// 1-D grid has 8 * per * n_q workgroups (per = ceil(n_s / 8)); workgroups are
+// dispatched round-robin over the 8 XCDs, so XCD x receives the linear ids x,
+// x + 8, ... and is given the modes x, x + 8, x + 16, ... of every query in turn.
+// The rows of the shared contraction T that an XCD reads (those of its modes)
+// are then the same for every query and stay in that XCD's L2.
+struct ModeItem {
+  int32_t q, i;
 };
 
-__device__ inline void query_setup(const RomView& rom, int32_t q, const double* __restrict__ thA,
-                                   const int32_t* __restrict__ nt_q, QueryLds L) {
-  const int n_s = rom.n_s;
-  if (threadIdx.x == 0) {
-    int32_t o = 0;
-    for (int i = 0; i < n_s; ++i) {
-      L.loff[i] = o;
-      o += nt_q ? nt_q[(int64_t)q * n_s + i] : (rom.moff[i + 1] - rom.moff[i]);
-    }
-    L.loff[n_s] = o;
-  }
-  __syncthreads();
-  for (int i = threadIdx.x; i < n_s; i += blockDim.x) {
-    const int32_t b = L.loff[i], e = L.loff[i + 1], g0 = rom.moff[i];
-    for (int32_t c = b; c < e; ++c) {
-      L.gmap[c] = g0 + (c - b);
-      L.mmap[c] = (int16_t)i;
-    }
-  }
-  const int ns2 = n_s * n_s;
-  for (int e = threadIdx.x; e < ns2; e += blockDim.x) {
-    double v = 0.0;
-    for (int k = 0; k < rom.Q; ++k) v = fma(thA[(int64_t)q * rom.Q + k], rom.Ahat[(int64_t)k * ns2 + e], v);
-    L.Ah[e] = v;
-  }
-  __syncthreads();
+__device__ inline ModeItem mode_item(int32_t n_s) {
+  const int32_t L = blockIdx.x;
+  const int32_t per = (n_s + 7) >> 3;
+  const int32_t k = L >> 3;
+  ModeItem it;
+  it.q = k / per;
+  it.i = (L & 7) + 8 * (k % per);
+  return it;
 }
+
+inline int32_t mode_grid(int32_t n_q, int32_t n_s) { return 8 * ((n_s + 7) / 8) * n_q; }
+
+// Per-workgroup view of one query: local -> global reduced index and mode of
+// every column, local mode offsets, and row i of Ahat(mu) = sum_q theta_q Ahat_q.
+struct QueryLds {
+  int32_t* gmap;   // w_max
+  int16_t* mmap;   // w_max
+  int32_t* loff;   // n_s + 1
+  double* Ah;      // n_s
+};
 
 __device__ inline QueryLds carve_lds(char* base, int n_s, int w_max) {
   QueryLds L;
   L.Ah = reinterpret_cast<double*>(base);
-  L.gmap = reinterpret_cast<int32_t*>(base + sizeof(double) * n_s * n_s);
+  L.gmap = reinterpret_cast<int32_t*>(base + sizeof(double) * n_s);
   L.loff = L.gmap + w_max;
   L.mmap = reinterpret_cast<int16_t*>(L.loff + n_s + 1);
   return L;
 }
 
 __host__ __device__ inline size_t query_lds_bytes(int n_s, int w_max) {
-  return sizeof(double) * n_s * n_s + sizeof(int32_t) * (w_max + n_s + 1) + sizeof(int16_t) * w_max + 16;
+  const size_t b = sizeof(double) * n_s + sizeof(int32_t) * (w_max + n_s + 1) + sizeof(int16_t) * w_max;
+  return (b + 15) / 16 * 16;
 }
+
+// Local mode offsets by a scan in wave 0 (two modes per lane, n_s <= 128), the
+// column maps, and row i of Ahat(mu).
+__device__ inline void query_setup(const RomView& rom, int32_t q, int32_t i, const double* __restrict__ thA,
+                                   const int32_t* __restrict__ nt_q, QueryLds L) {
+  const int n_s = rom.n_s;
+  if (threadIdx.x < 64) {
+    const int lane = threadIdx.x;
+    int32_t c0 = 0, c1 = 0;
+    const int i0 = 2 * lane, i1 = 2 * lane + 1;
+    if (i0 < n_s) c0 = nt_q ? nt_q[(int64_t)q * n_s + i0] : rom.moff[i0 + 1] - rom.moff[i0];
+    if (i1 < n_s) c1 = nt_q ? nt_q[(int64_t)q * n_s + i1] : rom.moff[i1 + 1] - rom.moff[i1];
+    int32_t incl = c0 + c1;
+    for (int d = 1; d < 64; d <<= 1) {
+      const int32_t v = __shfl_up(incl, d, 64);
+      if (lane >= d) incl += v;
+    }
+    const int32_t excl = incl - c0 - c1;
+    if (i0 < n_s) L.loff[i0] = excl;
+    if (i1 < n_s) L.loff[i1] = excl + c0;
+    if (lane == 63) L.loff[n_s] = incl;
+  }
+  const int ns2 = n_s * n_s;
+  for (int ic = threadIdx.x; ic < n_s; ic += blockDim.x) {
+    double v = 0.0;
+    for (int k = 0; k < rom.Q; ++k)
+      v = fma(thA[(int64_t)q * rom.Q + k], rom.Ahat[(int64_t)k * ns2 + (int64_t)ic * n_s + i], v);
+    L.Ah[ic] = v;
+  }
+  __syncthreads();
+  for (int m = threadIdx.x; m < n_s; m += blockDim.x) {
+    const int32_t b = L.loff[m], e = L.loff[m + 1], g0 = rom.moff[m];
+    for (int32_t c = b; c < e; ++c) {
+      L.gmap[c] = g0 + (c - b);
+      L.mmap[c] = (int16_t)m;
+    }
+  }
+  __syncthreads();
+}
+
+// Rows handled per pass of the row loops (two rows' loads in flight together).
+constexpr int kRowUnroll = 2;
+// Rows of one residual pass (their partial sums live in registers).
+constexpr int kResRows = 8;
 
 template <typename OutT>
 __global__ __launch_bounds__(kFormThreads) void form_kernel(RomView rom, int32_t n_q, const double* __restrict__ thA,
@@ -164,48 +204,70 @@ __global__ __launch_bounds__(kFormThreads) void form_kernel(RomView rom, int32_t
                                                             OutT* __restrict__ mats, double* __restrict__ rhs,
                                                             int32_t w_max) {
   extern __shared__ __align__(16) char lds[];
-  const int32_t q = blockIdx.y;
-  if (plan.info[q] != 0) return;
+  const ModeItem it = mode_item(rom.n_s);
+  const int32_t q = it.q, i = it.i;
+  if (q >= n_q || i >= rom.n_s || plan.info[q] != 0) return;
+  const int32_t nti = nt_q ? nt_q[(int64_t)q * rom.n_s + i] : rom.moff[i + 1] - rom.moff[i];
+  if (nti == 0) return;
   const int32_t w = plan.width[q];
-  const int32_t r0 = blockIdx.x * kFormRows;
-  if (r0 >= w) return;
   QueryLds L = carve_lds(lds, rom.n_s, w_max);
-  query_setup(rom, q, thA, nt_q, L);
-  const int n_s = rom.n_s;
+  query_setup(rom, q, i, thA, nt_q, L);
   const int64_t n = rom.n;
+  const int r0 = L.loff[i];
+  const int g0 = rom.moff[i];                         // global index of the mode's first temporal vector
+  const int ntf = rom.moff[i + 1] - g0;               // full n_t,i (leading dimension of K_i)
+  const double* Ki = rom.K + rom.koff[i];            // K_i[j', j] at Ki[j * ntf + j']
   OutT* M = mats + plan.mat_off[q];
-  const int rend = min(w, r0 + kFormRows);
-  for (int r = r0; r < rend; ++r) {
-    const int ir = L.mmap[r];
-    const int gr = L.gmap[r];
-    const int jr = gr - rom.moff[ir];
-    const double* Tcol = rom.T + (int64_t)gr * n;  // T symmetric: column gr holds row gr
-    const int ntr = rom.moff[ir + 1] - rom.moff[ir];
-    const double* Kr = rom.K + rom.koff[ir] + jr;  // K_ir[jr, j] at Kr[j * ntr]
-    const double* Ahr = L.Ah + ir;                 // Ahat(mu)[ir, ic] at Ahr[ic * n_s]
-    OutT* Mr = M + (int64_t)r * w;
-    for (int c = threadIdx.x; c < w; c += kFormThreads) {
-      const int ic = L.mmap[c];
-      const int gc = L.gmap[c];
-      double v = -Ahr[ic * n_s] * Tcol[gc];
-      if (ic == ir) v += Kr[(int64_t)(gc - rom.moff[ic]) * ntr];
-      Mr[c] = (OutT)v;
+  // Each thread owns the columns c = tid + 256 k; their mode and global index stay
+  // in registers while the rows of the mode stream past, kRowUnroll rows at a time.
+  for (int cb = threadIdx.x; cb < w; cb += kColChunk * kFormThreads) {
+    int ic[kColChunk], gc[kColChunk];
+    double ah[kColChunk];
+#pragma unroll
+    for (int k = 0; k < kColChunk; ++k) {
+      const int c = cb + k * kFormThreads;
+      ic[k] = c < w ? L.mmap[c] : -1;
+      gc[k] = c < w ? L.gmap[c] : 0;
+      ah[k] = c < w ? -L.Ah[ic[k]] : 0.0;
+    }
+    for (int j0 = 0; j0 < nti; j0 += kRowUnroll) {
+      double v[kRowUnroll][kColChunk];
+#pragma unroll
+      for (int u = 0; u < kRowUnroll; ++u) {
+        const int j = min(j0 + u, nti - 1);
+        const double* Trow = rom.T + (int64_t)(g0 + j) * n;  // T symmetric: column g0 + j holds row g0 + j
+#pragma unroll
+        for (int k = 0; k < kColChunk; ++k) {
+          double t = ic[k] >= 0 ? Trow[gc[k]] : 0.0;
+          const double kv = ic[k] == i ? Ki[(int64_t)(gc[k] - g0) * ntf + j] : 0.0;
+          v[u][k] = fma(ah[k], t, kv);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kRowUnroll; ++u) {
+        if (j0 + u >= nti) break;
+        OutT* Mr = M + (int64_t)(r0 + j0 + u) * w;
+#pragma unroll
+        for (int k = 0; k < kColChunk; ++k)
+          if (ic[k] >= 0) Mr[cb + k * kFormThreads] = (OutT)v[u][k];
+      }
     }
   }
   // right-hand side of these rows
-  for (int r = r0 + threadIdx.x; r < rend; r += kFormThreads) {
-    const int i = L.mmap[r];
-    const int g = L.gmap[r];
+  for (int j = threadIdx.x; j < nti; j += kFormThreads) {
+    const int g = g0 + j;
     double b = 0.0;
     for (int k = 0; k < rom.Qf; ++k)
-      b = fma(thf[(int64_t)q * rom.Qf + k] * rom.Wf[(int64_t)k * n + g], rom.bhat[(int64_t)k * n_s + i], b);
+      b = fma(thf[(int64_t)q * rom.Qf + k] * rom.Wf[(int64_t)k * n + g], rom.bhat[(int64_t)k * rom.n_s + i], b);
     double u0 = 0.0;
-    for (int k = 0; k < rom.Q0; ++k) u0 = fma(th0[(int64_t)q * rom.Q0 + k], rom.u0hat[(int64_t)k * n_s + i], u0);
-    rhs[plan.coeff_off[q] + r] = fma(rom.P1[g], u0, b);
+    for (int k = 0; k < rom.Q0; ++k) u0 = fma(th0[(int64_t)q * rom.Q0 + k], rom.u0hat[(int64_t)k * rom.n_s + i], u0);
+    rhs[plan.coeff_off[q] + r0 + j] = fma(rom.P1[g], u0, b);
   }
 }
 
-// r = b - Ahat_st(mu) x for rows [r0, r0 + kFormRows) of each active query; one wave per row.
+// r = b - Ahat_st(mu) x for the rows of one mode of each active query, in groups
+// of kFormRows rows: per-thread partial sums over the thread's columns, then a
+// workgroup reduction per row in a fixed order.
 __global__ __launch_bounds__(kFormThreads) void residual_kernel(RomView rom, int32_t n_q,
                                                                 const double* __restrict__ thA,
                                                                 const int32_t* __restrict__ nt_q, Plan plan,
@@ -213,39 +275,69 @@ __global__ __launch_bounds__(kFormThreads) void residual_kernel(RomView rom, int
                                                                 const double* __restrict__ x, double* __restrict__ r,
                                                                 const int32_t* __restrict__ active, int32_t w_max) {
   extern __shared__ __align__(16) char lds[];
-  const int32_t q = blockIdx.y;
-  if (plan.info[q] != 0) return;
+  const ModeItem it = mode_item(rom.n_s);
+  const int32_t q = it.q, i = it.i;
+  if (q >= n_q || i >= rom.n_s || plan.info[q] != 0) return;
   if (active && !active[q]) return;
+  const int32_t nti = nt_q ? nt_q[(int64_t)q * rom.n_s + i] : rom.moff[i + 1] - rom.moff[i];
+  if (nti == 0) return;
   const int32_t w = plan.width[q];
-  const int32_t r0 = blockIdx.x * kFormRows;
-  if (r0 >= w) return;
   QueryLds L = carve_lds(lds, rom.n_s, w_max);
-  double* xs = reinterpret_cast<double*>(lds + ((query_lds_bytes(rom.n_s, w_max) + 15) / 16) * 16);
+  double* xs = reinterpret_cast<double*>(lds + query_lds_bytes(rom.n_s, w_max));
   const int64_t off = plan.coeff_off[q];
   for (int c = threadIdx.x; c < w; c += kFormThreads) xs[c] = x[off + c];
-  query_setup(rom, q, thA, nt_q, L);
-  const int n_s = rom.n_s;
+  query_setup(rom, q, i, thA, nt_q, L);
   const int64_t n = rom.n;
+  const int r0 = L.loff[i];
+  const int g0 = rom.moff[i];
+  const int ntf = rom.moff[i + 1] - g0;
+  const double* Ki = rom.K + rom.koff[i];
+  __shared__ double s_red[kFormThreads / 64][kResRows];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int rend = min(w, r0 + kFormRows);
-  for (int row = r0 + wave; row < rend; row += kFormThreads / 64) {
-    const int ir = L.mmap[row];
-    const int gr = L.gmap[row];
-    const int jr = gr - rom.moff[ir];
-    const double* Tcol = rom.T + (int64_t)gr * n;
-    const int ntr = rom.moff[ir + 1] - rom.moff[ir];
-    const double* Kr = rom.K + rom.koff[ir] + jr;
-    const double* Ahr = L.Ah + ir;
-    double acc = 0.0;
-    for (int c = lane; c < w; c += 64) {
-      const int ic = L.mmap[c];
-      const int gc = L.gmap[c];
-      double v = -Ahr[ic * n_s] * Tcol[gc];
-      if (ic == ir) v += Kr[(int64_t)(gc - rom.moff[ic]) * ntr];
-      acc = fma(v, xs[c], acc);
+  for (int jb = 0; jb < nti; jb += kResRows) {
+    const int nrow = min(kResRows, nti - jb);
+    double acc[kResRows];
+#pragma unroll
+    for (int rr = 0; rr < kResRows; ++rr) acc[rr] = 0.0;
+    for (int cb = threadIdx.x; cb < w; cb += kColChunk * kFormThreads) {
+      int ic[kColChunk], gc[kColChunk];
+      double xa[kColChunk], ah[kColChunk];
+#pragma unroll
+      for (int k = 0; k < kColChunk; ++k) {
+        const int c = cb + k * kFormThreads;
+        ic[k] = c < w ? L.mmap[c] : -1;
+        gc[k] = c < w ? L.gmap[c] : 0;
+        xa[k] = c < w ? xs[c] : 0.0;
+        ah[k] = c < w ? -L.Ah[ic[k]] : 0.0;
+      }
+#pragma unroll
+      for (int rr = 0; rr < kResRows; ++rr) {
+        const int j = jb + min(rr, nrow - 1);
+        const double* Trow = rom.T + (int64_t)(g0 + j) * n;
+        double sum = 0.0;
+#pragma unroll
+        for (int k = 0; k < kColChunk; ++k) {
+          const double t = ic[k] >= 0 ? Trow[gc[k]] : 0.0;
+          const double kv = ic[k] == i ? Ki[(int64_t)(gc[k] - g0) * ntf + j] : 0.0;
+          sum = fma(fma(ah[k], t, kv), xa[k], sum);
+        }
+        acc[rr] += rr < nrow ? sum : 0.0;
+      }
     }
-    acc = __ockl_wfred_add_f64(acc);
-    if (lane == 0) r[off + row] = rhs[off + row] - acc;
+#pragma unroll
+    for (int rr = 0; rr < kResRows; ++rr) {
+      const double t = __ockl_wfred_add_f64(acc[rr]);
+      if (lane == 0) s_red[wave][rr] = t;
+    }
+    __syncthreads();
+    if (threadIdx.x < nrow) {
+      const int rr = threadIdx.x;
+      double t = 0.0;
+      for (int wv = 0; wv < kFormThreads / 64; ++wv) t += s_red[wv][rr];
+      const int64_t o = off + r0 + jb + rr;
+      r[o] = rhs[o] - t;
+    }
+    __syncthreads();
   }
 }
 
@@ -278,17 +370,19 @@ __global__ void ir_check_kernel(int32_t n_q, Plan plan, const double* __restrict
     if (last && plan.info[q] != -2) relres[q] = __longlong_as_double(0x7ff8000000000000LL);
     return;
   }
+  // queries that converged during refinement keep the residual recorded then
+  if (!active[q]) return;
   const double bn = bnorm[q];
   const double rel = bn > 0.0 ? rnorm[q] / bn : rnorm[q];
   if (last) {
     relres[q] = rel;
-    if (iters && active[q]) iters[q] = step;
+    if (iters) iters[q] = step;
     if (tol > 0.0 && last > 1 && !(rel <= tol)) plan.info[q] = -1;
     return;
   }
-  if (!active[q]) return;
   if (rel <= tol) {
     active[q] = 0;
+    relres[q] = rel;
     if (iters) iters[q] = step;
   }
 }
@@ -390,7 +484,7 @@ hipError_t launch_form(const RomView& rom, int32_t n_q, const double* thA, const
                        hipStream_t s) {
   if (n_q == 0 || n_max == 0) return hipSuccess;
   const size_t lds = query_lds_bytes(rom.n_s, n_max);
-  dim3 grid((n_max + kFormRows - 1) / kFormRows, n_q);
+  dim3 grid(mode_grid(n_q, rom.n_s));
   if (out_prec == ST_F64) {
     hipError_t e = hipFuncSetAttribute((const void*)form_kernel<double>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -411,11 +505,11 @@ hipError_t launch_residual(const RomView& rom, int32_t n_q, const double* thA, c
                            const double* rhs, const double* x, double* r, double* rnorm, const int32_t* active,
                            int32_t n_max, hipStream_t s) {
   if (n_q == 0 || n_max == 0) return hipSuccess;
-  const size_t lds = ((query_lds_bytes(rom.n_s, n_max) + 15) / 16) * 16 + sizeof(double) * n_max;
+  const size_t lds = query_lds_bytes(rom.n_s, n_max) + sizeof(double) * n_max;
   hipError_t e = hipFuncSetAttribute((const void*)residual_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)lds);
   if (e != hipSuccess) return e;
-  dim3 grid((n_max + kFormRows - 1) / kFormRows, n_q);
+  dim3 grid(mode_grid(n_q, rom.n_s));
   hipLaunchKernelGGL(residual_kernel, grid, dim3(kFormThreads), lds, s, rom, n_q, thA, nt_q, plan, rhs, x, r, active,
                      n_max);
   if ((e = hipGetLastError()) != hipSuccess) return e;
