@@ -11,6 +11,8 @@
 // the NB x (w - p0 - NB) block row is solved against the unit lower panel
 // block, and the trailing matrix is updated on the matrix cores with
 // v_mfma_{f64,f32}_16x16x4 tiles.
+#include <type_traits>
+
 #include "internal.h"
 
 namespace strom {
@@ -322,6 +324,88 @@ __device__ __forceinline__ void block_row_solve(T* __restrict__ A, int w, int r0
   __syncthreads();
 }
 
+// Compile-time loop: f(std::integral_constant<int, I>) for I = B .. E-1.
+template <int B, int E, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (B < E) {
+    f(std::integral_constant<int, B>{});
+    static_for<B + 1, E>(f);
+  }
+}
+
+// Inverse of the unit lower triangular n x n block L (n <= NB, rows and columns
+// from n to NB treated as the identity) into X, both in LDS with leading
+// dimension ld; X is written in full (zeros above the diagonal).  Blocked in
+// 32 x 32 blocks: the diagonal blocks are inverted one per wave (lane j solves
+// for column j), then block row bi of the inverse follows from
+// X[bi][bj] = -X[bi][bi] * sum_{bj <= k < bi} L[bi][k] X[k][bj] for all bj < bi
+// at once, with the whole workgroup on the products.
+template <typename T, int NB>
+__device__ __noinline__ void unit_lower_inverse(const T* __restrict__ L, T* __restrict__ X, int ld, int n) {
+  constexpr int SB = 32, NSB = NB / SB;
+  constexpr int PER = (NSB > 1 ? (NSB - 1) * SB * SB : 1) / kLuThreads + 1;  // outputs per thread per block row
+  static_assert(NB % SB == 0 && NSB <= kLuWaves, "inverse blocking");
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  auto Lv = [&](int i, int k) -> T { return (i < n && k < n) ? L[i * ld + k] : T(0); };
+  // 1. diagonal blocks
+  if (wave < NSB && lane < SB) {
+    const int b0 = wave * SB, j = lane;
+    for (int i = 0; i < SB; ++i) {
+      T x = T(0);
+      if (i == j) {
+        x = T(1);
+      } else if (i > j) {
+        for (int k = j; k < i; ++k) x -= Lv(b0 + i, b0 + k) * X[(b0 + k) * ld + b0 + j];
+      }
+      X[(b0 + i) * ld + b0 + j] = x;
+    }
+  }
+  __syncthreads();
+  // 2. block rows below the diagonal
+  for (int bi = 1; bi < NSB; ++bi) {
+    const int cnt = bi * SB * SB;
+    // S[bi][bj] = sum_{bj <= k < bi} L[bi][k] X[k][bj], staged in the X[bi][bj] slots
+    for (int e = tid; e < cnt; e += kLuThreads) {
+      const int bj = e / (SB * SB), i = (e / SB) % SB, j = e % SB;
+      const int r = bi * SB + i, c = bj * SB + j;
+      T acc = T(0);
+      for (int k = bj * SB + j; k < bi * SB; ++k) acc += Lv(r, k) * X[k * ld + c];
+      X[r * ld + c] = acc;
+    }
+    __syncthreads();
+    T out[PER];
+#pragma unroll
+    for (int t = 0; t < PER; ++t) {
+      const int e = tid + t * kLuThreads;
+      out[t] = T(0);
+      if (e < cnt) {
+        const int bj = e / (SB * SB), i = (e / SB) % SB, j = e % SB;
+        const T* Dinv = X + (bi * SB + i) * ld + bi * SB;   // row i of X[bi][bi]
+        const T* Sc = X + (bi * SB) * ld + bj * SB + j;      // column j of S[bi][bj]
+        T acc = T(0);
+        for (int k = 0; k <= i; ++k) acc += Dinv[k] * Sc[k * ld];
+        out[t] = -acc;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < PER; ++t) {
+      const int e = tid + t * kLuThreads;
+      if (e < cnt) {
+        const int bj = e / (SB * SB), i = (e / SB) % SB, j = e % SB;
+        X[(bi * SB + i) * ld + bj * SB + j] = out[t];
+      }
+    }
+    __syncthreads();
+  }
+  // zeros above the diagonal blocks
+  for (int e = tid; e < NB * NB; e += kLuThreads) {
+    const int i = e / NB, j = e % NB;
+    if (j / SB > i / SB) X[i * ld + j] = T(0);
+  }
+  __syncthreads();
+}
+
 // One workgroup factors one query at a time (persistent, work queue).  Row r of
 // the query is owned by thread r % 512 in register slot r / 512 (R slots) while
 // its sub-panel is factored.  Pivoting is LAPACK-style partial pivoting; P[i]
@@ -338,9 +422,7 @@ __global__ __launch_bounds__(kLuThreads) void lu_kernel(int32_t n_q, Plan plan, 
   static_assert(NBO % NBI == 0 && NBI <= 32, "block shape");
   extern __shared__ __align__(16) unsigned char lds_raw[];
   T* pool = reinterpret_cast<T*>(lds_raw);
-  __shared__ T s_urow[2][NBI];
-  __shared__ T s_xrow[2][NBI];
-  __shared__ T s_umask[2][NBI];
+  __shared__ T s_cand[2][kLuWaves][NBI];
   __shared__ T s_redv[2][NW];
   __shared__ int32_t s_redr[2][NW];
   __shared__ int32_t s_piv[NBO];
@@ -378,116 +460,111 @@ __global__ __launch_bounds__(kLuThreads) void lu_kernel(int32_t n_q, Plan plan, 
 #pragma unroll
           for (int c = 0; c < NBI; ++c) v[s][c] = (live && c < nbi) ? A[(int64_t)r * w + i0 + c] : T(0);
         }
-        // Column steps with a rotating register row: before step c, slot k of
-        // a row holds sub-panel column (c + k) mod NBI, so the pivot column is
-        // always slot 0 and every register index is a compile-time constant.
-        // After the step the row rotates left by one; the eliminated value (the
-        // L multiplier, or the U entry of a pivot row) moves to the end, so after
-        // NBI rotations every row is back in column order.  Rows exchange whole
-        // register rows, i.e. the full sub-panel row as in LAPACK.
-        for (int c = 0; c < nbi; ++c) {
-          const int buf = c & 1;
+        // Column steps, unrolled at compile time so that every register index is a
+        // constant.  Pivoting is by index: a pivot row stays in its thread's registers
+        // and is only marked done; thread 0 tracks the LAPACK interchange sequence
+        // (position of every row of the panel, in LDS) and the rows are written to
+        // their final positions afterwards.
+        int32_t* pos_of = reinterpret_cast<int32_t*>(pool);   // row -> current position (offset i0)
+        int32_t* row_at = pos_of + (w - i0);                  // position -> row (offset i0)
+        for (int t = tid; t < w - i0; t += BLOCK) {
+          pos_of[t] = i0 + t;
+          row_at[t] = i0 + t;
+        }
+        bool done[R];
+#pragma unroll
+        for (int s = 0; s < R; ++s) done[s] = false;
+        static_for<0, NBI>([&](auto CC) {
+          constexpr int c = decltype(CC)::value;
+          if (c >= nbi) return;
+          constexpr int buf = c & 1;
           const int diag = i0 + c;
           T best = T(-1);
           int32_t brow = 0x7fffffff;
 #pragma unroll
           for (int s = 0; s < R; ++s) {
             const int r = tid + s * BLOCK;
-            if (r >= diag && r < w) {
-              const T a = v[s][0] < T(0) ? -v[s][0] : v[s][0];
+            if (r >= i0 && r < w && !done[s]) {
+              T a = v[s][c] < T(0) ? -v[s][c] : v[s][c];
+              a = a == a ? a : T(0);  // a NaN entry never wins over a number
               if (a > best) { best = a; brow = r; }
             }
           }
           const T wbest = wave_max(best);
           const int32_t wrow = __ockl_wfred_min_i32(best == wbest ? brow : 0x7fffffff);
+          // One barrier per column: every wave publishes its best value, row index and the
+          // whole candidate row.
           if (lane == 0) { s_redv[buf][wave] = wbest; s_redr[buf][wave] = wrow; }
+#pragma unroll
+          for (int s = 0; s < R; ++s) {
+            const int r = tid + s * BLOCK;
+            if (r == wrow) {
+#pragma unroll
+              for (int k = 0; k < NBI; ++k) s_cand[buf][wave][k] = v[s][k];
+            }
+          }
           __syncthreads();
-          best = s_redv[buf][0];
-          brow = s_redr[buf][0];
+          // all candidates are read first, then reduced branch-free
+          T cv[NW];
+          int32_t cr[NW];
+#pragma unroll
+          for (int k = 0; k < NW; ++k) {
+            cv[k] = s_redv[buf][k];
+            cr[k] = s_redr[buf][k];
+          }
+          best = cv[0];
+          brow = cr[0];
 #pragma unroll
           for (int k = 1; k < NW; ++k) {
-            const T ob = s_redv[buf][k];
-            const int32_t orow = s_redr[buf][k];
-            if (ob > best || (ob == best && orow < brow)) { best = ob; brow = orow; }
+            const bool bt = cv[k] > best || (cv[k] == best && cr[k] < brow);
+            best = bt ? cv[k] : best;
+            brow = bt ? cr[k] : brow;
           }
-          int32_t prow = brow;
-          if (!(best > T(0))) {  // exactly zero (or no finite) pivot: keep the row, record the step
-            prow = diag;
-            if (zero_piv == 0) zero_piv = diag + 1;
-          }
-          const int live = nbi - c;  // slots 0..live-1 hold columns not yet eliminated
+          const int32_t prow = brow;  // a live row: every live entry compares >= 0 > -1
+          // the winning row belongs to thread prow % BLOCK, i.e. to wave (prow % BLOCK) / 64
+          const T* urow = s_cand[buf][(prow & (BLOCK - 1)) >> 6];
+          if (!(best > T(0)) && zero_piv == 0) zero_piv = diag + 1;  // exactly zero pivot
 #pragma unroll
-          for (int s = 0; s < R; ++s) {
-            const int r = tid + s * BLOCK;
-            if (r == prow) {
-#pragma unroll
-              for (int k = 0; k < NBI; ++k) {
-                s_urow[buf][k] = v[s][k];
-                s_umask[buf][k] = k < live ? v[s][k] : T(0);
-              }
-            }
-            if (r == diag) {
-#pragma unroll
-              for (int k = 0; k < NBI; ++k) s_xrow[buf][k] = v[s][k];
-            }
-          }
-          __syncthreads();
-#pragma unroll
-          for (int s = 0; s < R; ++s) {
-            const int r = tid + s * BLOCK;
-            if (r == diag) {
-#pragma unroll
-              for (int k = 0; k < NBI; ++k) v[s][k] = s_urow[buf][k];
-            } else if (r == prow) {
-#pragma unroll
-              for (int k = 0; k < NBI; ++k) v[s][k] = s_xrow[buf][k];
-            }
-          }
+          for (int s = 0; s < R; ++s)
+            if (tid + s * BLOCK == prow) done[s] = true;
           if (tid == 0) {
-            s_piv[diag - p0] = prow;
-            P[diag] = prow;
+            // LAPACK pivot index: the current position of the pivot row; then exchange
+            // the contents of that position and of position diag
+            const int pp = pos_of[prow - i0];
+            const int other = row_at[c];
+            s_piv[diag - p0] = pp;
+            P[diag] = pp;
+            row_at[pp - i0] = other;
+            pos_of[other - i0] = pp;
+            row_at[c] = prow;
+            pos_of[prow - i0] = diag;
           }
-          const T d = s_urow[buf][0];
+          const T d = urow[c];
           const T inv = (d != T(0)) ? T(1) / d : T(0);
           T um[NBI];
 #pragma unroll
-          for (int k = 1; k < NBI; ++k) um[k] = s_umask[buf][k];
+          for (int k = c + 1; k < NBI; ++k) um[k] = urow[k];
 #pragma unroll
           for (int s = 0; s < R; ++s) {
             if (s * BLOCK >= w) continue;  // slot empty for every thread (uniform)
             const int r = tid + s * BLOCK;
-            if (r > diag && r < w) {
-              const T l = v[s][0] * inv;
-              v[s][0] = l;
+            if (r >= i0 && r < w && !done[s]) {
+              const T l = v[s][c] * inv;
+              v[s][c] = l;
 #pragma unroll
-              for (int k = 1; k < NBI; ++k) v[s][k] -= l * um[k];
-            }
-#pragma unroll
-            for (int k = 0; k + 1 < NBI; ++k) {
-              const T t = v[s][k];
-              v[s][k] = v[s][k + 1];
-              v[s][k + 1] = t;
+              for (int k = c + 1; k < NBI; ++k) v[s][k] -= l * um[k];
             }
           }
-        }
-        // complete the NBI rotations when the sub-panel is narrower than NBI
-        for (int c = nbi; c < NBI; ++c) {
-#pragma unroll
-          for (int s = 0; s < R; ++s)
-#pragma unroll
-            for (int k = 0; k + 1 < NBI; ++k) {
-              const T t = v[s][k];
-              v[s][k] = v[s][k + 1];
-              v[s][k + 1] = t;
-            }
-        }
+        });
+        __syncthreads();
 #pragma unroll
         for (int s = 0; s < R; ++s) {
           const int r = tid + s * BLOCK;
           if (r >= i0 && r < w) {
+            const int64_t dst = pos_of[r - i0];
 #pragma unroll
             for (int c = 0; c < NBI; ++c)
-              if (c < nbi) A[(int64_t)r * w + i0 + c] = v[s][c];
+              if (c < nbi) A[dst * w + i0 + c] = v[s][c];
           }
         }
         __syncthreads();
@@ -519,16 +596,7 @@ __global__ __launch_bounds__(kLuThreads) void lu_kernel(int32_t n_q, Plan plan, 
           L11[i * LDL + k] = A[(int64_t)(p0 + i) * w + p0 + k];
         }
         __syncthreads();
-        for (int j = tid; j < NBO; j += BLOCK) {
-          for (int i = 0; i < NBO; ++i) {
-            T x = T(0);
-            if (i == j) x = T(1);
-            else if (i > j && i < nbo)
-              for (int k = j; k < i; ++k) x -= L11[i * LDL + k] * Linv[k * LDL + j];
-            Linv[i * LDL + j] = x;
-          }
-        }
-        __syncthreads();
+        unit_lower_inverse<T, NBO>(L11, Linv, LDL, nbo);
         typedef typename Mfma<T>::v4 v4;
         const int li = lane & 15, lk = lane >> 4;
         const int n2 = w - c0;
