@@ -129,6 +129,14 @@ def main():
         offline()
         online(strom.ST_F32, b32)
 
+    # ------------------------------------------------------------- LU autotuning (once, before the steps)
+    offline()
+    tune = {}
+    for name, prec, bufs in (("fp32", strom.ST_F32, b32), ("fp64", strom.ST_F64, b64)):
+        choice, ms = strom.st_autotune(desc, state["rom"], dA, None, d0, ntd, prec, bufs=bufs)
+        tune[name] = {"choice": choice, "lu_ms_per_variant": ms}
+    print(f"[bench] LU autotune: {json.dumps(tune)}", file=sys.stderr, flush=True)
+
     # ------------------------------------------------------------- warmup + timed steps
     strom.st_timing_enable(True)
     for _ in range(args.warmup):
@@ -162,6 +170,23 @@ def main():
     print(f"[bench] {K} steps: {ms_per_step:.2f} ms/step (offline {off_ms / K:.2f} ms, online {on_ms / K:.2f} ms), "
           f"{ok32}/{nq} certified; phases {json.dumps({k: round(v, 3) for k, v in phases32.items()})}",
           file=sys.stderr, flush=True)
+
+    # ------------------------------------------------------------- the same steps replayed from HIP graphs
+    strom.st_timing_enable(False)
+    strom.st_graph_enable(True)
+    step()  # records the solve graph (eager run)
+    torch.cuda.synchronize()
+    t_g = time.perf_counter()
+    for _ in range(K):
+        offline()
+        online(strom.ST_F32, b32)
+    torch.cuda.synchronize()
+    graph_ms = 1e3 * (time.perf_counter() - t_g) / K
+    ok_graph = int(np.sum((b32.info.cpu().numpy()[:nq] == 0) & (b32.relres.cpu().numpy()[:nq] <= IR_TOL)))
+    strom.st_graph_enable(False)
+    strom.st_graph_reset()
+    strom.st_timing_enable(True)
+    print(f"[bench] graph replay: {graph_ms:.2f} ms/step, {ok_graph}/{nq} certified", file=sys.stderr, flush=True)
 
     # ------------------------------------------------------------- plain FP64 online path (same ROM)
     for _ in range(1):
@@ -247,6 +272,9 @@ def main():
         "breakdown_ms": {"offline_pod_assemble": off_ms / K, "online_fp32_ir": on_ms / K,
                          "st_solve_phases_fp32": phases32,
                          "st_solve_phases_fp64": {k: v / K for k, v in ph64.items()}},
+        "graph_replay": {"ms_per_step": graph_ms, "certified": ok_graph,
+                         "queries_per_s": ok_graph / (graph_ms * 1e-3)},
+        "lu_autotune": tune,
         "online_only_qps": {"fp32_ir": ok32 / (on_ms / K * 1e-3),
                             "fp64": int(np.sum(info64 == 0)) / (f64_ms * 1e-3)},
         "accuracy": accuracy,

@@ -336,6 +336,42 @@ st_status st_surrogate_check(const st_rom_desc* d, const void* rom, int32_t n_q,
 st_status st_timing_enable(int32_t on);
 int32_t st_timing_read(double* ms, int32_t cap);
 
+/* ========================================================================
+ * HIP graph replay of st_solve.  After st_graph_enable(1), the first st_solve
+ * call with a given set of arguments runs eagerly and records its whole launch
+ * sequence as a HIP graph; later calls with the same arguments (the
+ * description by value; every pointer, size, precision and tolerance; and the
+ * LU variant in use) replay it with one hipGraphLaunch on the caller's stream.
+ * The data behind the pointers may change between calls; the buffers must stay
+ * allocated while a graph using them is cached (st_graph_reset destroys every
+ * cached graph).  Graphs are bypassed while phase timing is on.  The cache is
+ * guarded by a mutex; st_graph_count returns its size.
+ * ====================================================================== */
+st_status st_graph_enable(int32_t on);
+st_status st_graph_reset(void);
+int32_t st_graph_count(void);
+
+/* ========================================================================
+ * LU autotuner.  st_autotune times every batched-LU configuration (register
+ * sub-panel widths) on the given batch, forming the systems afresh before each,
+ * records the fastest for the batch's LU precision and width class (total
+ * reduced width n <= 1536, or n <= 4096) and st_solve uses it from then on.
+ * Arguments as st_solve, with the same workspace size; coeff_off and info
+ * receive the plan, while coeff and the workspace are used as scratch (no
+ * solution is produced).  choice [host, may be NULL] receives the chosen
+ * variant, ms [host, may be NULL, >= ST_LU_VARIANTS entries] each candidate's
+ * time.  Synchronises the stream.
+ * st_autotune_choice returns the recorded variant for (lu_prec, n), -1 if
+ * none (variant 0 is then used); st_autotune_set records one directly.
+ * ====================================================================== */
+#define ST_LU_VARIANTS 2
+st_status st_autotune(const st_rom_desc* d, const void* rom, int32_t n_q, const double* theta_A,
+                      const double* theta_f, const double* theta_0, const int32_t* nt_q, int32_t lu_prec,
+                      double* coeff, int64_t coeff_cap, int64_t* coeff_off, double* relres, int32_t* info, void* ws,
+                      size_t ws_bytes, void* stream, int32_t* choice, double* ms);
+int32_t st_autotune_choice(int32_t lu_prec, int32_t n);
+st_status st_autotune_set(int32_t lu_prec, int32_t n, int32_t variant);
+
 #ifdef __cplusplus
 }
 #endif

@@ -4,6 +4,11 @@
 #include <math.h>
 #include <string.h>
 
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <vector>
+
 #include "internal.h"
 
 using namespace strom;
@@ -284,6 +289,177 @@ size_t st_solve_workspace(const st_rom_desc* d, int32_t n_q, int64_t sum_w, int6
   return o;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Arguments of one st_solve call (validated), in the form the launch sequence needs.
+struct SolveArgs {
+  const st_rom_desc* d;
+  const void* rom;
+  int32_t n_q;
+  const double *thA, *thf, *th0;
+  const int32_t *nt_q, *skip;
+  int32_t lu_prec;
+  double ir_tol;
+  int32_t ir_max;
+  double* coeff;
+  int64_t coeff_cap;
+  int64_t* coeff_off;
+  double* relres;
+  int32_t* info;
+  int32_t* iters;
+  void* ws;
+  size_t ws_bytes;
+};
+
+// Workspace sections of st_solve.
+struct SolveWs {
+  Plan plan;
+  int32_t* active;
+  double *bnorm, *rnorm, *b, *r;
+  int32_t* perm;
+  void* mats;
+};
+
+SolveWs solve_ws(const SolveArgs& a) {
+  const size_t el = a.lu_prec == ST_F32 ? sizeof(float) : sizeof(double);
+  Carver c(a.ws);
+  SolveWs w;
+  w.plan.width = c.take<int32_t>(a.n_q);
+  w.plan.order = c.take<int32_t>(a.n_q);
+  w.plan.counter = c.take<int32_t>(4);
+  w.active = c.take<int32_t>(a.n_q);
+  w.plan.mat_off = c.take<int64_t>(a.n_q + 1);
+  w.bnorm = c.take<double>(a.n_q);
+  w.rnorm = c.take<double>(a.n_q);
+  w.b = c.take<double>(a.coeff_cap);
+  w.r = c.take<double>(a.coeff_cap);
+  w.perm = c.take<int32_t>(a.coeff_cap);
+  w.mats = c.base + c.used;
+  w.plan.coeff_off = a.coeff_off;
+  w.plan.info = a.info;
+  (void)el;
+  return w;
+}
+
+int64_t solve_mats_cap(const SolveArgs& a) {
+  const size_t el = a.lu_prec == ST_F32 ? sizeof(float) : sizeof(double);
+  const size_t fixed = st_solve_workspace(a.d, a.n_q, a.coeff_cap, 0, a.lu_prec);
+  return (int64_t)((a.ws_bytes - fixed) / el);
+}
+
+// Autotuned LU variant per (precision, width class); -1 = not tuned (variant 0).
+std::mutex g_tune_mu;
+int g_lu_choice[2][2] = {{-1, -1}, {-1, -1}};
+
+int width_class(int32_t n_max) { return n_max <= 3 * 512 ? 0 : 1; }
+
+int lu_choice(int32_t prec, int32_t n_max) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  const int c = g_lu_choice[prec == ST_F32 ? 1 : 0][width_class(n_max)];
+  return c < 0 ? 0 : c;
+}
+
+// The whole launch sequence of st_solve on stream s.
+hipError_t solve_launches(const SolveArgs& a, hipStream_t s) {
+  const RomView rv = view_of(a.d, a.rom);
+  SolveWs w = solve_ws(a);
+  Plan plan = w.plan;
+  const int32_t n_max = (int32_t)total_nt(a.d);
+  const int32_t n_q = a.n_q;
+  const int variant = lu_choice(a.lu_prec, n_max);
+  hipError_t e;
+#define SL_TRY(expr)                 \
+  do {                               \
+    if ((e = (expr)) != hipSuccess) return e; \
+  } while (0)
+  SL_TRY(mark(0, s));
+  SL_TRY(launch_plan(n_q, a.d->n_s, rv.moff, a.nt_q, a.skip, a.thA, a.thf, a.th0, a.d->Q, a.d->Qf, a.d->Q0,
+                     a.coeff_cap, solve_mats_cap(a), plan, s));
+  SL_TRY(mark(1, s));
+  SL_TRY(launch_form(rv, n_q, a.thA, a.thf, a.th0, a.nt_q, plan, a.lu_prec, w.mats, w.b, n_max, s));
+  SL_TRY(mark(2, s));
+  SL_TRY(launch_vec_norms(n_q, plan, w.b, w.bnorm, s));
+  SL_TRY(mark(3, s));
+  SL_TRY(launch_lu(n_q, plan, a.lu_prec, w.mats, w.perm, n_max, variant, s));
+  SL_TRY(mark(4, s));
+  SL_TRY(launch_fill_i32(w.active, n_q, 1, s));
+  SL_TRY(launch_lu_solve(n_q, plan, a.lu_prec, w.mats, w.perm, w.b, a.coeff, 0, w.active, n_max, s));
+  SL_TRY(mark(5, s));
+  for (int it = 0; it < a.ir_max; ++it) {
+    SL_TRY(launch_residual(rv, n_q, a.thA, a.nt_q, plan, w.b, a.coeff, w.r, w.rnorm, w.active, n_max, s));
+    SL_TRY(launch_ir_check(n_q, plan, w.rnorm, w.bnorm, a.ir_tol, it, 0, w.active, a.relres, a.iters, s));
+    SL_TRY(launch_lu_solve(n_q, plan, a.lu_prec, w.mats, w.perm, w.r, a.coeff, 1, w.active, n_max, s));
+  }
+  SL_TRY(mark(6, s));
+  // final residual of the queries still active (all of them without refinement)
+  SL_TRY(launch_residual(rv, n_q, a.thA, a.nt_q, plan, w.b, a.coeff, w.r, w.rnorm, w.active, n_max, s));
+  const int flag = (a.lu_prec == ST_F32 || a.ir_max > 0) ? 2 : 1;
+  SL_TRY(launch_ir_check(n_q, plan, w.rnorm, w.bnorm, a.ir_tol, a.ir_max, flag, w.active, a.relres, a.iters, s));
+  SL_TRY(launch_finalize(n_q, plan, a.coeff, a.info, s));
+  SL_TRY(mark(7, s));
+#undef SL_TRY
+  return hipSuccess;
+}
+
+// ---------------------------------------------------------------------------
+// HIP graph cache of st_solve launch sequences, keyed by every argument (the
+// description by value, buffers by address) and the LU variant in use.
+// ---------------------------------------------------------------------------
+bool g_graph = false;
+std::mutex g_graph_mu;
+std::map<std::vector<uint64_t>, hipGraphExec_t> g_graphs;
+hipStream_t g_capture_stream = nullptr;
+
+std::vector<uint64_t> graph_key(const SolveArgs& a, int device) {
+  std::vector<uint64_t> k;
+  auto put = [&](uint64_t v) { k.push_back(v); };
+  auto ptr = [&](const void* p) { put((uint64_t)(uintptr_t)p); };
+  put((uint64_t)device);
+  put((uint64_t)a.d->n_s); put((uint64_t)a.d->N_t); put((uint64_t)a.d->Q); put((uint64_t)a.d->Qf);
+  put((uint64_t)a.d->Q0);
+  for (int i = 0; i < a.d->n_s; ++i) put((uint64_t)a.d->n_t[i]);
+  ptr(a.rom); put((uint64_t)a.n_q); ptr(a.thA); ptr(a.thf); ptr(a.th0); ptr(a.nt_q); ptr(a.skip);
+  put((uint64_t)a.lu_prec);
+  uint64_t tb;
+  memcpy(&tb, &a.ir_tol, sizeof(tb));
+  put(tb); put((uint64_t)a.ir_max);
+  ptr(a.coeff); put((uint64_t)a.coeff_cap); ptr(a.coeff_off); ptr(a.relres); ptr(a.info); ptr(a.iters); ptr(a.ws);
+  put((uint64_t)a.ws_bytes);
+  put((uint64_t)lu_choice(a.lu_prec, (int32_t)total_nt(a.d)));
+  return k;
+}
+
+// Record the launch sequence as a graph (on the library's capture stream; the
+// kernels are not run) and instantiate it.
+hipError_t capture_solve(const SolveArgs& a, hipGraphExec_t* exec) {
+  hipError_t e;
+  if (!g_capture_stream && (e = hipStreamCreateWithFlags(&g_capture_stream, hipStreamNonBlocking)) != hipSuccess)
+    return e;
+  if ((e = hipStreamBeginCapture(g_capture_stream, hipStreamCaptureModeRelaxed)) != hipSuccess) return e;
+  g_capturing = true;
+  const hipError_t le = solve_launches(a, g_capture_stream);
+  g_capturing = false;
+  hipGraph_t graph = nullptr;
+  e = hipStreamEndCapture(g_capture_stream, &graph);
+  if (le != hipSuccess || e != hipSuccess) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return le != hipSuccess ? le : e;
+  }
+  e = hipGraphInstantiate(exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  return e;
+}
+
+}  // namespace
+
+namespace strom {
+bool g_capturing = false;
+}  // namespace strom
+
+extern "C" {
+
 st_status st_solve(const st_rom_desc* d, const void* rom, int32_t n_q, const double* theta_A, const double* theta_f,
                    const double* theta_0, const int32_t* nt_q, const int32_t* skip, int32_t lu_prec, double ir_tol,
                    int32_t ir_max,
@@ -299,54 +475,119 @@ st_status st_solve(const st_rom_desc* d, const void* rom, int32_t n_q, const dou
   if (n > kMaxWidth) return ST_EUNSUPPORTED;
   const size_t fixed = st_solve_workspace(d, n_q, coeff_cap, 0, lu_prec);
   if (ws_bytes < fixed) return ST_EWORKSPACE;
-  const size_t el = lu_prec == ST_F32 ? sizeof(float) : sizeof(double);
   hipStream_t s = static_cast<hipStream_t>(stream);
-  RomView rv = view_of(d, rom);
-
-  Carver c(ws);
-  Plan plan;
-  plan.width = c.take<int32_t>(n_q);
-  plan.order = c.take<int32_t>(n_q);
-  plan.counter = c.take<int32_t>(4);
-  int32_t* active = c.take<int32_t>(n_q);
-  plan.mat_off = c.take<int64_t>(n_q + 1);
-  double* bnorm = c.take<double>(n_q);
-  double* rnorm = c.take<double>(n_q);
-  double* b = c.take<double>(coeff_cap);
-  double* r = c.take<double>(coeff_cap);
-  int32_t* perm = c.take<int32_t>(coeff_cap);
-  void* mats = c.base + c.used;
-  const int64_t mats_cap = (int64_t)((ws_bytes - c.used) / el);
-  plan.coeff_off = coeff_off;
-  plan.info = info;
-  const int32_t n_max = (int32_t)n;
-
-  ST_TRY(mark(0, s));
-  ST_TRY(launch_plan(n_q, d->n_s, rv.moff, nt_q, skip, theta_A, theta_f, theta_0, d->Q, d->Qf, d->Q0, coeff_cap,
-                     mats_cap, plan, s));
-  ST_TRY(mark(1, s));
-  ST_TRY(launch_form(rv, n_q, theta_A, theta_f, theta_0, nt_q, plan, lu_prec, mats, b, n_max, s));
-  ST_TRY(mark(2, s));
-  ST_TRY(launch_vec_norms(n_q, plan, b, bnorm, s));
-  ST_TRY(mark(3, s));
-  ST_TRY(launch_lu(n_q, plan, lu_prec, mats, perm, n_max, s));
-  ST_TRY(mark(4, s));
-  ST_TRY(launch_fill_i32(active, n_q, 1, s));
-  ST_TRY(launch_lu_solve(n_q, plan, lu_prec, mats, perm, b, coeff, 0, active, n_max, s));
-  ST_TRY(mark(5, s));
-  for (int it = 0; it < ir_max; ++it) {
-    ST_TRY(launch_residual(rv, n_q, theta_A, nt_q, plan, b, coeff, r, rnorm, active, n_max, s));
-    ST_TRY(launch_ir_check(n_q, plan, rnorm, bnorm, ir_tol, it, 0, active, relres, iters, s));
-    ST_TRY(launch_lu_solve(n_q, plan, lu_prec, mats, perm, r, coeff, 1, active, n_max, s));
+  const SolveArgs a{d, rom, n_q, theta_A, theta_f, theta_0, nt_q, skip, lu_prec, ir_tol, ir_max,
+                    coeff, coeff_cap, coeff_off, relres, info, iters, ws, ws_bytes};
+  if (!g_graph || g_timing) {
+    ST_TRY(solve_launches(a, s));
+    if (g_timing) g_timing_recorded = true;
+    return ST_OK;
   }
-  ST_TRY(mark(6, s));
-  // final residual of the queries still active (all of them without refinement)
-  ST_TRY(launch_residual(rv, n_q, theta_A, nt_q, plan, b, coeff, r, rnorm, active, n_max, s));
-  const int flag = (lu_prec == ST_F32 || ir_max > 0) ? 2 : 1;
-  ST_TRY(launch_ir_check(n_q, plan, rnorm, bnorm, ir_tol, ir_max, flag, active, relres, iters, s));
-  ST_TRY(launch_finalize(n_q, plan, coeff, info, s));
-  ST_TRY(mark(7, s));
-  if (g_timing) g_timing_recorded = true;
+  int device = 0;
+  ST_TRY(hipGetDevice(&device));
+  const std::vector<uint64_t> key = graph_key(a, device);
+  std::lock_guard<std::mutex> lk(g_graph_mu);
+  auto it = g_graphs.find(key);
+  if (it != g_graphs.end()) {
+    ST_TRY(hipGraphLaunch(it->second, s));
+    return ST_OK;
+  }
+  // first call with these arguments: run eagerly, then record the graph for the next ones
+  ST_TRY(solve_launches(a, s));
+  hipGraphExec_t exec = nullptr;
+  ST_TRY(capture_solve(a, &exec));
+  g_graphs.emplace(key, exec);
+  return ST_OK;
+}
+
+st_status st_graph_enable(int32_t on) {
+  g_graph = on != 0;
+  return ST_OK;
+}
+
+st_status st_graph_reset(void) {
+  std::lock_guard<std::mutex> lk(g_graph_mu);
+  for (auto& kv : g_graphs) (void)hipGraphExecDestroy(kv.second);
+  g_graphs.clear();
+  return ST_OK;
+}
+
+int32_t st_graph_count(void) {
+  std::lock_guard<std::mutex> lk(g_graph_mu);
+  return (int32_t)g_graphs.size();
+}
+
+st_status st_autotune(const st_rom_desc* d, const void* rom, int32_t n_q, const double* theta_A,
+                      const double* theta_f, const double* theta_0, const int32_t* nt_q, int32_t lu_prec,
+                      double* coeff, int64_t coeff_cap, int64_t* coeff_off, double* relres, int32_t* info, void* ws,
+                      size_t ws_bytes, void* stream, int32_t* choice, double* ms) {
+  if (!query_args_ok(d, rom, n_q, theta_A, theta_f, theta_0)) return ST_EINVAL;
+  if (lu_prec != ST_F64 && lu_prec != ST_F32) return ST_EINVAL;
+  if (d->n_s > kMaxFormModes) return ST_EUNSUPPORTED;
+  if (n_q == 0) return ST_OK;
+  if (!coeff || !coeff_off || !relres || !info || !ws || coeff_cap < 0) return ST_EINVAL;
+  const int64_t n = total_nt(d);
+  if (n > kMaxWidth) return ST_EUNSUPPORTED;
+  if (ws_bytes < st_solve_workspace(d, n_q, coeff_cap, 0, lu_prec)) return ST_EWORKSPACE;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const SolveArgs a{d, rom, n_q, theta_A, theta_f, theta_0, nt_q, nullptr, lu_prec, 0.0, 0,
+                    coeff, coeff_cap, coeff_off, relres, info, nullptr, ws, ws_bytes};
+  const RomView rv = view_of(d, rom);
+  SolveWs w = solve_ws(a);
+  const int32_t n_max = (int32_t)n;
+  const int nv = lu_variant_count(lu_prec, n_max);
+  if (nv <= 0) return ST_EUNSUPPORTED;
+  hipEvent_t e0, e1;
+  ST_TRY(hipEventCreate(&e0));
+  ST_TRY(hipEventCreate(&e1));
+  int best = 0;
+  float best_ms = 0.f;
+  st_status st = ST_OK;
+  for (int v = 0; v < nv && st == ST_OK; ++v) {
+    // each candidate factors freshly formed systems (the LU works in place); the
+    // plan's work-queue counter is reset by re-running the plan
+    if (launch_plan(n_q, d->n_s, rv.moff, nt_q, nullptr, theta_A, theta_f, theta_0, d->Q, d->Qf, d->Q0, coeff_cap,
+                    solve_mats_cap(a), w.plan, s) != hipSuccess ||
+        launch_form(rv, n_q, theta_A, theta_f, theta_0, nt_q, w.plan, lu_prec, w.mats, w.b, n_max, s) != hipSuccess ||
+        hipEventRecord(e0, s) != hipSuccess ||
+        launch_lu(n_q, w.plan, lu_prec, w.mats, w.perm, n_max, v, s) != hipSuccess ||
+        hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+      st = ST_EDEVICE;
+      break;
+    }
+    float t = 0.f;
+    if (hipEventElapsedTime(&t, e0, e1) != hipSuccess) {
+      st = ST_EDEVICE;
+      break;
+    }
+    if (ms) ms[v] = (double)t;
+    if (v == 0 || t < best_ms) {
+      best = v;
+      best_ms = t;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st != ST_OK) return st;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_lu_choice[lu_prec == ST_F32 ? 1 : 0][width_class(n_max)] = best;
+  }
+  if (choice) *choice = best;
+  return ST_OK;
+}
+
+int32_t st_autotune_choice(int32_t lu_prec, int32_t n) {
+  if ((lu_prec != ST_F64 && lu_prec != ST_F32) || n < 0 || n > kMaxWidth) return ST_EINVAL;
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  return g_lu_choice[lu_prec == ST_F32 ? 1 : 0][width_class(n)];
+}
+
+st_status st_autotune_set(int32_t lu_prec, int32_t n, int32_t variant) {
+  if ((lu_prec != ST_F64 && lu_prec != ST_F32) || n < 0 || n > kMaxWidth) return ST_EINVAL;
+  if (variant < -1 || variant >= ST_LU_VARIANTS) return ST_EINVAL;
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_lu_choice[lu_prec == ST_F32 ? 1 : 0][width_class(n)] = variant;
   return ST_OK;
 }
 

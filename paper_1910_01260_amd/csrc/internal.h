@@ -111,7 +111,13 @@ hipError_t launch_residual(const RomView& rom, int32_t n_q, const double* thA, c
                            int32_t n_max, hipStream_t s);
 
 // k_lu.hip: batched LU (a8) and triangular solves
-hipError_t launch_lu(int32_t n_q, Plan plan, int32_t prec, void* mats, int32_t* piv, int32_t n_max, hipStream_t s);
+int lu_variant_count(int32_t prec, int32_t n_max);
+hipError_t launch_lu(int32_t n_q, Plan plan, int32_t prec, void* mats, int32_t* piv, int32_t n_max, int variant,
+                     hipStream_t s);
+
+// True while st_solve records its launches into a HIP graph: launchers then skip
+// hipFuncSetAttribute (set on the eager run that precedes every capture).
+extern bool g_capturing;
 // x (or x += solution when accumulate) for every active query: solve LU x = b
 hipError_t launch_lu_solve(int32_t n_q, Plan plan, int32_t prec, const void* mats, const int32_t* piv, const double* b,
                            double* x, int accumulate, const int32_t* active, int32_t n_max, hipStream_t s);

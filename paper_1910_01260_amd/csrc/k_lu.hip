@@ -776,9 +776,11 @@ int device_cus() {
 template <typename T, int R, int NBI>
 hipError_t lu_go(int32_t n_q, Plan plan, void* mats, int32_t* piv, hipStream_t s) {
   const size_t lds = sizeof(T) * lu_pool_elems<T>();
-  hipError_t e = hipFuncSetAttribute((const void*)lu_kernel<T, R, NBI>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     (int)lds);
-  if (e != hipSuccess) return e;
+  if (!g_capturing) {
+    const hipError_t e = hipFuncSetAttribute((const void*)lu_kernel<T, R, NBI>,
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
   const int grid = max(1, min(n_q, device_cus()));
   hipLaunchKernelGGL((lu_kernel<T, R, NBI>), dim3(grid), dim3(kLuThreads), lds, s, n_q, plan, (T*)mats, piv);
   return hipGetLastError();
@@ -786,15 +788,26 @@ hipError_t lu_go(int32_t n_q, Plan plan, void* mats, int32_t* piv, hipStream_t s
 
 }  // namespace
 
-hipError_t launch_lu(int32_t n_q, Plan plan, int32_t prec, void* mats, int32_t* piv, int32_t n_max, hipStream_t s) {
+// Register-panel configurations (R row slots per thread, NBI-wide sub-panels):
+// variant 0 is the widest sub-panel that fits the registers, variant 1 a
+// narrower one (fewer registers, more sub-panels per block).  Which is faster
+// depends on the widths of the batch; the autotuner times both.
+int lu_variant_count(int32_t prec, int32_t n_max) {
+  (void)prec;
+  return n_max <= 8 * kLuThreads ? 2 : 0;
+}
+
+hipError_t launch_lu(int32_t n_q, Plan plan, int32_t prec, void* mats, int32_t* piv, int32_t n_max, int variant,
+                     hipStream_t s) {
   if (n_q == 0) return hipSuccess;
+  const bool f64 = prec == ST_F64;
   if (n_max <= 3 * kLuThreads) {
-    if (prec == ST_F64) return lu_go<double, 3, 16>(n_q, plan, mats, piv, s);
-    return lu_go<float, 3, 32>(n_q, plan, mats, piv, s);
+    if (variant == 1) return f64 ? lu_go<double, 3, 8>(n_q, plan, mats, piv, s) : lu_go<float, 3, 16>(n_q, plan, mats, piv, s);
+    return f64 ? lu_go<double, 3, 16>(n_q, plan, mats, piv, s) : lu_go<float, 3, 32>(n_q, plan, mats, piv, s);
   }
   if (n_max <= 8 * kLuThreads) {
-    if (prec == ST_F64) return lu_go<double, 8, 8>(n_q, plan, mats, piv, s);
-    return lu_go<float, 8, 16>(n_q, plan, mats, piv, s);
+    if (variant == 1) return f64 ? lu_go<double, 8, 4>(n_q, plan, mats, piv, s) : lu_go<float, 8, 8>(n_q, plan, mats, piv, s);
+    return f64 ? lu_go<double, 8, 8>(n_q, plan, mats, piv, s) : lu_go<float, 8, 16>(n_q, plan, mats, piv, s);
   }
   return hipErrorInvalidValue;
 }
@@ -803,10 +816,12 @@ hipError_t launch_lu_solve(int32_t n_q, Plan plan, int32_t prec, const void* mat
                            double* x, int accumulate, const int32_t* active, int32_t n_max, hipStream_t s) {
   if (n_q == 0) return hipSuccess;
   const size_t lds = sizeof(double) * (size_t)n_max;
-  hipError_t e = hipFuncSetAttribute(prec == ST_F64 ? (const void*)lu_solve_kernel<double>
-                                                    : (const void*)lu_solve_kernel<float>,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  if (e != hipSuccess) return e;
+  if (!g_capturing) {
+    const hipError_t e = hipFuncSetAttribute(prec == ST_F64 ? (const void*)lu_solve_kernel<double>
+                                                            : (const void*)lu_solve_kernel<float>,
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
   if (prec == ST_F64) {
     hipLaunchKernelGGL(lu_solve_kernel<double>, dim3(n_q), dim3(kSolveThreads), lds, s, n_q, plan,
                        (const double*)mats, piv, b, x, accumulate, active);

@@ -486,15 +486,19 @@ hipError_t launch_form(const RomView& rom, int32_t n_q, const double* thA, const
   const size_t lds = query_lds_bytes(rom.n_s, n_max);
   dim3 grid(mode_grid(n_q, rom.n_s));
   if (out_prec == ST_F64) {
-    hipError_t e = hipFuncSetAttribute((const void*)form_kernel<double>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
+    if (!g_capturing) {
+      const hipError_t e = hipFuncSetAttribute((const void*)form_kernel<double>,
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      if (e != hipSuccess) return e;
+    }
     hipLaunchKernelGGL(form_kernel<double>, grid, dim3(kFormThreads), lds, s, rom, n_q, thA, thf, th0, nt_q, plan,
                        (double*)mats, rhs, n_max);
   } else {
-    hipError_t e = hipFuncSetAttribute((const void*)form_kernel<float>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
+    if (!g_capturing) {
+      const hipError_t e = hipFuncSetAttribute((const void*)form_kernel<float>,
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      if (e != hipSuccess) return e;
+    }
     hipLaunchKernelGGL(form_kernel<float>, grid, dim3(kFormThreads), lds, s, rom, n_q, thA, thf, th0, nt_q, plan,
                        (float*)mats, rhs, n_max);
   }
@@ -506,9 +510,11 @@ hipError_t launch_residual(const RomView& rom, int32_t n_q, const double* thA, c
                            int32_t n_max, hipStream_t s) {
   if (n_q == 0 || n_max == 0) return hipSuccess;
   const size_t lds = query_lds_bytes(rom.n_s, n_max) + sizeof(double) * n_max;
-  hipError_t e = hipFuncSetAttribute((const void*)residual_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     (int)lds);
-  if (e != hipSuccess) return e;
+  hipError_t e = hipSuccess;
+  if (!g_capturing) {
+    e = hipFuncSetAttribute((const void*)residual_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
   dim3 grid(mode_grid(n_q, rom.n_s));
   hipLaunchKernelGGL(residual_kernel, grid, dim3(kFormThreads), lds, s, rom, n_q, thA, nt_q, plan, rhs, x, r, active,
                      n_max);

@@ -66,6 +66,13 @@ _SIGNATURES = {
     "st_solve_workspace": (_SZ, [ctypes.POINTER(st_rom_desc), _I32, _I64, _I64, _I32]),
     "st_solve": (_I32, [ctypes.POINTER(st_rom_desc), _P, _I32, _P, _P, _P, _P, _P, _I32, _D, _I32, _P, _I64, _P, _P,
                         _P, _P, _P, _SZ, _P]),
+    "st_graph_enable": (_I32, [_I32]),
+    "st_graph_reset": (_I32, []),
+    "st_graph_count": (_I32, []),
+    "st_autotune": (_I32, [ctypes.POINTER(st_rom_desc), _P, _I32, _P, _P, _P, _P, _I32, _P, _I64, _P, _P, _P, _P,
+                           _SZ, _P, _P, _P]),
+    "st_autotune_choice": (_I32, [_I32, _I32]),
+    "st_autotune_set": (_I32, [_I32, _I32, _I32]),
     "st_mlp_param_count": (_I64, [_P]),
     "st_mlp_workspace": (_SZ, [_P, _I32]),
     "st_mlp_forward": (_I32, [_P, _P, _I32, _P, _P, _P, _SZ, _P]),
@@ -286,6 +293,48 @@ def st_solve(desc: RomDesc, rom: torch.Tensor, theta_A: torch.Tensor, theta_f: O
                           _ptr(bufs.relres), _ptr(bufs.info), _ptr(bufs.iters), _ptr(bufs.ws), bufs.ws_bytes,
                           _stream()), "st_solve")
     return bufs
+
+
+def st_graph_enable(on: bool = True):
+    _check(lib().st_graph_enable(1 if on else 0), "st_graph_enable")
+
+
+def st_graph_reset():
+    _check(lib().st_graph_reset(), "st_graph_reset")
+
+
+def st_graph_count() -> int:
+    return int(lib().st_graph_count())
+
+
+LU_VARIANTS = 2
+
+
+def st_autotune(desc: RomDesc, rom: torch.Tensor, theta_A: torch.Tensor, theta_f: Optional[torch.Tensor] = None,
+                theta_0: Optional[torch.Tensor] = None, nt_q: Optional[torch.Tensor] = None, lu_prec: int = ST_F64,
+                bufs: Optional[SolveBuffers] = None, widths: Optional[np.ndarray] = None):
+    """Time the batched-LU variants on this batch and record the fastest.
+    Returns (choice, [ms per variant]).  bufs' outputs are scratch afterwards."""
+    n_q = int(theta_A.shape[0])
+    if bufs is None:
+        if widths is None:
+            widths = query_widths(desc, None if nt_q is None else nt_q.cpu().numpy(), n_q)
+        bufs = SolveBuffers(desc, n_q, widths, lu_prec, theta_A.device)
+    choice = ctypes.c_int32(-1)
+    ms = (ctypes.c_double * LU_VARIANTS)()
+    _check(lib().st_autotune(desc.ref(), _ptr(rom), n_q, _ptr(theta_A), _ptr(theta_f), _ptr(theta_0), _ptr(nt_q),
+                             lu_prec, _ptr(bufs.coeff), bufs.sum_w, _ptr(bufs.coeff_off), _ptr(bufs.relres),
+                             _ptr(bufs.info), _ptr(bufs.ws), bufs.ws_bytes, _stream(), ctypes.byref(choice), ms),
+           "st_autotune")
+    return int(choice.value), [float(ms[i]) for i in range(LU_VARIANTS)]
+
+
+def st_autotune_choice(lu_prec: int, n: int) -> int:
+    return int(lib().st_autotune_choice(lu_prec, n))
+
+
+def st_autotune_set(lu_prec: int, n: int, variant: int):
+    _check(lib().st_autotune_set(lu_prec, n, variant), "st_autotune_set")
 
 
 def st_timing_enable(on: bool = True):

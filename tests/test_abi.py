@@ -147,3 +147,24 @@ def test_mlp_and_certificate_host_validation():
     assert call(1e-3, -1.0) == -1
     assert call(float("nan"), 1e-6) == -1
     assert call(1e-3, 1e-6, ws=nb - 1) == -3
+
+
+def test_graph_and_autotune_host_calls():
+    L = strom.lib()
+    assert L.st_graph_enable(0) == 0
+    assert L.st_graph_reset() == 0
+    assert L.st_graph_count() == 0
+    assert L.st_autotune_choice(7, 100) == -1           # bad precision
+    assert L.st_autotune_choice(0, 1 << 20) == -1       # width out of range
+    assert L.st_autotune_set(1, 100, 2) == -1           # no such variant
+    assert L.st_autotune_set(1, 100, 1) == 0
+    assert L.st_autotune_choice(1, 100) == 1
+    assert L.st_autotune_set(1, 100, -1) == 0
+    assert L.st_autotune_choice(1, 100) == -1
+    d = strom.RomDesc([4, 4], 8, 2, 0, 1)
+    fake = ctypes.c_void_p(0x1000)
+    # bad precision and short workspace are rejected before any launch
+    assert L.st_autotune(d.ref(), fake, 4, fake, None, fake, None, 5, fake, 100, fake, fake, fake, fake, 1 << 30,
+                         None, None, None) == -1
+    assert L.st_autotune(d.ref(), fake, 4, fake, None, fake, None, 1, fake, 100, fake, fake, fake, fake, 16,
+                         None, None, None) == -3
