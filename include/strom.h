@@ -337,6 +337,23 @@ st_status st_timing_enable(int32_t on);
 int32_t st_timing_read(double* ms, int32_t cap);
 
 /* ========================================================================
+ * st_reconstruct - space-time state of each query (Sec. 3.2, the space-time
+ * state approximation): out_q[x, k] = sum_i Phi_s[x, i] sum_j Phi_t[k, (i, j)] c_q[(i, j)]
+ * over query q's per-mode prefixes (nt_q as in st_solve; NULL = full bases).
+ *
+ * rom       [dev] ROM buffer of d (its mode offsets are used).
+ * Phi_s     [dev] N_s x n_s column-major, leading dimension ldp >= N_s.
+ * Phi_t     [dev] N_t x n column-major, leading dimension ldt >= N_t.
+ * coeff, coeff_off [dev] packed coefficients as written by st_solve.
+ * out       [dev] n_q blocks of ldo x N_t (column-major, ldo >= N_s); block q
+ *           starts at out + q * ldo * N_t.  Validation only (the full-order
+ *           state is large): not part of the online solve.
+ * ====================================================================== */
+st_status st_reconstruct(const st_rom_desc* d, const void* rom, int64_t N_s, const double* Phi_s, int64_t ldp,
+                         const double* Phi_t, int64_t ldt, int32_t n_q, const int32_t* nt_q, const double* coeff,
+                         const int64_t* coeff_off, double* out, int64_t ldo, void* stream);
+
+/* ========================================================================
  * HIP graph replay of st_solve.  After st_graph_enable(1), the first st_solve
  * call with a given set of arguments runs eagerly and records its whole launch
  * sequence as a HIP graph; later calls with the same arguments (the

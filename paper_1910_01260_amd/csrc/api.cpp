@@ -500,6 +500,20 @@ st_status st_solve(const st_rom_desc* d, const void* rom, int32_t n_q, const dou
   return ST_OK;
 }
 
+st_status st_reconstruct(const st_rom_desc* d, const void* rom, int64_t N_s, const double* Phi_s, int64_t ldp,
+                         const double* Phi_t, int64_t ldt, int32_t n_q, const int32_t* nt_q, const double* coeff,
+                         const int64_t* coeff_off, double* out, int64_t ldo, void* stream) {
+  if (!desc_ok(d) || !rom || N_s < 1 || n_q < 0) return ST_EINVAL;
+  if (ldp < N_s || ldt < d->N_t || ldo < N_s) return ST_EINVAL;
+  if (d->n_s > kMaxFormModes) return ST_EUNSUPPORTED;
+  if (n_q == 0) return ST_OK;
+  if (!Phi_s || !Phi_t || !coeff || !coeff_off || !out) return ST_EINVAL;
+  const RomView rv = view_of(d, rom);
+  ST_TRY(launch_reconstruct(N_s, d->N_t, d->n_s, Phi_s, ldp, Phi_t, ldt, rv.moff, nt_q, n_q, coeff, coeff_off, out,
+                            ldo, static_cast<hipStream_t>(stream)));
+  return ST_OK;
+}
+
 st_status st_graph_enable(int32_t on) {
   g_graph = on != 0;
   return ST_OK;

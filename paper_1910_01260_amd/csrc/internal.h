@@ -115,6 +115,11 @@ int lu_variant_count(int32_t prec, int32_t n_max);
 hipError_t launch_lu(int32_t n_q, Plan plan, int32_t prec, void* mats, int32_t* piv, int32_t n_max, int variant,
                      hipStream_t s);
 
+hipError_t launch_reconstruct(int64_t N_s, int32_t N_t, int32_t n_s, const double* Phi_s, int64_t ldp,
+                              const double* Phi_t, int64_t ldt, const int32_t* moff, const int32_t* nt_q, int32_t n_q,
+                              const double* coeff, const int64_t* coeff_off, double* out, int64_t ldo,
+                              hipStream_t s);
+
 // True while st_solve records its launches into a HIP graph: launchers then skip
 // hipFuncSetAttribute (set on the eager run that precedes every capture).
 extern bool g_capturing;

@@ -192,7 +192,7 @@ __device__ inline void query_setup(const RomView& rom, int32_t q, int32_t i, con
 }
 
 // Rows handled per pass of the row loops (two rows' loads in flight together).
-constexpr int kRowUnroll = 2;
+constexpr int kRowUnroll = 4;
 // Rows of one residual pass (their partial sums live in registers).
 constexpr int kResRows = 8;
 
@@ -546,6 +546,85 @@ hipError_t launch_finalize(int32_t n_q, Plan plan, double* coeff, int32_t* info_
 hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s) {
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(fill_i32_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n, v);
+  return hipGetLastError();
+}
+
+}  // namespace strom
+
+// ---------------------------------------------------------------------------
+// Reconstruction of the space-time state (Sec. 3.2, the space-time state
+// approximation): u(x, t_k) = sum_i Phi_s[x, i] sum_j Phi_t[k, (i, j)] c_(i,j),
+// over the query's per-mode prefixes.
+// ---------------------------------------------------------------------------
+namespace strom {
+namespace {
+
+constexpr int kRecThreads = 256;
+constexpr int kRecSteps = 16;  // time steps per workgroup
+
+// Y[k, i] = sum_{j < nt_q[q, i]} Phi_t[k, moff[i] + j] c[off + loff[i] + j] for the
+// workgroup's time steps (in LDS), then out_q[x, k] = sum_i Phi_s[x, i] Y[k, i] with
+// one spatial row per thread: Phi_s rows read once per workgroup, coalesced writes.
+__global__ __launch_bounds__(kRecThreads) void reconstruct_kernel(int64_t N_s, int32_t N_t, int32_t n_s,
+                                                                  const double* __restrict__ Phi_s, int64_t ldp,
+                                                                  const double* __restrict__ Phi_t, int64_t ldt,
+                                                                  const int32_t* __restrict__ moff,
+                                                                  const int32_t* __restrict__ nt_q,
+                                                                  const double* __restrict__ coeff,
+                                                                  const int64_t* __restrict__ coeff_off,
+                                                                  double* __restrict__ out, int64_t ldo) {
+  extern __shared__ __align__(16) double rec_lds[];
+  double* Y = rec_lds;                                    // kRecSteps x n_s
+  int32_t* loff = reinterpret_cast<int32_t*>(Y + kRecSteps * n_s);  // n_s + 1
+  const int32_t q = blockIdx.z;
+  const int32_t k0 = blockIdx.y * kRecSteps;
+  const int nk = min(kRecSteps, N_t - k0);
+  if (threadIdx.x == 0) {
+    int32_t o = 0;
+    for (int i = 0; i < n_s; ++i) {
+      loff[i] = o;
+      o += nt_q ? nt_q[(int64_t)q * n_s + i] : moff[i + 1] - moff[i];
+    }
+    loff[n_s] = o;
+  }
+  __syncthreads();
+  const double* c = coeff + coeff_off[q];
+  for (int e = threadIdx.x; e < nk * n_s; e += kRecThreads) {
+    const int kk = e / n_s, i = e % n_s;
+    const int nti = loff[i + 1] - loff[i];
+    double y = 0.0;
+    for (int j = 0; j < nti; ++j) y = fma(Phi_t[(int64_t)(moff[i] + j) * ldt + k0 + kk], c[loff[i] + j], y);
+    Y[kk * n_s + i] = y;
+  }
+  __syncthreads();
+  const int64_t x = (int64_t)blockIdx.x * kRecThreads + threadIdx.x;
+  if (x >= N_s) return;
+  double acc[kRecSteps];
+#pragma unroll
+  for (int kk = 0; kk < kRecSteps; ++kk) acc[kk] = 0.0;
+  for (int i = 0; i < n_s; ++i) {
+    const double p = Phi_s[x + (int64_t)i * ldp];
+#pragma unroll
+    for (int kk = 0; kk < kRecSteps; ++kk) acc[kk] = fma(p, Y[kk * n_s + i], acc[kk]);
+  }
+  double* o = out + (int64_t)q * ldo * N_t;
+#pragma unroll
+  for (int kk = 0; kk < kRecSteps; ++kk)
+    if (kk < nk) o[x + (int64_t)(k0 + kk) * ldo] = acc[kk];
+}
+
+}  // namespace
+
+hipError_t launch_reconstruct(int64_t N_s, int32_t N_t, int32_t n_s, const double* Phi_s, int64_t ldp,
+                              const double* Phi_t, int64_t ldt, const int32_t* moff, const int32_t* nt_q, int32_t n_q,
+                              const double* coeff, const int64_t* coeff_off, double* out, int64_t ldo,
+                              hipStream_t s) {
+  if (n_q == 0 || N_s == 0 || N_t == 0) return hipSuccess;
+  const size_t lds = sizeof(double) * kRecSteps * n_s + sizeof(int32_t) * (n_s + 1);
+  dim3 grid((unsigned)((N_s + kRecThreads - 1) / kRecThreads), (unsigned)((N_t + kRecSteps - 1) / kRecSteps),
+            (unsigned)n_q);
+  hipLaunchKernelGGL(reconstruct_kernel, grid, dim3(kRecThreads), lds, s, N_s, N_t, n_s, Phi_s, ldp, Phi_t, ldt, moff,
+                     nt_q, coeff, coeff_off, out, ldo);
   return hipGetLastError();
 }
 

@@ -66,6 +66,8 @@ _SIGNATURES = {
     "st_solve_workspace": (_SZ, [ctypes.POINTER(st_rom_desc), _I32, _I64, _I64, _I32]),
     "st_solve": (_I32, [ctypes.POINTER(st_rom_desc), _P, _I32, _P, _P, _P, _P, _P, _I32, _D, _I32, _P, _I64, _P, _P,
                         _P, _P, _P, _SZ, _P]),
+    "st_reconstruct": (_I32, [ctypes.POINTER(st_rom_desc), _P, _I64, _P, _I64, _P, _I64, _I32, _P, _P, _P, _P, _I64,
+                              _P]),
     "st_graph_enable": (_I32, [_I32]),
     "st_graph_reset": (_I32, []),
     "st_graph_count": (_I32, []),
@@ -126,6 +128,15 @@ def _ptr(t: Optional[torch.Tensor]):
         raise ValueError("expected a device tensor")
     if not t.is_contiguous():
         raise ValueError("expected a contiguous tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _colptr(t: torch.Tensor):
+    """Pointer of a column-major device matrix (unit stride down a column; any leading dimension)."""
+    if not t.is_cuda:
+        raise ValueError("expected a device tensor")
+    if t.dim() != 2 or t.stride(0) != 1 or t.stride(1) < t.shape[0]:
+        raise ValueError("expected a column-major matrix")
     return ctypes.c_void_p(t.data_ptr())
 
 
@@ -293,6 +304,19 @@ def st_solve(desc: RomDesc, rom: torch.Tensor, theta_A: torch.Tensor, theta_f: O
                           _ptr(bufs.relres), _ptr(bufs.info), _ptr(bufs.iters), _ptr(bufs.ws), bufs.ws_bytes,
                           _stream()), "st_solve")
     return bufs
+
+
+def st_reconstruct(desc: RomDesc, rom: torch.Tensor, Phi_s: torch.Tensor, Phi_t: torch.Tensor,
+                   bufs: "SolveBuffers", n_q: int, nt_q: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Space-time states of the first n_q queries of a solve: (n_q, N_t, N_s) view of
+    column-major N_s x N_t blocks (Phi_s, Phi_t column-major device tensors)."""
+    N_s = int(Phi_s.shape[0])
+    N_t = desc.c.N_t
+    out = torch.empty((n_q, N_t, N_s), dtype=torch.float64, device=Phi_s.device)
+    _check(lib().st_reconstruct(desc.ref(), _ptr(rom), N_s, _colptr(Phi_s), int(Phi_s.stride(1)), _colptr(Phi_t),
+                                int(Phi_t.stride(1)), int(n_q), _ptr(nt_q), _ptr(bufs.coeff), _ptr(bufs.coeff_off),
+                                _ptr(out), N_s, _stream()), "st_reconstruct")
+    return out
 
 
 def st_graph_enable(on: bool = True):
