@@ -43,6 +43,12 @@ def parse():
     ap.add_argument("--queries", type=int, default=4096)
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the oracle baseline leg")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", choices=["batch", "surrogate"], default="batch",
+                    help="batch: the 4096-query batched solve (default); surrogate: train the learned "
+                         "surrogate on batched solves of the transport-with-absorber ROM and measure "
+                         "surrogate + certificate + fallback against the batched solve")
+    ap.add_argument("--surrogate-train", type=int, default=20000)
+    ap.add_argument("--surrogate-steps", type=int, default=6000)
     ap.add_argument("--copy-calibration-gib", type=float, default=0.0,
                     help="before the steps, copy a buffer of this size once (device to device) so that a "
                          "hardware-counter run can scale byte counters against a kernel of known traffic")
@@ -63,6 +69,8 @@ def main():
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(queries would shard across GPUs with no communication; see the design notes)", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "surrogate":
+        return bench_surrogate(args)
 
     import numpy as np
     import torch
@@ -329,6 +337,150 @@ def cpu_baseline(prob, U, n_s, n_t_max, mus, nt, tA, t0_, budget_s, state, c32, 
     return ({"value": rate, "unit": "queries/s", "cores": threads, "kind": "oracle",
              "sample": f"oracle POD once ({t_off:.2f} s) + {done} of {nq} queries ({t_q:.1f} s); "
                        f"rate extrapolated to the {nq}-query batch"}, worst)
+
+
+def bench_surrogate(args):
+    """Learned surrogate on the transport-with-absorber ROM (64^2 cells, 12 directions,
+    N_t = 200, n_s = 40 modes x 30 temporal vectors = 1200 coefficients, 3 parameters).
+
+    Training data are batched FP64 solves at seeded parameters; the network
+    (3 -> 4 x 512 GELU -> 1200) is trained by the library's BF16 kernels.  A fresh
+    4096-query batch is then answered (a) by the batched solve alone and (b) by the
+    network + FP64 residual certificate, with the rejected queries re-solved, for
+    several certificate tolerances."""
+    import numpy as np
+    import torch
+
+    from paper_1910_01260_amd import strom
+    from paper_1910_01260_amd import surrogate as S
+    from paper_1910_01260_amd import workloads as W
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    strom.lib()
+    dev = "cuda"
+    log = lambda m: print(f"[surrogate] {m}", file=sys.stderr, flush=True)
+    t0 = time.time()
+    prob = W.transport2d_absorber()
+    n_s, n_t = 40, 30
+    U = W.snapshots(prob)
+    log(f"snapshots {U.shape} in {time.time() - t0:.1f}s")
+    Ud = torch.tensor(np.ascontiguousarray(U.T), device=dev).T
+    Phi_s, Phi_t, sigma, rank = strom.st_build_bases(Ud, prob.N_t, len(prob.train_mu), n_s, [n_t] * n_s)
+    desc = strom.RomDesc([n_t] * n_s, prob.N_t, prob.Q, prob.Qf, prob.Q0)
+    csr = [strom.csr_to_device(*W.csr_arrays(A)) for A in prob.terms]
+    cm = lambda a: torch.tensor(np.ascontiguousarray(np.asarray(a, dtype=np.float64).T), device=dev).T
+    rom = strom.st_assemble(desc, Phi_s, Phi_t, torch.tensor(prob.dt, device=dev), [c[0] for c in csr],
+                            cm(prob.Bf), cm(prob.g), None)
+    torch.cuda.synchronize()
+    del Ud
+    n = desc.n
+    gamma = S.coercivity_floor(prob.N_t)
+
+    def thetas(mus):
+        tA, tf, t0_ = prob.thetas(mus)
+        dv = lambda a: torch.tensor(np.ascontiguousarray(a), device=dev) if a.shape[1] else None
+        return dv(tA), dv(tf), dv(t0_)
+
+    # ---- training data: batched FP64 solves
+    n_train = args.surrogate_train
+    mus_tr = W.sample_params(prob, n_train, seed=191001261)
+    C = np.empty((n_train, n))
+    chunk = 2048
+    bufs = strom.SolveBuffers(desc, chunk, np.full(chunk, n), strom.ST_F64, dev)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for a in range(0, n_train, chunk):
+        b = min(n_train, a + chunk)
+        dA, df, d0 = thetas(mus_tr[a:b])
+        if b - a < chunk:
+            bufs = strom.SolveBuffers(desc, b - a, np.full(b - a, n), strom.ST_F64, dev)
+        strom.st_solve(desc, rom, dA, df, d0, None, strom.ST_F64, bufs=bufs)
+        C[a:b] = bufs.coeff[: (b - a) * n].view(b - a, n).cpu().numpy()
+    data_s = time.perf_counter() - t1
+    del bufs
+    log(f"{n_train} training solves in {data_s:.2f}s")
+
+    # ---- training
+    X = S.scaled_inputs(prob.box_lo, prob.box_hi, mus_tr)
+    net = S.Surrogate(X.shape[1], n, width=512, n_hidden=4, seed=191001263)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    hist = net.fit(X, C, steps=args.surrogate_steps, batch=1024, lr=1e-3, lr_final=1e-5, log=log)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t2
+    log(f"trained {args.surrogate_steps} steps in {train_s:.1f}s; final val loss {hist[-1][2]:.3e}")
+
+    # ---- test batch
+    nq = args.queries
+    mus = W.sample_params(prob, nq, seed=191001265)
+    dA, df, d0 = thetas(mus)
+    Xt = torch.tensor(S.scaled_inputs(prob.box_lo, prob.box_hi, mus), device=dev)
+    widths = np.full(nq, n)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+
+    def timed(fn, reps=3):
+        fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            ev[0].record()
+            fn()
+            ev[1].record()
+            torch.cuda.synchronize()
+            ts.append(ev[0].elapsed_time(ev[1]))
+        return float(np.median(ts))
+
+    b64 = strom.SolveBuffers(desc, nq, widths, strom.ST_F64, dev)
+    b32 = strom.SolveBuffers(desc, nq, widths, strom.ST_F32, dev)
+    ms64 = timed(lambda: strom.st_solve(desc, rom, dA, df, d0, None, strom.ST_F64, bufs=b64))
+    ms32 = timed(lambda: strom.st_solve(desc, rom, dA, df, d0, None, strom.ST_F32, 1e-12, 6, bufs=b32))
+    ref = b64.coeff.cpu().numpy().reshape(nq, n)
+    ok32 = int(np.sum((b32.info.cpu().numpy()[:nq] == 0) & (b32.relres.cpu().numpy()[:nq] <= 1e-12)))
+    ms_pred = timed(lambda: net.predict(Xt))
+    Y = net.predict(Xt)
+    coeff = torch.empty(nq * n, dtype=torch.float64, device=dev)
+    ms_check = timed(lambda: net.check(desc, rom, dA, df, d0, Y, gamma, 0.0, coeff))
+    cert, acc = net.check(desc, rom, dA, df, d0, Y, gamma, 0.0, coeff)
+    torch.cuda.synchronize()
+    pred = coeff.cpu().numpy().reshape(nq, n)
+    rel = np.linalg.norm(pred - ref, axis=1) / np.linalg.norm(ref, axis=1)
+    certs = cert.cpu().numpy()
+    sound = bool(np.all(rel <= certs * (1 + 1e-9) + 1e-15))
+    tols = [1e-6, 1e-4, 1e-2, 1e-1, 1.0]
+    rows = []
+    for tol in tols:
+        bs = strom.SolveBuffers(desc, nq, widths, strom.ST_F32, dev)
+
+        def run(tol=tol, bs=bs):
+            net.solve(desc, rom, dA, df, d0, Xt, gamma, tol, bs, strom.ST_F32, 1e-12, 6)
+
+        ms = timed(run)
+        acc_t = int(np.sum(certs <= tol))
+        rows.append({"tol": tol, "accepted": acc_t, "ms": ms, "queries_per_s": nq / (ms * 1e-3),
+                     "vs_batched_fp32ir": ms32 / ms})
+        log(f"tol {tol:g}: accepted {acc_t}/{nq}, {ms:.2f} ms ({ms32 / ms:.2f}x the batched FP32+IR solve)")
+        del bs
+    out = {
+        "metric": "surrogate-with-fallback ST-ROM queries/s at certified rel err <= tol",
+        "workload": "2-D transport with central absorber, 64^2 x 12 directions, N_t=200, 3 parameters, "
+                    "n_s=40 x n_t=30 = 1200 coefficients; MLP 3->4x512->1200 (GELU, BF16 products)",
+        "data": "synthetic (seeded)", "n_gpus": 1,
+        "train": {"queries": n_train, "solve_s": data_s, "steps": args.surrogate_steps, "batch": 1024,
+                  "train_s": train_s, "ms_per_step": 1e3 * train_s / max(1, args.surrogate_steps),
+                  "val_loss_first": hist[0][2], "val_loss_last": hist[-1][2]},
+        "test_queries": nq,
+        "batched_fp64_ms": ms64, "batched_fp32ir_ms": ms32, "batched_fp32ir_certified": ok32,
+        "batched_fp32ir_queries_per_s": ok32 / (ms32 * 1e-3),
+        "predict_ms": ms_pred, "certificate_ms": ms_check,
+        "prediction_rel_err": {"p50": float(np.median(rel)), "p90": float(np.quantile(rel, 0.9)),
+                               "max": float(rel.max())},
+        "certificate": {"gamma": gamma, "p50": float(np.median(certs)), "finite": int(np.isfinite(certs).sum()),
+                        "bounds_true_error": sound},
+        "by_tolerance": rows,
+    }
+    print(json.dumps(out))
 
 
 if __name__ == "__main__":
