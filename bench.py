@@ -226,13 +226,18 @@ def main():
     form_bytes = float(np.sum(widths.astype(np.float64) ** 2) * 4 + np.sum(widths) * 8)
     lu_tflops = lu_flops / (lu_ms * 1e-3) / 1e12
     form_gbs = form_bytes / (form_ms * 1e-3) / 1e9
-    traffic = None
-    tfile = os.path.join(ROOT, "profiles", "lu_f32_cb4096_traffic.json")
-    if os.path.exists(tfile):
-        with open(tfile) as f:
+    def counter_traffic(fname, src):
+        """HBM bytes per launch from the committed byte-counter summary, if the kernel source
+        is unchanged since the counters were taken."""
+        path = os.path.join(ROOT, "profiles", fname)
+        if not os.path.exists(path):
+            return None
+        with open(path) as f:
             tr = json.load(f)
-        if tr.get("source_hash") == source_hash("k_lu.hip"):
-            traffic = tr.get("bytes_per_launch")
+        return tr.get("bytes_per_launch") if tr.get("source_hash") == source_hash(src) else None
+
+    traffic = counter_traffic("lu_f32_cb4096_traffic.json", "k_lu.hip")
+    form_traffic = counter_traffic("form_f32_cb4096_traffic.json", "k_query.hip")
 
     # ------------------------------------------------------------- CPU baseline (the oracle, bounded sample)
     cpu = None
@@ -276,7 +281,7 @@ def main():
         },
         "assembly": {"kernel": "form_kernel<float>", "bound": "hbm", "achieved": form_gbs, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": form_gbs / HBM_PEAK_GBS, "algorithmic_bytes_per_launch": form_bytes,
-                     "avg_launch_ms": form_ms},
+                     "avg_launch_ms": form_ms, "traffic": form_traffic},
         "breakdown_ms": {"offline_pod_assemble": off_ms / K, "online_fp32_ir": on_ms / K,
                          "st_solve_phases_fp32": phases32,
                          "st_solve_phases_fp64": {k: v / K for k, v in ph64.items()}},
