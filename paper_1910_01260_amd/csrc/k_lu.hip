@@ -308,8 +308,11 @@ __device__ __forceinline__ void block_row_solve(T* __restrict__ A, int w, int r0
     }
     __syncthreads();
     if (tid < nc) {
+      // one column per thread (column-major in LDS, conflict free); the inner products are
+      // unrolled so that their LDS reads are issued together
       for (int c = 1; c < n; ++c) {
         T acc = pool[c * CW + tid];
+#pragma unroll 8
         for (int k = 0; k < c; ++k) acc -= Ls[c * NMAX + k] * pool[k * CW + tid];
         pool[c * CW + tid] = acc;
       }
@@ -349,15 +352,14 @@ __device__ __noinline__ void unit_lower_inverse(const T* __restrict__ L, T* __re
   auto Lv = [&](int i, int k) -> T { return (i < n && k < n) ? L[i * ld + k] : T(0); };
   // 1. diagonal blocks
   if (wave < NSB && lane < SB) {
+    // lane j solves L x = e_j into column j of the block (x_k = 0 for k < j follows from
+    // the recurrence); the inner products are unrolled so that their LDS reads issue together
     const int b0 = wave * SB, j = lane;
     for (int i = 0; i < SB; ++i) {
-      T x = T(0);
-      if (i == j) {
-        x = T(1);
-      } else if (i > j) {
-        for (int k = j; k < i; ++k) x -= Lv(b0 + i, b0 + k) * X[(b0 + k) * ld + b0 + j];
-      }
-      X[(b0 + i) * ld + b0 + j] = x;
+      T acc = i == j ? T(1) : T(0);
+#pragma unroll 8
+      for (int k = 0; k < i; ++k) acc -= Lv(b0 + i, b0 + k) * X[(b0 + k) * ld + b0 + j];
+      X[(b0 + i) * ld + b0 + j] = acc;
     }
   }
   __syncthreads();
@@ -369,7 +371,8 @@ __device__ __noinline__ void unit_lower_inverse(const T* __restrict__ L, T* __re
       const int bj = e / (SB * SB), i = (e / SB) % SB, j = e % SB;
       const int r = bi * SB + i, c = bj * SB + j;
       T acc = T(0);
-      for (int k = bj * SB + j; k < bi * SB; ++k) acc += Lv(r, k) * X[k * ld + c];
+#pragma unroll 8
+      for (int k = bj * SB; k < bi * SB; ++k) acc += Lv(r, k) * X[k * ld + c];  // X[k][c] = 0 for k < c
       X[r * ld + c] = acc;
     }
     __syncthreads();
@@ -383,7 +386,8 @@ __device__ __noinline__ void unit_lower_inverse(const T* __restrict__ L, T* __re
         const T* Dinv = X + (bi * SB + i) * ld + bi * SB;   // row i of X[bi][bi]
         const T* Sc = X + (bi * SB) * ld + bj * SB + j;      // column j of S[bi][bj]
         T acc = T(0);
-        for (int k = 0; k <= i; ++k) acc += Dinv[k] * Sc[k * ld];
+#pragma unroll
+        for (int k = 0; k < SB; ++k) acc += Dinv[k] * Sc[k * ld];  // Dinv[k] = 0 above the diagonal
         out[t] = -acc;
       }
     }
