@@ -69,10 +69,10 @@ template <typename T>
 constexpr size_t lu_pool_elems() {
   using C = LuCfg<T>;
   // max of: update tiles ((RB + 2 CB) x (NBO + 4)), the row-permutation staging
-  // (2 NBO x CHW) and the unit lower block with its inverse (2 NBO x (NBO + 1)) plus the
+  // (2 NBO x CHW, then a position map of up to kMaxWidth ints) and the unit lower block with its inverse (2 NBO x (NBO + 1)) plus the
   // per-wave strips of the triangular product when they do not fit in the first
   constexpr size_t a = (size_t)(C::RB + 2 * C::CB) * (C::NBO + 4);
-  constexpr size_t b = (size_t)2 * C::NBO * C::CHW;
+  constexpr size_t b = (size_t)2 * C::NBO * C::CHW + (kMaxWidth * sizeof(int32_t) + sizeof(T) - 1) / sizeof(T);
   constexpr size_t strips = (size_t)kLuWaves * C::NBO * 16;
   constexpr size_t c = (size_t)2 * C::NBO * (C::NBO + 1) + (strips <= (size_t)C::NBO * (C::NBO + 1) ? 0 : strips);
   return a > b ? (a > c ? a : c) : (b > c ? b : c);
@@ -225,45 +225,42 @@ __device__ __forceinline__ void tile_update(T* __restrict__ A, int w, int r_lo, 
 
 // Row interchanges piv[0..n) (step i swaps rows base+i and piv[i] >= base+i),
 // composed into a list of moves "row dst receives the old content of row src"
-// (thread 0, in LDS), then applied to the columns [c_lo, c_hi) outside
+// (a position map in LDS: thread 0 applies the swaps, all threads list the changed
+// positions), then applied to the columns [c_lo, c_hi) outside
 // [skip_lo, skip_hi) by staging the source row segments through LDS with
-// coalesced loads and stores.  Uses s_mv (>= 7 n ints).
+// coalesced loads and stores.  Uses s_mv (>= 4 n ints).
 template <typename T>
 __device__ __forceinline__ void permute_rows(T* __restrict__ A, int w, int base, int n, const int32_t* __restrict__ piv, int c_lo,
                              int c_hi, int skip_lo, int skip_hi, T* __restrict__ pool, int32_t* __restrict__ s_mv,
                              int32_t* s_nmoves) {
   constexpr int CHW = LuCfg<T>::CHW;
+  constexpr int NBO = LuCfg<T>::NBO;
   const int tid = threadIdx.x;
-  int32_t* cin = s_mv;            // content of rows base..base+n-1
-  int32_t* orow = s_mv + n;       // rows outside the range that were touched
-  int32_t* ocon = s_mv + 2 * n;   // their content
-  int32_t* msrc = s_mv + 3 * n;   // moves (src packed with dst: dst in cin-reuse)
+  // content of every position base + p of the range the interchanges can touch, after applying
+  // them in order (a dense map in the pool, past the row-staging area)
+  int32_t* cmap = reinterpret_cast<int32_t*>(pool + 2 * NBO * CHW);
+  int32_t* msrc = s_mv;  // moves: (source row, destination row) pairs
+  const int span = w - base;
+  for (int p = tid; p < span; p += kLuThreads) cmap[p] = base + p;
+  if (tid == 0) *s_nmoves = 0;
+  __syncthreads();
   if (tid == 0) {
-    int m = 0;
-    for (int i = 0; i < n; ++i) cin[i] = base + i;
     for (int i = 0; i < n; ++i) {
-      const int r = base + i, p = piv[i];
-      if (p == r) continue;
-      if (p < base + n) {
-        const int t = cin[i];
-        cin[i] = cin[p - base];
-        cin[p - base] = t;
-      } else {
-        int j = 0;
-        while (j < m && orow[j] != p) ++j;
-        if (j == m) { orow[m] = p; ocon[m] = p; ++m; }
-        const int t = cin[i];
-        cin[i] = ocon[j];
-        ocon[j] = t;
-      }
+      const int p = piv[i] - base;
+      if (p == i) continue;
+      const int t = cmap[i];
+      cmap[i] = cmap[p];
+      cmap[p] = t;
     }
-    // moves: rows inside first (dst = base + i), then outside rows
-    int nm = 0;
-    for (int i = 0; i < n; ++i)
-      if (cin[i] != base + i) { msrc[2 * nm] = cin[i]; msrc[2 * nm + 1] = base + i; ++nm; }
-    for (int j = 0; j < m; ++j)
-      if (ocon[j] != orow[j]) { msrc[2 * nm] = ocon[j]; msrc[2 * nm + 1] = orow[j]; ++nm; }
-    *s_nmoves = nm;
+  }
+  __syncthreads();
+  for (int p = tid; p < span; p += kLuThreads) {
+    const int c = cmap[p];
+    if (c != base + p) {
+      const int t = atomicAdd(s_nmoves, 1);
+      msrc[2 * t] = c;
+      msrc[2 * t + 1] = base + p;
+    }
   }
   __syncthreads();
   const int nm = *s_nmoves;
@@ -430,7 +427,7 @@ __global__ __launch_bounds__(kLuThreads) void lu_kernel(int32_t n_q, Plan plan, 
   __shared__ T s_redv[2][NW];
   __shared__ int32_t s_redr[2][NW];
   __shared__ int32_t s_piv[NBO];
-  __shared__ int32_t s_mv[7 * NBO + 8];  // permute_rows: 3 n bookkeeping + up to 2 n moves (src, dst)
+  __shared__ int32_t s_mv[4 * NBO + 8];  // permute_rows: up to 2 n moves (src, dst)
   __shared__ int32_t s_nm;
   __shared__ T s_L[32 * 32];
   __shared__ int32_t s_q;
