@@ -370,7 +370,8 @@ int32_t st_graph_count(void);
 
 /* ========================================================================
  * LU autotuner.  st_autotune times every batched-LU configuration (register
- * sub-panel widths) on the given batch, forming the systems afresh before each,
+ * sub-panel widths; for n <= 1536 also a 256-thread configuration that runs two
+ * queries per compute unit) on the given batch, forming the systems afresh before each,
  * records the fastest for the batch's LU precision and width class (total
  * reduced width n <= 1536, or n <= 4096) and st_solve uses it from then on.
  * Arguments as st_solve, with the same workspace size; coeff_off and info
@@ -381,7 +382,7 @@ int32_t st_graph_count(void);
  * st_autotune_choice returns the recorded variant for (lu_prec, n), -1 if
  * none (variant 0 is then used); st_autotune_set records one directly.
  * ====================================================================== */
-#define ST_LU_VARIANTS 2
+#define ST_LU_VARIANTS 3
 st_status st_autotune(const st_rom_desc* d, const void* rom, int32_t n_q, const double* theta_A,
                       const double* theta_f, const double* theta_0, const int32_t* nt_q, int32_t lu_prec,
                       double* coeff, int64_t coeff_cap, int64_t* coeff_off, double* relres, int32_t* info, void* ws,

@@ -369,6 +369,7 @@ hipError_t solve_launches(const SolveArgs& a, hipStream_t s) {
   const int32_t n_max = (int32_t)total_nt(a.d);
   const int32_t n_q = a.n_q;
   const int variant = lu_choice(a.lu_prec, n_max);
+  const int nbo = lu_outer_block(a.lu_prec, n_max, variant);
   hipError_t e;
 #define SL_TRY(expr)                 \
   do {                               \
@@ -385,12 +386,12 @@ hipError_t solve_launches(const SolveArgs& a, hipStream_t s) {
   SL_TRY(launch_lu(n_q, plan, a.lu_prec, w.mats, w.perm, n_max, variant, s));
   SL_TRY(mark(4, s));
   SL_TRY(launch_fill_i32(w.active, n_q, 1, s));
-  SL_TRY(launch_lu_solve(n_q, plan, a.lu_prec, w.mats, w.perm, w.b, a.coeff, 0, w.active, n_max, s));
+  SL_TRY(launch_lu_solve(n_q, plan, a.lu_prec, w.mats, w.perm, w.b, a.coeff, 0, w.active, n_max, nbo, s));
   SL_TRY(mark(5, s));
   for (int it = 0; it < a.ir_max; ++it) {
     SL_TRY(launch_residual(rv, n_q, a.thA, a.nt_q, plan, w.b, a.coeff, w.r, w.rnorm, w.active, n_max, s));
     SL_TRY(launch_ir_check(n_q, plan, w.rnorm, w.bnorm, a.ir_tol, it, 0, w.active, a.relres, a.iters, s));
-    SL_TRY(launch_lu_solve(n_q, plan, a.lu_prec, w.mats, w.perm, w.r, a.coeff, 1, w.active, n_max, s));
+    SL_TRY(launch_lu_solve(n_q, plan, a.lu_prec, w.mats, w.perm, w.r, a.coeff, 1, w.active, n_max, nbo, s));
   }
   SL_TRY(mark(6, s));
   // final residual of the queries still active (all of them without refinement)
@@ -599,7 +600,7 @@ int32_t st_autotune_choice(int32_t lu_prec, int32_t n) {
 
 st_status st_autotune_set(int32_t lu_prec, int32_t n, int32_t variant) {
   if ((lu_prec != ST_F64 && lu_prec != ST_F32) || n < 0 || n > kMaxWidth) return ST_EINVAL;
-  if (variant < -1 || variant >= ST_LU_VARIANTS) return ST_EINVAL;
+  if (variant < -1 || variant >= ST_LU_VARIANTS || variant >= lu_variant_count(lu_prec, n)) return ST_EINVAL;
   std::lock_guard<std::mutex> lk(g_tune_mu);
   g_lu_choice[lu_prec == ST_F32 ? 1 : 0][width_class(n)] = variant;
   return ST_OK;

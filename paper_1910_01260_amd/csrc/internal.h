@@ -112,6 +112,7 @@ hipError_t launch_residual(const RomView& rom, int32_t n_q, const double* thA, c
 
 // k_lu.hip: batched LU (a8) and triangular solves
 int lu_variant_count(int32_t prec, int32_t n_max);
+int lu_outer_block(int32_t prec, int32_t n_max, int variant);
 hipError_t launch_lu(int32_t n_q, Plan plan, int32_t prec, void* mats, int32_t* piv, int32_t n_max, int variant,
                      hipStream_t s);
 
@@ -125,7 +126,7 @@ hipError_t launch_reconstruct(int64_t N_s, int32_t N_t, int32_t n_s, const doubl
 extern bool g_capturing;
 // x (or x += solution when accumulate) for every active query: solve LU x = b
 hipError_t launch_lu_solve(int32_t n_q, Plan plan, int32_t prec, const void* mats, const int32_t* piv, const double* b,
-                           double* x, int accumulate, const int32_t* active, int32_t n_max, hipStream_t s);
+                           double* x, int accumulate, const int32_t* active, int32_t n_max, int nbo, hipStream_t s);
 // refinement bookkeeping: relres, convergence flags, NaN for failed queries
 hipError_t launch_ir_check(int32_t n_q, Plan plan, const double* rnorm, const double* bnorm, double tol, int32_t step,
                            int32_t last, int32_t* active, double* relres, int32_t* iters, hipStream_t s);

@@ -48,32 +48,44 @@ extern "C" __device__ double __ockl_wfred_add_f64(double);
 __device__ inline float wave_max(float v) { return __ockl_wfred_max_f32(v); }
 __device__ inline double wave_max(double v) { return __ockl_wfred_max_f64(v); }
 
-// Block sizes per element type: NBO-wide outer blocks are factored as
-// NBI-wide sub-panels held in registers; updates run on the matrix cores from
-// LDS tiles of RB rows x K and K x CB columns (K <= NBO).
-template <typename T>
+// Block sizes per element type and workgroup size NT: NBO-wide outer blocks are
+// factored as NBI-wide sub-panels held in registers; updates run on the matrix
+// cores from LDS tiles of RB rows x K and K x CB columns (K <= NBO), the NW waves
+// of the workgroup arranged as WR x 2 over the output tile.  NT = 512 runs one
+// workgroup per CU; NT = 256 halves the LDS so that two workgroups (two queries)
+// share a CU and overlap their latency-bound phases.
+template <typename T, int NT>
 struct LuCfg;
 template <>
-struct LuCfg<float> {
+struct LuCfg<float, 512> {
   static constexpr int NBO = 128, RB = 128, CB = 64, CHW = 64;
 };
 template <>
-struct LuCfg<double> {
+struct LuCfg<double, 512> {
   static constexpr int NBO = 64, RB = 64, CB = 64, CHW = 64;
 };
+template <>
+struct LuCfg<float, 256> {
+  static constexpr int NBO = 64, RB = 64, CB = 64, CHW = 64;
+};
+template <>
+struct LuCfg<double, 256> {
+  static constexpr int NBO = 64, RB = 64, CB = 32, CHW = 32;
+};
 
-constexpr int kLuThreads = 512;
-constexpr int kLuWaves = kLuThreads / 64;
+constexpr int kLuThreads = 512;  // the default workgroup size
 
-template <typename T>
+template <typename T, int NT>
 constexpr size_t lu_pool_elems() {
-  using C = LuCfg<T>;
+  using C = LuCfg<T, NT>;
+  constexpr int NW = NT / 64;
   // max of: update tiles ((RB + 2 CB) x (NBO + 4)), the row-permutation staging
-  // (2 NBO x CHW, then a position map of up to kMaxWidth ints) and the unit lower block with its inverse (2 NBO x (NBO + 1)) plus the
-  // per-wave strips of the triangular product when they do not fit in the first
+  // (2 NBO x CHW, then a position map of up to kMaxWidth ints) and the unit lower
+  // block with its inverse (2 NBO x (NBO + 1)) plus the per-wave strips of the
+  // triangular product when they do not fit in the first
   constexpr size_t a = (size_t)(C::RB + 2 * C::CB) * (C::NBO + 4);
   constexpr size_t b = (size_t)2 * C::NBO * C::CHW + (kMaxWidth * sizeof(int32_t) + sizeof(T) - 1) / sizeof(T);
-  constexpr size_t strips = (size_t)kLuWaves * C::NBO * 16;
+  constexpr size_t strips = (size_t)NW * C::NBO * 16;
   constexpr size_t c = (size_t)2 * C::NBO * (C::NBO + 1) + (strips <= (size_t)C::NBO * (C::NBO + 1) ? 0 : strips);
   return a > b ? (a > c ? a : c) : (b > c ? b : c);
 }
@@ -99,22 +111,24 @@ struct Vec4<double> {
   static constexpr int per = 2;
 };
 
-template <typename T>
+template <typename T, int NT>
 __device__ __forceinline__ int kperm(int k) {
-  constexpr int Q = LuCfg<T>::NBO / 4;
+  constexpr int Q = LuCfg<T, NT>::NBO / 4;
   return (k & 3) * Q + (k >> 2);
 }
 
-template <typename T>
+template <typename T, int NT>
 __device__ __forceinline__ void tile_update(T* __restrict__ A, int w, int r_lo, int r_hi, int c_lo, int c_hi, int k0,
                                             int K, T* __restrict__ pool) {
-  using C = LuCfg<T>;
+  using C = LuCfg<T, NT>;
   constexpr int NBO = C::NBO, RB = C::RB, CB = C::CB;
+  constexpr int WR = NT / 128;  // wave rows over the output tile (two wave columns)
   constexpr int LDK = NBO + 4;  // row stride of the staged operands (16-byte aligned rows)
   constexpr int Q = NBO / 4;
-  constexpr int MR = RB / 4 / 16, MC = CB / 2 / 16;
+  constexpr int MR = RB / WR / 16, MC = CB / 2 / 16;
   constexpr int PER = Vec4<T>::per;  // K steps per 128-bit read
-  constexpr int UPT = NBO * CB / kLuThreads;  // right-factor elements staged per thread
+  constexpr int UPT = NBO * CB / NT;  // right-factor elements staged per thread
+  static_assert(NBO * CB % NT == 0 && RB % (16 * WR) == 0, "update tile shape");
   typedef typename Vec4<T>::type VT;
   typedef typename Mfma<T>::v4 v4;
   if (r_lo >= r_hi || c_lo >= c_hi || K <= 0) return;
@@ -122,7 +136,7 @@ __device__ __forceinline__ void tile_update(T* __restrict__ A, int w, int r_lo, 
   T* Us0 = pool + RB * LDK;       // CB x LDK, two buffers (transposed right factor)
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
-  const int wr = (wave >> 1) * (RB / 4);
+  const int wr = (wave >> 1) * (RB / WR);
   const int wc = (wave & 1) * (CB / 2);
   const int ksteps = (K + 3) / 4;
   const int kchunks = (ksteps + PER - 1) / PER;
@@ -148,7 +162,7 @@ __device__ __forceinline__ void tile_update(T* __restrict__ A, int w, int r_lo, 
       const int nc = min(CB, c_hi - cb);
 #pragma unroll
       for (int t = 0; t < UPT; ++t) {
-        const int e = tid + t * kLuThreads;
+        const int e = tid + t * NT;
         const int k = e / CB, j = e % CB;
         ur[t] = (k < K && j < nc) ? A[(int64_t)(k0 + k) * w + cb + j] : T(0);
       }
@@ -156,18 +170,18 @@ __device__ __forceinline__ void tile_update(T* __restrict__ A, int w, int r_lo, 
     auto store_u = [&](T* Us) {
 #pragma unroll
       for (int t = 0; t < UPT; ++t) {
-        const int e = tid + t * kLuThreads;
+        const int e = tid + t * NT;
         const int k = e / CB, j = e % CB;
-        Us[j * LDK + kperm<T>(k)] = ur[t];
+        Us[j * LDK + kperm<T, NT>(k)] = ur[t];
       }
     };
     __syncthreads();
     load_u(c_lo);
     load_acc(c_lo, acc);
 #pragma unroll 8
-    for (int e = tid; e < RB * NBO; e += kLuThreads) {
+    for (int e = tid; e < RB * NBO; e += NT) {
       const int i = e / NBO, k = e % NBO;
-      Ls[i * LDK + kperm<T>(k)] = (i < nr && k < K) ? A[(int64_t)(rb + i) * w + k0 + k] : T(0);
+      Ls[i * LDK + kperm<T, NT>(k)] = (i < nr && k < K) ? A[(int64_t)(rb + i) * w + k0 + k] : T(0);
     }
     store_u(Us0);
     __syncthreads();
@@ -229,19 +243,19 @@ __device__ __forceinline__ void tile_update(T* __restrict__ A, int w, int r_lo, 
 // positions), then applied to the columns [c_lo, c_hi) outside
 // [skip_lo, skip_hi) by staging the source row segments through LDS with
 // coalesced loads and stores.  Uses s_mv (>= 4 n ints).
-template <typename T>
+template <typename T, int NT>
 __device__ __forceinline__ void permute_rows(T* __restrict__ A, int w, int base, int n, const int32_t* __restrict__ piv, int c_lo,
                              int c_hi, int skip_lo, int skip_hi, T* __restrict__ pool, int32_t* __restrict__ s_mv,
                              int32_t* s_nmoves) {
-  constexpr int CHW = LuCfg<T>::CHW;
-  constexpr int NBO = LuCfg<T>::NBO;
+  constexpr int CHW = LuCfg<T, NT>::CHW;
+  constexpr int NBO = LuCfg<T, NT>::NBO;
   const int tid = threadIdx.x;
   // content of every position base + p of the range the interchanges can touch, after applying
   // them in order (a dense map in the pool, past the row-staging area)
   int32_t* cmap = reinterpret_cast<int32_t*>(pool + 2 * NBO * CHW);
   int32_t* msrc = s_mv;  // moves: (source row, destination row) pairs
   const int span = w - base;
-  for (int p = tid; p < span; p += kLuThreads) cmap[p] = base + p;
+  for (int p = tid; p < span; p += NT) cmap[p] = base + p;
   if (tid == 0) *s_nmoves = 0;
   __syncthreads();
   if (tid == 0) {
@@ -254,7 +268,7 @@ __device__ __forceinline__ void permute_rows(T* __restrict__ A, int w, int base,
     }
   }
   __syncthreads();
-  for (int p = tid; p < span; p += kLuThreads) {
+  for (int p = tid; p < span; p += NT) {
     const int c = cmap[p];
     if (c != base + p) {
       const int t = atomicAdd(s_nmoves, 1);
@@ -267,13 +281,13 @@ __device__ __forceinline__ void permute_rows(T* __restrict__ A, int w, int base,
   if (nm == 0) return;
   for (int cb = c_lo; cb < c_hi; cb += CHW) {
     if (cb + CHW > skip_lo && cb < skip_hi && cb >= skip_lo && cb + CHW <= skip_hi) continue;
-    for (int e = tid; e < nm * CHW; e += kLuThreads) {
+    for (int e = tid; e < nm * CHW; e += NT) {
       const int t = e / CHW, j = e % CHW;
       const int col = cb + j;
       if (col < c_hi && (col < skip_lo || col >= skip_hi)) pool[t * CHW + j] = A[(int64_t)msrc[2 * t] * w + col];
     }
     __syncthreads();
-    for (int e = tid; e < nm * CHW; e += kLuThreads) {
+    for (int e = tid; e < nm * CHW; e += NT) {
       const int t = e / CHW, j = e % CHW;
       const int col = cb + j;
       if (col < c_hi && (col < skip_lo || col >= skip_hi)) A[(int64_t)msrc[2 * t + 1] * w + col] = pool[t * CHW + j];
@@ -286,12 +300,12 @@ __device__ __forceinline__ void permute_rows(T* __restrict__ A, int w, int base,
 // lower n x n block at A[r0.., r0..] (n <= NMAX <= 32).  Column chunks are
 // staged through LDS with coalesced row-segment loads; each thread then
 // substitutes down one column in LDS; the chunk is stored back coalesced.
-template <typename T, int NMAX>
+template <typename T, int NMAX, int NT>
 __device__ __forceinline__ void block_row_solve(T* __restrict__ A, int w, int r0, int n, int c_lo, int c_hi,
                                                 T* __restrict__ Ls, T* __restrict__ pool) {
-  constexpr int CW = (64 * 1024) / (sizeof(T) * NMAX) < kLuThreads ? (64 * 1024) / (sizeof(T) * NMAX) : kLuThreads;
+  constexpr int CW = (64 * 1024) / (sizeof(T) * NMAX) < NT ? (64 * 1024) / (sizeof(T) * NMAX) : NT;
   const int tid = threadIdx.x;
-  for (int e = tid; e < n * n; e += kLuThreads) {
+  for (int e = tid; e < n * n; e += NT) {
     const int i = e / n, k = e % n;
     Ls[i * NMAX + k] = A[(int64_t)(r0 + i) * w + r0 + k];
   }
@@ -299,7 +313,7 @@ __device__ __forceinline__ void block_row_solve(T* __restrict__ A, int w, int r0
     const int nc = min(CW, c_hi - cb);
     __syncthreads();
 #pragma unroll 4
-    for (int e = tid; e < n * CW; e += kLuThreads) {
+    for (int e = tid; e < n * CW; e += NT) {
       const int i = e / CW, j = e % CW;
       if (j < nc) pool[i * CW + j] = A[(int64_t)(r0 + i) * w + cb + j];
     }
@@ -316,7 +330,7 @@ __device__ __forceinline__ void block_row_solve(T* __restrict__ A, int w, int r0
     }
     __syncthreads();
 #pragma unroll 4
-    for (int e = tid; e < n * CW; e += kLuThreads) {
+    for (int e = tid; e < n * CW; e += NT) {
       const int i = e / CW, j = e % CW;
       if (j < nc) A[(int64_t)(r0 + i) * w + cb + j] = pool[i * CW + j];
     }
@@ -340,11 +354,11 @@ __device__ __forceinline__ void static_for(F&& f) {
 // for column j), then block row bi of the inverse follows from
 // X[bi][bj] = -X[bi][bi] * sum_{bj <= k < bi} L[bi][k] X[k][bj] for all bj < bi
 // at once, with the whole workgroup on the products.
-template <typename T, int NB>
+template <typename T, int NB, int NT>
 __device__ __noinline__ void unit_lower_inverse(const T* __restrict__ L, T* __restrict__ X, int ld, int n) {
   constexpr int SB = 32, NSB = NB / SB;
-  constexpr int PER = (NSB > 1 ? (NSB - 1) * SB * SB : 1) / kLuThreads + 1;  // outputs per thread per block row
-  static_assert(NB % SB == 0 && NSB <= kLuWaves, "inverse blocking");
+  constexpr int PER = (NSB > 1 ? (NSB - 1) * SB * SB : 1) / NT + 1;  // outputs per thread per block row
+  static_assert(NB % SB == 0 && NSB <= NT / 64, "inverse blocking");
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   auto Lv = [&](int i, int k) -> T { return (i < n && k < n) ? L[i * ld + k] : T(0); };
   // 1. diagonal blocks
@@ -364,7 +378,7 @@ __device__ __noinline__ void unit_lower_inverse(const T* __restrict__ L, T* __re
   for (int bi = 1; bi < NSB; ++bi) {
     const int cnt = bi * SB * SB;
     // S[bi][bj] = sum_{bj <= k < bi} L[bi][k] X[k][bj], staged in the X[bi][bj] slots
-    for (int e = tid; e < cnt; e += kLuThreads) {
+    for (int e = tid; e < cnt; e += NT) {
       const int bj = e / (SB * SB), i = (e / SB) % SB, j = e % SB;
       const int r = bi * SB + i, c = bj * SB + j;
       T acc = T(0);
@@ -376,22 +390,21 @@ __device__ __noinline__ void unit_lower_inverse(const T* __restrict__ L, T* __re
     T out[PER];
 #pragma unroll
     for (int t = 0; t < PER; ++t) {
-      const int e = tid + t * kLuThreads;
+      const int e = tid + t * NT;
       out[t] = T(0);
       if (e < cnt) {
         const int bj = e / (SB * SB), i = (e / SB) % SB, j = e % SB;
         const T* Dinv = X + (bi * SB + i) * ld + bi * SB;   // row i of X[bi][bi]
         const T* Sc = X + (bi * SB) * ld + bj * SB + j;      // column j of S[bi][bj]
         T acc = T(0);
-#pragma unroll
-        for (int k = 0; k < SB; ++k) acc += Dinv[k] * Sc[k * ld];  // Dinv[k] = 0 above the diagonal
+        for (int k = 0; k <= i; ++k) acc += Dinv[k] * Sc[k * ld];  // X[bi][bi] is lower triangular
         out[t] = -acc;
       }
     }
     __syncthreads();
 #pragma unroll
     for (int t = 0; t < PER; ++t) {
-      const int e = tid + t * kLuThreads;
+      const int e = tid + t * NT;
       if (e < cnt) {
         const int bj = e / (SB * SB), i = (e / SB) % SB, j = e % SB;
         X[(bi * SB + i) * ld + bj * SB + j] = out[t];
@@ -400,7 +413,7 @@ __device__ __noinline__ void unit_lower_inverse(const T* __restrict__ L, T* __re
     __syncthreads();
   }
   // zeros above the diagonal blocks
-  for (int e = tid; e < NB * NB; e += kLuThreads) {
+  for (int e = tid; e < NB * NB; e += NT) {
     const int i = e / NB, j = e % NB;
     if (j / SB > i / SB) X[i * ld + j] = T(0);
   }
@@ -414,16 +427,16 @@ __device__ __noinline__ void unit_lower_inverse(const T* __restrict__ L, T* __re
 // inside the current outer block and to the columns right of it; columns left
 // of the block are never swapped, so the solve interleaves each block's
 // interchanges with its forward-substitution step.
-template <typename T, int R, int NBI>
-__global__ __launch_bounds__(kLuThreads) void lu_kernel(int32_t n_q, Plan plan, T* __restrict__ mats,
+template <typename T, int R, int NBI, int NT>
+__global__ __launch_bounds__(NT, 2) void lu_kernel(int32_t n_q, Plan plan, T* __restrict__ mats,
                                                         int32_t* __restrict__ piv) {
-  using C = LuCfg<T>;
+  using C = LuCfg<T, NT>;
   constexpr int NBO = C::NBO;
-  constexpr int BLOCK = kLuThreads, NW = kLuWaves;
+  constexpr int BLOCK = NT, NW = NT / 64;
   static_assert(NBO % NBI == 0 && NBI <= 32, "block shape");
   extern __shared__ __align__(16) unsigned char lds_raw[];
   T* pool = reinterpret_cast<T*>(lds_raw);
-  __shared__ T s_cand[2][kLuWaves][NBI];
+  __shared__ T s_cand[2][NW][NBI];
   __shared__ T s_redv[2][NW];
   __shared__ int32_t s_redr[2][NW];
   __shared__ int32_t s_piv[NBO];
@@ -570,12 +583,12 @@ __global__ __launch_bounds__(kLuThreads) void lu_kernel(int32_t n_q, Plan plan, 
         }
         __syncthreads();
         // this sub-panel's interchanges on the other columns of the outer block
-        permute_rows<T>(A, w, i0, nbi, s_piv + (i0 - p0), p0, p0 + nbo, i0, i0 + nbi, pool, s_mv, &s_nm);
+        permute_rows<T, NT>(A, w, i0, nbi, s_piv + (i0 - p0), p0, p0 + nbo, i0, i0 + nbi, pool, s_mv, &s_nm);
         const int cr = i0 + nbi;
         if (cr < p0 + nbo) {
           // pivot rows: solve against the sub-panel's unit lower block; rows below: rank-nbi update
-          block_row_solve<T, NBI>(A, w, i0, nbi, cr, p0 + nbo, s_L, pool);
-          tile_update<T>(A, w, cr, w, cr, p0 + nbo, i0, nbi, pool);
+          block_row_solve<T, NBI, NT>(A, w, i0, nbi, cr, p0 + nbo, s_L, pool);
+          tile_update<T, NT>(A, w, cr, w, cr, p0 + nbo, i0, nbi, pool);
         }
       }
       const int c0 = p0 + nbo;
@@ -584,7 +597,7 @@ __global__ __launch_bounds__(kLuThreads) void lu_kernel(int32_t n_q, Plan plan, 
         break;
       }
       // ===================== the block's interchanges on the columns right of it
-      permute_rows<T>(A, w, p0, nbo, s_piv, c0, w, 0, 0, pool, s_mv, &s_nm);
+      permute_rows<T, NT>(A, w, p0, nbo, s_piv, c0, w, 0, 0, pool, s_mv, &s_nm);
       // ===================== U12 = L11^{-1} A12: explicit inverse of the unit lower
       // block (one column per thread, in LDS), then a triangular product on the
       // matrix cores in 16-column strips per wave (zero blocks of the inverse skipped)
@@ -597,7 +610,7 @@ __global__ __launch_bounds__(kLuThreads) void lu_kernel(int32_t n_q, Plan plan, 
           L11[i * LDL + k] = A[(int64_t)(p0 + i) * w + p0 + k];
         }
         __syncthreads();
-        unit_lower_inverse<T, NBO>(L11, Linv, LDL, nbo);
+        unit_lower_inverse<T, NBO, NT>(L11, Linv, LDL, nbo);
         typedef typename Mfma<T>::v4 v4;
         const int li = lane & 15, lk = lane >> 4;
         const int n2 = w - c0;
@@ -631,7 +644,7 @@ __global__ __launch_bounds__(kLuThreads) void lu_kernel(int32_t n_q, Plan plan, 
         __syncthreads();
       }
       // ===================== trailing update A22 -= L21 U12 with K = nbo
-      tile_update<T>(A, w, c0, w, c0, w, p0, nbo, pool);
+      tile_update<T, NT>(A, w, c0, w, c0, w, p0, nbo, pool);
     }
     if (tid == 0 && zero_piv) plan.info[q] = zero_piv;
   }
@@ -643,6 +656,7 @@ __global__ __launch_bounds__(kLuThreads) void lu_kernel(int32_t n_q, Plan plan, 
 // coalesced row dot products).  Accumulation in FP64 whatever T is.
 constexpr int kSolveBS = 64;
 constexpr int kSolveThreads = 512;
+constexpr int kMaxSolveNbo = 128;
 
 // Value of a double in lane k (k uniform across the wave): two v_readlane, no LDS round trip.
 __device__ __forceinline__ double readlane_d(double v, int k) {
@@ -680,12 +694,12 @@ template <typename T>
 __global__ __launch_bounds__(kSolveThreads) void lu_solve_kernel(int32_t n_q, Plan plan, const T* __restrict__ mats,
                                                                  const int32_t* __restrict__ piv,
                                                                  const double* __restrict__ b, double* __restrict__ x,
-                                                                 int accumulate, const int32_t* __restrict__ active) {
+                                                                 int accumulate, const int32_t* __restrict__ active,
+                                                                 int NBO) {
+  // NBO: the factorisation's outer block (a multiple of kSolveBS, at most kMaxSolveNbo)
   extern __shared__ __align__(16) double y[];
   __shared__ double dblk[kSolveBS][kSolveBS + 1];
-  __shared__ int32_t spiv[LuCfg<T>::NBO];
-  constexpr int NBO = LuCfg<T>::NBO;
-  static_assert(NBO % kSolveBS == 0, "solve blocks must tile the factorisation blocks");
+  __shared__ int32_t spiv[kMaxSolveNbo];
   const int32_t q = blockIdx.x;
   if (plan.info[q] != 0) return;
   if (active && !active[q]) return;
@@ -774,28 +788,39 @@ int device_cus() {
   return cus;
 }
 
-template <typename T, int R, int NBI>
+template <typename T, int R, int NBI, int NT>
 hipError_t lu_go(int32_t n_q, Plan plan, void* mats, int32_t* piv, hipStream_t s) {
-  const size_t lds = sizeof(T) * lu_pool_elems<T>();
+  const size_t lds = sizeof(T) * lu_pool_elems<T, NT>();
   if (!g_capturing) {
-    const hipError_t e = hipFuncSetAttribute((const void*)lu_kernel<T, R, NBI>,
+    const hipError_t e = hipFuncSetAttribute((const void*)lu_kernel<T, R, NBI, NT>,
                                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
-  const int grid = max(1, min(n_q, device_cus()));
-  hipLaunchKernelGGL((lu_kernel<T, R, NBI>), dim3(grid), dim3(kLuThreads), lds, s, n_q, plan, (T*)mats, piv);
+  // NT = 512: one workgroup per CU; NT = 256: two (their LDS fits together)
+  const int grid = max(1, min(n_q, (512 / NT) * device_cus()));
+  hipLaunchKernelGGL((lu_kernel<T, R, NBI, NT>), dim3(grid), dim3(NT), lds, s, n_q, plan, (T*)mats, piv);
   return hipGetLastError();
 }
 
 }  // namespace
 
-// Register-panel configurations (R row slots per thread, NBI-wide sub-panels):
-// variant 0 is the widest sub-panel that fits the registers, variant 1 a
-// narrower one (fewer registers, more sub-panels per block).  Which is faster
-// depends on the widths of the batch; the autotuner times both.
+// Batched-LU configurations.  Widths up to 1536: variant 0 = 512 threads, 3 row
+// slots, the widest register sub-panel (32 FP32 / 16 FP64 columns); variant 1 = the
+// same with half-width sub-panels; variant 2 = 256 threads, 6 row slots, 64-column
+// outer blocks, two workgroups per CU.  Widths up to 4096: variants 0 and 1 with 8 row
+// slots.  Which is fastest depends on the batch; the autotuner times them.
 int lu_variant_count(int32_t prec, int32_t n_max) {
   (void)prec;
+  if (n_max <= 3 * kLuThreads) return 3;
   return n_max <= 8 * kLuThreads ? 2 : 0;
+}
+
+// Outer block width of a configuration (the triangular solves apply the row
+// interchanges block by block, so they need it).
+int lu_outer_block(int32_t prec, int32_t n_max, int variant) {
+  if (n_max <= 3 * kLuThreads && variant == 2)
+    return prec == ST_F64 ? LuCfg<double, 256>::NBO : LuCfg<float, 256>::NBO;
+  return prec == ST_F64 ? LuCfg<double, 512>::NBO : LuCfg<float, 512>::NBO;
 }
 
 hipError_t launch_lu(int32_t n_q, Plan plan, int32_t prec, void* mats, int32_t* piv, int32_t n_max, int variant,
@@ -803,19 +828,24 @@ hipError_t launch_lu(int32_t n_q, Plan plan, int32_t prec, void* mats, int32_t* 
   if (n_q == 0) return hipSuccess;
   const bool f64 = prec == ST_F64;
   if (n_max <= 3 * kLuThreads) {
-    if (variant == 1) return f64 ? lu_go<double, 3, 8>(n_q, plan, mats, piv, s) : lu_go<float, 3, 16>(n_q, plan, mats, piv, s);
-    return f64 ? lu_go<double, 3, 16>(n_q, plan, mats, piv, s) : lu_go<float, 3, 32>(n_q, plan, mats, piv, s);
+    if (variant == 2)
+      return f64 ? lu_go<double, 6, 8, 256>(n_q, plan, mats, piv, s) : lu_go<float, 6, 16, 256>(n_q, plan, mats, piv, s);
+    if (variant == 1)
+      return f64 ? lu_go<double, 3, 8, 512>(n_q, plan, mats, piv, s) : lu_go<float, 3, 16, 512>(n_q, plan, mats, piv, s);
+    return f64 ? lu_go<double, 3, 16, 512>(n_q, plan, mats, piv, s) : lu_go<float, 3, 32, 512>(n_q, plan, mats, piv, s);
   }
   if (n_max <= 8 * kLuThreads) {
-    if (variant == 1) return f64 ? lu_go<double, 8, 4>(n_q, plan, mats, piv, s) : lu_go<float, 8, 8>(n_q, plan, mats, piv, s);
-    return f64 ? lu_go<double, 8, 8>(n_q, plan, mats, piv, s) : lu_go<float, 8, 16>(n_q, plan, mats, piv, s);
+    if (variant == 1)
+      return f64 ? lu_go<double, 8, 4, 512>(n_q, plan, mats, piv, s) : lu_go<float, 8, 8, 512>(n_q, plan, mats, piv, s);
+    return f64 ? lu_go<double, 8, 8, 512>(n_q, plan, mats, piv, s) : lu_go<float, 8, 16, 512>(n_q, plan, mats, piv, s);
   }
   return hipErrorInvalidValue;
 }
 
 hipError_t launch_lu_solve(int32_t n_q, Plan plan, int32_t prec, const void* mats, const int32_t* piv, const double* b,
-                           double* x, int accumulate, const int32_t* active, int32_t n_max, hipStream_t s) {
+                           double* x, int accumulate, const int32_t* active, int32_t n_max, int nbo, hipStream_t s) {
   if (n_q == 0) return hipSuccess;
+  if (nbo <= 0 || nbo % kSolveBS != 0 || nbo > kMaxSolveNbo) return hipErrorInvalidValue;
   const size_t lds = sizeof(double) * (size_t)n_max;
   if (!g_capturing) {
     const hipError_t e = hipFuncSetAttribute(prec == ST_F64 ? (const void*)lu_solve_kernel<double>
@@ -825,10 +855,10 @@ hipError_t launch_lu_solve(int32_t n_q, Plan plan, int32_t prec, const void* mat
   }
   if (prec == ST_F64) {
     hipLaunchKernelGGL(lu_solve_kernel<double>, dim3(n_q), dim3(kSolveThreads), lds, s, n_q, plan,
-                       (const double*)mats, piv, b, x, accumulate, active);
+                       (const double*)mats, piv, b, x, accumulate, active, nbo);
   } else {
     hipLaunchKernelGGL(lu_solve_kernel<float>, dim3(n_q), dim3(kSolveThreads), lds, s, n_q, plan, (const float*)mats,
-                       piv, b, x, accumulate, active);
+                       piv, b, x, accumulate, active, nbo);
   }
   return hipGetLastError();
 }

@@ -331,7 +331,7 @@ def st_graph_count() -> int:
     return int(lib().st_graph_count())
 
 
-LU_VARIANTS = 2
+LU_VARIANTS = 3
 
 
 def st_autotune(desc: RomDesc, rom: torch.Tensor, theta_A: torch.Tensor, theta_f: Optional[torch.Tensor] = None,

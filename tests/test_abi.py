@@ -156,7 +156,10 @@ def test_graph_and_autotune_host_calls():
     assert L.st_graph_count() == 0
     assert L.st_autotune_choice(7, 100) == -1           # bad precision
     assert L.st_autotune_choice(0, 1 << 20) == -1       # width out of range
-    assert L.st_autotune_set(1, 100, 2) == -1           # no such variant
+    assert L.st_autotune_set(1, 100, 3) == -1           # no such variant
+    assert L.st_autotune_set(1, 2000, 2) == -1          # the 256-thread variant is for widths <= 1536
+    assert L.st_autotune_set(1, 100, 2) == 0
+    assert L.st_autotune_set(1, 100, -1) == 0
     assert L.st_autotune_set(1, 100, 1) == 0
     assert L.st_autotune_choice(1, 100) == 1
     assert L.st_autotune_set(1, 100, -1) == 0

@@ -44,16 +44,36 @@ def wide_rom():
     return DeviceRom(prob, Phi_s, Pt), Phi_s, Pt
 
 
-def _oracle_coeffs(prob, Phi_s, Phi_t, tA, tf, t0, nt=None):
+def _oracle_coeffs(prob, Phi_s, Phi_t, tA, tf, t0, nt=None, with_cond=False):
     Ahat = [orom.spatial_operator(Phi_s, A) for A in prob.terms]
     bhat = orom.reduced_vector(Phi_s, prob.Bf) if prob.Qf else np.zeros((Phi_s.shape[1], 0))
     u0hat = orom.reduced_vector(Phi_s, prob.u0) if prob.Q0 else np.zeros((Phi_s.shape[1], 0))
-    out = []
+    out, cond = [], []
     for q in range(tA.shape[0]):
         Pt = Phi_t if nt is None else [Phi_t[i][:, :int(nt[q][i])] for i in range(len(Phi_t))]
         M, b = orom.reduced_system(Ahat, tA[q], bhat, tf[q], prob.g, u0hat, t0[q], Pt, prob.dt)
         out.append(orom.solve(M, b))
-    return out
+        if with_cond:
+            cond.append(float(np.linalg.cond(M)))
+    return (out, cond) if with_cond else out
+
+
+U32 = 2.0 ** -24
+
+
+def _check_f32_factors(bufs, ref, cond):
+    """Plain FP32-LU solve (no refinement): a backward-stable factorization with
+    backward error below 20 u_32 gives a forward error below 20 kappa_2 u_32.
+    Broken factors (a wrong block of the trailing update, say) miss this by
+    orders of magnitude even where refinement would still converge."""
+    torch.cuda.synchronize()
+    coeff = bufs.coeff.cpu().numpy()
+    off = bufs.coeff_off.cpu().numpy()
+    errs = [_rel(coeff[off[q]:off[q + 1]], ref[q]) for q in range(len(ref))]
+    bounds = [20.0 * k * U32 for k in cond]
+    print("  FP32 factors: max err", f"{max(errs):.2e}", "min bound", f"{min(bounds):.2e}", flush=True)
+    for q, (e, bd) in enumerate(zip(errs, bounds)):
+        assert e <= bd, (q, e, bd)
 
 
 def _check(bufs, ref):
@@ -67,7 +87,7 @@ def _check(bufs, ref):
     return max(errs)
 
 
-@pytest.mark.parametrize("variant", [0, 1])
+@pytest.mark.parametrize("variant", [0, 1, 2])
 def test_lu_variants_match_oracle_ragged(cb_rom, variant):
     prob = C.problem("cb")
     Phi_s, sigma, V, Phi_t, ranks = C.oracle_bases("cb")
@@ -75,7 +95,7 @@ def test_lu_variants_match_oracle_ragged(cb_rom, variant):
     nt = W.ragged_profiles(12, 40, seed=42)
     nt[0] = 32   # one full-width query
     (tA, tf, t0), (dA, df, d0) = thetas_device(prob, mus)
-    ref = _oracle_coeffs(prob, Phi_s, Phi_t, tA, tf, t0, nt)
+    ref, cond = _oracle_coeffs(prob, Phi_s, Phi_t, tA, tf, t0, nt, with_cond=True)
     ntd = torch.tensor(nt, device="cuda")
     n = cb_rom.desc.n
     try:
@@ -85,6 +105,9 @@ def test_lu_variants_match_oracle_ragged(cb_rom, variant):
             b = strom.st_solve(cb_rom.desc, cb_rom.rom, dA, df, d0, ntd, lu_prec=prec,
                                ir_tol=1e-13 if prec == strom.ST_F32 else 0.0, ir_max=12 if prec == strom.ST_F32 else 0)
             print(f"  max rel err {_check(b, ref):.2e}")
+            if prec == strom.ST_F32:
+                b = strom.st_solve(cb_rom.desc, cb_rom.rom, dA, df, d0, ntd, lu_prec=prec, ir_max=0)
+                _check_f32_factors(b, ref, cond)
     finally:
         for prec in (strom.ST_F64, strom.ST_F32):
             strom.st_autotune_set(prec, n, -1)
@@ -96,7 +119,7 @@ def test_lu_variants_match_oracle_wide(wide_rom, variant):
     prob = dr.prob
     mus = W.sample_params(prob, 3, seed=43)
     (tA, tf, t0), (dA, df, d0) = thetas_device(prob, mus)
-    ref = _oracle_coeffs(prob, Phi_s, Pt, tA, tf, t0)
+    ref, cond = _oracle_coeffs(prob, Phi_s, Pt, tA, tf, t0, with_cond=True)
     n = dr.desc.n
     assert n > 1536
     try:
@@ -106,6 +129,9 @@ def test_lu_variants_match_oracle_wide(wide_rom, variant):
             b = strom.st_solve(dr.desc, dr.rom, dA, df, d0, None, lu_prec=prec,
                                ir_tol=1e-13 if prec == strom.ST_F32 else 0.0, ir_max=12 if prec == strom.ST_F32 else 0)
             print(f"  max rel err {_check(b, ref):.2e}")
+            if prec == strom.ST_F32:
+                b = strom.st_solve(dr.desc, dr.rom, dA, df, d0, None, lu_prec=prec, ir_max=0)
+                _check_f32_factors(b, ref, cond)
     finally:
         for prec in (strom.ST_F64, strom.ST_F32):
             strom.st_autotune_set(prec, n, -1)
@@ -122,7 +148,7 @@ def test_autotune_records_a_choice(cb_rom):
         print("[autotune] cb 64 queries FP32", flush=True)
         choice, ms = strom.st_autotune(cb_rom.desc, cb_rom.rom, dA, df, d0, ntd, strom.ST_F32)
         print(f"  choice {choice}, ms {ms}")
-        assert choice in (0, 1) and all(t > 0 for t in ms)
+        assert choice in (0, 1, 2) and all(t > 0 for t in ms)
         assert strom.st_autotune_choice(strom.ST_F32, n) == choice
         Phi_s, sigma, V, Phi_t, ranks = C.oracle_bases("cb")
         ref = _oracle_coeffs(prob, Phi_s, Phi_t, tA[:8], tf[:8], t0[:8], nt[:8])
