@@ -664,32 +664,66 @@ __device__ __forceinline__ double readlane_d(double v, int k) {
   const int hi = __builtin_amdgcn_readlane(__double2hiint(v), k);
   return __hiloint2double(hi, lo);
 }
-constexpr int kSolveRowsInFlight = 8;  // rows whose loads one wave issues before reducing them
 
-// y[r] -= A[r, b0 : b0 + 64] . y[b0 : b0 + 64] for the rows r in [r_begin, r_end) owned by
-// this wave (groups of kSolveRowsInFlight rows, strided by the workgroup); lane l holds
-// column b0 + l (inactive lanes pass lane_ok = false).  All loads of a group are issued
-// before any of its reductions, so a wave keeps that many rows in flight.
-template <typename T>
-__device__ __forceinline__ void solve_rows_update(const T* __restrict__ A, int w, int b0, bool lane_ok, double yl,
-                                                  int r_begin, int r_end, double* y) {
-  constexpr int NW = kSolveThreads / 64;
-  const int lane = threadIdx.x & 63;
-  for (int r = r_begin; r < r_end; r += NW * kSolveRowsInFlight) {
-    double a[kSolveRowsInFlight];
-#pragma unroll
-    for (int u = 0; u < kSolveRowsInFlight; ++u) {
-      const int rr = r + u;
-      a[u] = (lane_ok && rr < r_end) ? (double)A[(int64_t)rr * w + b0 + lane] : 0.0;
-    }
-#pragma unroll
-    for (int u = 0; u < kSolveRowsInFlight; ++u) {
-      const double s = __ockl_wfred_add_f64(a[u] * yl);
-      if (lane == 0 && r + u < r_end) y[r + u] -= s;
-    }
-  }
+// One DPP move of a double (both halves) within rows of 16 lanes.
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
 }
 
+// Sum over each row of 16 lanes, left in every lane of the row: exchanges with lane ^ 1 and
+// lane ^ 2 (quad permutes), then the half-row and row mirrors.  Both partners of every
+// exchange add the same two values, so all 16 lanes hold the identical total.  Must run
+// with the whole wave active.
+__device__ __forceinline__ double row16_sum(double v) {
+  v += dpp_d<0xB1>(v);   // quad_perm [1, 0, 3, 2]
+  v += dpp_d<0x4E>(v);   // quad_perm [2, 3, 0, 1]
+  v += dpp_d<0x141>(v);  // row_half_mirror
+  v += dpp_d<0x140>(v);  // row_mirror
+  return v;
+}
+
+constexpr int kSolveRowGroups = 4;  // groups of 4 rows whose loads a wave issues before reducing them
+
+// Rows [r, r + 4 kSolveRowGroups) of this wave's share of an update against the block
+// columns [b0, b0 + nbk): a row is spread over the 16 lanes of a DPP row (lane c holds
+// columns c, c + 16, c + 32, c + 48), so one load instruction covers 4 rows.
+template <typename T>
+struct SolveRows {
+  T a[kSolveRowGroups][4];
+  __device__ __forceinline__ void fetch(const T* __restrict__ A, int w, int b0, int nbk, int r, int r_end) {
+    const int lane = threadIdx.x & 63, sub = lane >> 4, c = lane & 15;
+#pragma unroll
+    for (int u = 0; u < kSolveRowGroups; ++u) {
+      const int rr = r + 4 * u + sub;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int col = c + 16 * j;
+        a[u][j] = (rr < r_end && col < nbk) ? A[(int64_t)rr * w + b0 + col] : T(0);
+      }
+    }
+  }
+  // y[rr] -= row . y_block with one 16-lane reduction per 4 rows; the whole wave must be active
+  __device__ __forceinline__ void reduce(const double (&yc)[4], int r, int r_end, double* y) const {
+    const int lane = threadIdx.x & 63, sub = lane >> 4, c = lane & 15;
+#pragma unroll
+    for (int u = 0; u < kSolveRowGroups; ++u) {
+      double p = 0.0;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) p += (double)a[u][j] * yc[j];
+      p = row16_sum(p);
+      const int rr = r + 4 * u + sub;
+      if (c == 0 && rr < r_end) y[rr] -= p;
+    }
+  }
+};
+
+// The factor data never depends on the right-hand side, so its loads run ahead of the
+// serial chain: the next diagonal block is fetched into registers during the current
+// block's update, and each wave's first row group of an update is fetched before the
+// diagonal solve that produces the y values it multiplies.
 template <typename T>
 __global__ __launch_bounds__(kSolveThreads) void lu_solve_kernel(int32_t n_q, Plan plan, const T* __restrict__ mats,
                                                                  const int32_t* __restrict__ piv,
@@ -697,9 +731,10 @@ __global__ __launch_bounds__(kSolveThreads) void lu_solve_kernel(int32_t n_q, Pl
                                                                  int accumulate, const int32_t* __restrict__ active,
                                                                  int NBO) {
   // NBO: the factorisation's outer block (a multiple of kSolveBS, at most kMaxSolveNbo)
+  constexpr int NW = kSolveThreads / 64, ROWS = 4 * kSolveRowGroups, STRIDE = NW * ROWS;
+  constexpr int DPT = kSolveBS * kSolveBS / kSolveThreads;  // diagonal-block entries per thread
   extern __shared__ __align__(16) double y[];
-  __shared__ double dblk[kSolveBS][kSolveBS + 1];
-  __shared__ int32_t spiv[kMaxSolveNbo];
+  __shared__ T dblk[kSolveBS][kSolveBS + 1];
   const int32_t q = blockIdx.x;
   if (plan.info[q] != 0) return;
   if (active && !active[q]) return;
@@ -709,66 +744,123 @@ __global__ __launch_bounds__(kSolveThreads) void lu_solve_kernel(int32_t n_q, Pl
   const T* A = mats + plan.mat_off[q];
   const int32_t* P = piv + off;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  T dreg[DPT];
+  auto fetch_dblk = [&](int b0) {
+    const int nbk = min(kSolveBS, w - b0);
+#pragma unroll
+    for (int t = 0; t < DPT; ++t) {
+      const int e = tid + t * kSolveThreads, i = e / kSolveBS, k = e % kSolveBS;
+      dreg[t] = (i < nbk && k < nbk) ? A[(int64_t)(b0 + i) * w + b0 + k] : T(0);
+    }
+  };
+  auto store_dblk = [&]() {
+#pragma unroll
+    for (int t = 0; t < DPT; ++t) {
+      const int e = tid + t * kSolveThreads;
+      dblk[e / kSolveBS][e % kSolveBS] = dreg[t];
+    }
+  };
+  // y values of the columns b0 + c + 16 j held by this lane for the row updates
+  auto y_cols = [&](int b0, int nbk, double (&yc)[4]) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int col = (lane & 15) + 16 * j;
+      yc[j] = col < nbk ? y[b0 + col] : 0.0;
+    }
+  };
+  SolveRows<T> rows;
   for (int c = tid; c < w; c += kSolveThreads) y[c] = b[off + c];
+  fetch_dblk(0);
   __syncthreads();
   // forward substitution, unit lower triangular, each outer block's interchanges first
   for (int b0 = 0; b0 < w; b0 += kSolveBS) {
     const int nbk = min(kSolveBS, w - b0);
-    if (b0 % NBO == 0) {
+    if (b0 % NBO == 0 && wave == 0) {
+      // the block's interchanges, in order, by lane 0; a 64-pivot chunk without any
+      // interchange (the common case) costs one ballot
       const int nblk = min(NBO, w - b0);
-      for (int i = tid; i < nblk; i += kSolveThreads) spiv[i] = P[b0 + i];
-      __syncthreads();
-      if (tid == 0) {
-        for (int i = 0; i < nblk; ++i) {
-          const int p = spiv[i];
-          if (p != b0 + i) {
-            const double t = y[b0 + i];
-            y[b0 + i] = y[p];
-            y[p] = t;
+      for (int i0 = 0; i0 < nblk; i0 += 64) {
+        const int i = i0 + lane;
+        const int p = i < nblk ? P[b0 + i] : b0 + i;
+        uint64_t m = __ballot(p != b0 + i);
+        while (m) {
+          const int l = __builtin_ctzll(m);
+          m &= m - 1;
+          const int pl = __builtin_amdgcn_readlane(p, l);
+          if (lane == 0) {
+            const double t = y[b0 + i0 + l];
+            y[b0 + i0 + l] = y[pl];
+            y[pl] = t;
           }
         }
       }
-      __syncthreads();
     }
-    for (int e = tid; e < nbk * kSolveBS; e += kSolveThreads) {
-      const int i = e / kSolveBS, k = e % kSolveBS;
-      dblk[i][k] = (k < nbk) ? (double)A[(int64_t)(b0 + i) * w + b0 + k] : 0.0;
-    }
+    store_dblk();
+    const int r0 = b0 + nbk + wave * ROWS;
+    rows.fetch(A, w, b0, nbk, r0, w);
     __syncthreads();
     if (wave == 0) {
+      // lane i holds y[b0 + i]; step k broadcasts y[b0 + k] and updates the lanes below it.
+      // The block's entries are read from LDS eight steps ahead of their use.
       double yi = lane < nbk ? y[b0 + lane] : 0.0;
-      for (int k = 0; k < nbk; ++k) {
-        const double yk = readlane_d(yi, k);
-        if (lane > k && lane < nbk) yi -= dblk[lane][k] * yk;
+      for (int k0 = 0; k0 < nbk; k0 += 8) {
+        double lk[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) lk[u] = (double)dblk[lane][k0 + u];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int k = k0 + u;
+          const double yk = readlane_d(yi, k);
+          if (lane > k && lane < nbk) yi -= lk[u] * yk;
+        }
       }
       if (lane < nbk) y[b0 + lane] = yi;
     }
+    if (b0 + kSolveBS < w) fetch_dblk(b0 + kSolveBS);
     __syncthreads();
-    const double yl = lane < nbk ? y[b0 + lane] : 0.0;
-    solve_rows_update(A, w, b0, lane < nbk, yl, b0 + nbk + wave * kSolveRowsInFlight, w, y);
+    double yc[4];
+    y_cols(b0, nbk, yc);
+    for (int r = r0; r < w; r += STRIDE) {
+      if (r != r0) rows.fetch(A, w, b0, nbk, r, w);
+      rows.reduce(yc, r, w, y);
+    }
     __syncthreads();
   }
-  // back substitution, upper triangular
+  // back substitution, upper triangular (reciprocals of the diagonal taken off the serial chain)
   const int last0 = ((w - 1) / kSolveBS) * kSolveBS;
+  fetch_dblk(last0);
   for (int b0 = last0; b0 >= 0; b0 -= kSolveBS) {
     const int nbk = min(kSolveBS, w - b0);
-    for (int e = tid; e < nbk * kSolveBS; e += kSolveThreads) {
-      const int i = e / kSolveBS, k = e % kSolveBS;
-      dblk[i][k] = (k < nbk) ? (double)A[(int64_t)(b0 + i) * w + b0 + k] : 0.0;
-    }
+    store_dblk();
+    const int r0 = wave * ROWS;
+    rows.fetch(A, w, b0, nbk, r0, b0);
     __syncthreads();
     if (wave == 0) {
       double yi = lane < nbk ? y[b0 + lane] : 0.0;
-      for (int k = nbk - 1; k >= 0; --k) {
-        const double yk = readlane_d(yi, k) / dblk[k][k];
-        if (lane == k) yi = yk;
-        if (lane < k) yi -= dblk[lane][k] * yk;
+      const double dinv = lane < nbk ? 1.0 / (double)dblk[lane][lane] : 0.0;
+      for (int k0 = ((nbk - 1) / 8) * 8; k0 >= 0; k0 -= 8) {
+        double uk[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) uk[u] = (double)dblk[lane][k0 + u];
+#pragma unroll
+        for (int u = 7; u >= 0; --u) {
+          const int k = k0 + u;
+          if (k >= nbk) continue;
+          const double yk = readlane_d(yi, k) * readlane_d(dinv, k);
+          if (lane == k) yi = yk;
+          if (lane < k) yi -= uk[u] * yk;
+        }
       }
       if (lane < nbk) y[b0 + lane] = yi;
     }
+    if (b0 > 0) fetch_dblk(b0 - kSolveBS);
     __syncthreads();
-    const double yl = lane < nbk ? y[b0 + lane] : 0.0;
-    solve_rows_update(A, w, b0, lane < nbk, yl, wave * kSolveRowsInFlight, b0, y);
+    double yc[4];
+    y_cols(b0, nbk, yc);
+    for (int r = r0; r < b0; r += STRIDE) {
+      if (r != r0) rows.fetch(A, w, b0, nbk, r, b0);
+      rows.reduce(yc, r, b0, y);
+    }
     __syncthreads();
   }
   for (int c = tid; c < w; c += kSolveThreads) {
