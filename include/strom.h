@@ -124,10 +124,12 @@ typedef struct {
  *   mode   n (int32)         spatial mode of reduced index a
  *   moff   n_s + 1 (int32)   mode offsets into the reduced index
  *   koff   n_s + 1 (int64)   element offsets of each K_i inside K
+ *   Phit   N_t x n           the concatenated temporal bases, column-major (Phit[k + N_t a] = phi_a(k))
+ *   dt     N_t               the time steps
  * where phi_a is column a of the concatenated temporal bases (mode-major).
  */
 typedef struct {
-  size_t Ahat, bhat, u0hat, T, K, Wf, P1, mode, moff, koff, total;
+  size_t Ahat, bhat, u0hat, T, K, Wf, P1, mode, moff, koff, Phit, dt, total;
 } st_rom_layout_t;
 
 st_status st_rom_layout(const st_rom_desc* d, st_rom_layout_t* out);
@@ -181,7 +183,8 @@ st_status st_build_bases(const void* U, int32_t U_prec, int64_t ldU, int64_t N_s
  * Phi_s^T (I - dt A) Phi_s = I - dt Ahat follows from Phi_s^T Phi_s = I.
  *
  * Temporal contractions (Sec. 4.3, Eq. (ij-block-matrix), (j-block-vector)):
- * T, K, Wf and P1 of the layout above, from the temporal bases and steps.
+ * T, K, Wf and P1 of the layout above, from the temporal bases and steps
+ * (which are also copied into the buffer: Phit and dt).
  *
  * d        [host] model shape; d->n_t must match the bases.
  * Phi_s    [dev] N_s x n_s (ld N_s); Phi_t [dev] N_t x n (ld N_t).

@@ -45,6 +45,8 @@ void layout_of(const st_rom_desc* d, st_rom_layout_t* L) {
   L->mode = o;  o = align_up(o + sizeof(int32_t) * n);
   L->moff = o;  o = align_up(o + sizeof(int32_t) * (n_s + 1));
   L->koff = o;  o = align_up(o + sizeof(int64_t) * (n_s + 1));
+  L->Phit = o;  o = align_up(o + sizeof(double) * d->N_t * n);
+  L->dt = o;    o = align_up(o + sizeof(double) * d->N_t);
   L->total = o;
 }
 
@@ -63,6 +65,8 @@ RomView view_of(const st_rom_desc* d, const void* rom) {
   v.mode = reinterpret_cast<const int32_t*>(b + L.mode);
   v.moff = reinterpret_cast<const int32_t*>(b + L.moff);
   v.koff = reinterpret_cast<const int64_t*>(b + L.koff);
+  v.Phit = reinterpret_cast<const double*>(b + L.Phit);
+  v.dt = reinterpret_cast<const double*>(b + L.dt);
   v.n_s = d->n_s;
   v.N_t = d->N_t;
   v.n = (int32_t)total_nt(d);
@@ -173,6 +177,8 @@ st_status st_assemble(const st_rom_desc* d, int64_t N_s, const double* Phi_s, co
   mv.mode = reinterpret_cast<int32_t*>(rb + L.mode);
   mv.moff = reinterpret_cast<int32_t*>(rb + L.moff);
   mv.koff = reinterpret_cast<int64_t*>(rb + L.koff);
+  mv.Phit = reinterpret_cast<double*>(rb + L.Phit);
+  mv.dt = reinterpret_cast<double*>(rb + L.dt);
 
   Carver c(ws);
   double* Phir = c.take<double>((size_t)N_s * d->n_s);
@@ -198,6 +204,9 @@ st_status st_assemble(const st_rom_desc* d, int64_t N_s, const double* Phi_s, co
   ST_TRY(launch_tsgemm_w(d->N_t, (int32_t)n, (int32_t)n, Phi_t, 1, d->N_t, Phi_t, 1, d->N_t, dt, mv.T, (int32_t)n, part,
                          part_elems, s));
   ST_TRY(launch_temporal(Phi_t, d->N_t, (int32_t)n, dt, g, d->Qf, mt, mv, s));
+  // the bases and steps themselves, for the residual evaluated on the time grid
+  ST_TRY(launch_copy_cols(Phi_t, d->N_t, mv.Phit, d->N_t, d->N_t, (int)n, s));
+  ST_TRY(launch_copy_cols(dt, d->N_t, mv.dt, d->N_t, d->N_t, 1, s));
   return ST_OK;
 }
 

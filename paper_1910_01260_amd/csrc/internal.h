@@ -32,6 +32,8 @@ struct RomView {
   const int32_t* mode;  // n
   const int32_t* moff;  // n_s + 1
   const int64_t* koff;  // n_s + 1
+  const double* Phit;   // N_t x n, column-major (the concatenated temporal bases)
+  const double* dt;     // N_t
   int32_t n_s, N_t, n, Q, Qf, Q0;
 };
 
@@ -39,6 +41,7 @@ struct MutRomView {
   double *Ahat, *bhat, *u0hat, *T, *K, *Wf, *P1;
   int32_t *mode, *moff;
   int64_t* koff;
+  double *Phit, *dt;
 };
 
 inline size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }

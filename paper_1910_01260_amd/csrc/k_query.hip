@@ -7,6 +7,7 @@
 //     (T, K, Ahat_q), never from a stored matrix;
 //   * small bookkeeping kernels for iterative refinement.
 #include "internal.h"
+#include "wave_ops.h"
 
 namespace strom {
 namespace {
@@ -444,6 +445,105 @@ __global__ void fill_i32_kernel(int32_t* p, int64_t n, int32_t v) {
   if (i < n) p[i] = v;
 }
 
+// Residual r = b - Ahat_st(mu) x of each active query without the reduced matrix.  With
+// z_i = Phi_i x_i (the query's prefix of mode i's temporal basis, evaluated on the time
+// grid), the blocks of Eq. (ij-block-matrix) give
+//   (Ahat_st x)_i = Phi_i^T [ z_i - S z_i - dt .* sum_i' Ahat(mu)[i, i'] z_i' ],
+// S the one-step delay ((S z)(k) = z(k - 1), (S z)(0) = 0): the K_i blocks are the
+// first two terms, the dt-weighted Gram T the third.  One workgroup per query: z and the
+// bracket live in LDS (n_s x N_t each), the temporal bases are read twice per query and
+// are shared by all queries (L2 resident), instead of n^2 gathers of T per query.
+constexpr int kResMfThreads = 512;
+constexpr size_t kResMfMaxLds = 150 * 1024;  // dynamic LDS the matrix-free residual may take
+
+size_t residual_mf_lds_bytes(int n_s, int N_t, int w_max) {
+  return sizeof(double) * ((size_t)2 * n_s * N_t + (size_t)n_s * n_s + (size_t)w_max) +
+         sizeof(int32_t) * (2 * (size_t)n_s + 1) + sizeof(int16_t) * (size_t)w_max;
+}
+
+__global__ __launch_bounds__(kResMfThreads) void residual_mf_kernel(RomView rom, int32_t n_q,
+                                                                    const double* __restrict__ thA,
+                                                                    const int32_t* __restrict__ nt_q, Plan plan,
+                                                                    const double* __restrict__ rhs,
+                                                                    const double* __restrict__ x,
+                                                                    double* __restrict__ r,
+                                                                    const int32_t* __restrict__ active, int32_t w_max) {
+  extern __shared__ __align__(16) double sm[];
+  const int32_t q = blockIdx.x;
+  if (q >= n_q || plan.info[q] != 0) return;
+  if (active && !active[q]) return;
+  const int32_t w = plan.width[q];
+  if (w == 0) return;
+  const int n_s = rom.n_s, N_t = rom.N_t;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  double* Z = sm;                          // n_s x N_t, Z[i * N_t + k] = z_i(k)
+  double* V = Z + (size_t)n_s * N_t;       // n_s x N_t, the bracket
+  double* Ah = V + (size_t)n_s * N_t;      // n_s x n_s, Ah[i * n_s + i'] = Ahat(mu)[i, i']
+  double* xs = Ah + (size_t)n_s * n_s;     // w
+  int32_t* nt = reinterpret_cast<int32_t*>(xs + w_max);  // n_s
+  int32_t* loff = nt + n_s;                                // n_s + 1
+  int16_t* cmode = reinterpret_cast<int16_t*>(loff + n_s + 1);  // w: mode of each local column
+  const int64_t off = plan.coeff_off[q];
+  if (tid == 0) {
+    int32_t acc = 0;
+    for (int i = 0; i < n_s; ++i) {
+      const int32_t c = nt_q ? nt_q[(int64_t)q * n_s + i] : rom.moff[i + 1] - rom.moff[i];
+      nt[i] = c;
+      loff[i] = acc;
+      acc += c;
+    }
+    loff[n_s] = acc;
+  }
+  const int ns2 = n_s * n_s;
+  for (int e = tid; e < ns2; e += kResMfThreads) {
+    const int i = e / n_s, ip = e % n_s;
+    double v = 0.0;
+    for (int k = 0; k < rom.Q; ++k)
+      v = fma(thA[(int64_t)q * rom.Q + k], rom.Ahat[(int64_t)k * ns2 + (int64_t)ip * n_s + i], v);
+    Ah[e] = v;
+  }
+  for (int c = tid; c < w; c += kResMfThreads) xs[c] = x[off + c];
+  __syncthreads();
+  for (int m = tid; m < n_s; m += kResMfThreads)
+    for (int32_t c = loff[m]; c < loff[m + 1]; ++c) cmode[c] = (int16_t)m;
+  // z_i(k) = sum_j phi_(i,j)(k) x_(i,j): consecutive threads take consecutive k (coalesced)
+  for (int e = tid; e < n_s * N_t; e += kResMfThreads) {
+    const int i = e / N_t, k = e % N_t;
+    const double* ph = rom.Phit + (int64_t)rom.moff[i] * N_t + k;
+    const double* xv = xs + loff[i];
+    const int ni = nt[i];
+    double z = 0.0;
+    for (int j = 0; j < ni; ++j) z = fma(ph[(int64_t)j * N_t], xv[j], z);
+    Z[e] = z;
+  }
+  __syncthreads();
+  // bracket: z_i(k) - z_i(k - 1) - dt_k sum_i' Ahat(mu)[i, i'] z_i'(k)
+  for (int e = tid; e < n_s * N_t; e += kResMfThreads) {
+    const int i = e / N_t, k = e % N_t;
+    const double* ar = Ah + i * n_s;
+    double u = 0.0;
+    for (int ip = 0; ip < n_s; ++ip) u = fma(ar[ip], Z[ip * N_t + k], u);
+    V[e] = Z[e] - (k > 0 ? Z[e - 1] : 0.0) - rom.dt[k] * u;
+  }
+  __syncthreads();
+  // (Ahat_st x)_(i,j) = sum_k phi_(i,j)(k) V_i(k): 16 lanes per output (one DPP row), 4
+  // outputs per wave per pass; the pass count is uniform per wave
+  const int sub = lane >> 4, c16 = lane & 15;
+  constexpr int NW = kResMfThreads / 64;
+  for (int cb = wave * 4; cb < w; cb += NW * 4) {
+    const int c = cb + sub;
+    const bool ok = c < w;
+    const int m = ok ? cmode[c] : 0;
+    const double* ph = rom.Phit + (int64_t)(rom.moff[m] + (ok ? c - loff[m] : 0)) * N_t;
+    const double* vm = V + (size_t)m * N_t;
+    double acc = 0.0;
+    if (ok)
+      for (int k = c16; k < N_t; k += 16) acc = fma(ph[k], vm[k], acc);
+    acc = row16_sum(acc);
+    if (ok && c16 == 0) r[off + c] = rhs[off + c] - acc;
+  }
+}
+
 }  // namespace
 
 hipError_t launch_plan(int32_t n_q, int32_t n_s, const int32_t* moff, const int32_t* nt_q, const int32_t* skip,
@@ -509,8 +609,20 @@ hipError_t launch_residual(const RomView& rom, int32_t n_q, const double* thA, c
                            const double* rhs, const double* x, double* r, double* rnorm, const int32_t* active,
                            int32_t n_max, hipStream_t s) {
   if (n_q == 0 || n_max == 0) return hipSuccess;
-  const size_t lds = query_lds_bytes(rom.n_s, n_max) + sizeof(double) * n_max;
   hipError_t e = hipSuccess;
+  const size_t lds_mf = residual_mf_lds_bytes(rom.n_s, rom.N_t, n_max);
+  if (lds_mf <= kResMfMaxLds) {
+    if (!g_capturing) {
+      e = hipFuncSetAttribute((const void*)residual_mf_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_mf);
+      if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(residual_mf_kernel, dim3(n_q), dim3(kResMfThreads), lds_mf, s, rom, n_q, thA, nt_q, plan, rhs, x,
+                       r, active, n_max);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    return launch_vec_norms(n_q, plan, r, rnorm, s);
+  }
+  // n_s x N_t too large for LDS: gather the reduced operator from T and K instead
+  const size_t lds = query_lds_bytes(rom.n_s, n_max) + sizeof(double) * n_max;
   if (!g_capturing) {
     e = hipFuncSetAttribute((const void*)residual_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;

@@ -39,7 +39,7 @@ class st_rom_desc(ctypes.Structure):
 
 
 class st_rom_layout_t(ctypes.Structure):
-    _fields_ = [(k, ctypes.c_size_t) for k in ("Ahat", "bhat", "u0hat", "T", "K", "Wf", "P1", "mode", "moff", "koff",
+    _fields_ = [(k, ctypes.c_size_t) for k in ("Ahat", "bhat", "u0hat", "T", "K", "Wf", "P1", "mode", "moff", "koff", "Phit", "dt",
                                                "total")]
 
 
@@ -235,7 +235,7 @@ def st_assemble(desc: RomDesc, Phi_s: torch.Tensor, Phi_t: torch.Tensor, dt: tor
 def rom_section(desc: RomDesc, rom: torch.Tensor, name: str) -> torch.Tensor:
     """View of one FP64 section of a ROM buffer (flat)."""
     lay = st_rom_layout(desc)
-    order = ["Ahat", "bhat", "u0hat", "T", "K", "Wf", "P1", "mode", "moff", "koff", "total"]
+    order = ["Ahat", "bhat", "u0hat", "T", "K", "Wf", "P1", "mode", "moff", "koff", "Phit", "dt", "total"]
     i = order.index(name)
     b0, b1 = lay[name], lay[order[i + 1]]
     dtype = {"mode": torch.int32, "moff": torch.int32, "koff": torch.int64}.get(name, torch.float64)
