@@ -24,11 +24,14 @@ def problem(name):
         return W.transport2d_absorber()
     if name == "cs_small":
         return W.transport2d_absorber(nx=16, N_t=60)
+    if name == "c_long":
+        # 40 modes x 320 steps: the residual's n_s x N_t arrays exceed LDS (gather path)
+        return W.advdiff1d(N=128, N_t=320, n_train=4)
     raise KeyError(name)
 
 
 BASIS_SIZES = {"c1": (8, 8), "cb": (40, 32), "c2": (40, 20), "c2_small": (20, 12), "cs": (40, 30),
-               "cs_small": (12, 10)}
+               "cs_small": (12, 10), "c_long": (40, 4)}
 
 
 @functools.lru_cache(maxsize=None)

@@ -78,6 +78,9 @@ def test_projection_and_temporal_pieces(name, request):
     T = dr.section("T").cpu().numpy()[: n * n].reshape(n, n).T
     np.testing.assert_allclose(T, P.T @ (prob.dt[:, None] * P), rtol=0, atol=1e-14)
     np.testing.assert_allclose(dr.section("P1").cpu().numpy()[:n], P[0], rtol=0, atol=0)
+    # the bases and steps copied into the buffer for the residual
+    np.testing.assert_array_equal(dr.section("Phit").cpu().numpy()[: prob.N_t * n].reshape(n, prob.N_t).T, P)
+    np.testing.assert_array_equal(dr.section("dt").cpu().numpy()[: prob.N_t], prob.dt)
     K = dr.section("K").cpu().numpy()
     off = 0
     for Pi in Phi_t:
@@ -180,6 +183,20 @@ def test_solve_c2_small_fp64_and_fp32(c2s_rom):
     mus = W.sample_params(prob, 6)
     _solve_and_compare(c2s_rom, "c2_small", mus)
     _solve_and_compare(c2s_rom, "c2_small", mus, lu_prec=strom.ST_F32, ir_tol=1e-13, ir_max=12)
+
+
+def test_solve_long_horizon_gather_residual():
+    """N_t = 320 with 40 modes: the refinement residual takes the gather kernel over T and
+    K (its time-grid arrays do not fit in LDS); FP64 and FP32 + refinement vs the oracle."""
+    prob = C.problem("c_long")
+    Phi_s, sigma, V, Phi_t, ranks = C.oracle_bases("c_long")
+    assert 2 * 40 * prob.N_t * 8 > 150 * 1024
+    print(f"[c_long] building device ROM n = {sum(P.shape[1] for P in Phi_t)}", flush=True)
+    dr = DeviceRom(prob, Phi_s, Phi_t)
+    mus = W.sample_params(prob, 6, seed=13)
+    _solve_and_compare(dr, "c_long", mus)
+    relres, iters, errs = _solve_and_compare(dr, "c_long", mus, lu_prec=strom.ST_F32, ir_tol=1e-13, ir_max=12)
+    assert relres.max() <= 1e-13
 
 
 def test_solve_edge_widths(cb_rom):
