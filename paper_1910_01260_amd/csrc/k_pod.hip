@@ -18,6 +18,7 @@ namespace strom {
 namespace {
 
 constexpr int kOneWG = 1024;
+constexpr size_t kOrthMaxLds = 144 * 1024;  // columns staged in LDS up to this size
 
 // wavefront reductions of the device library (DPP based, all lanes active)
 extern "C" __device__ double __ockl_wfred_add_f64(double);
@@ -269,11 +270,20 @@ __global__ void rand_fill_kernel(double* X, int64_t p, int k, uint64_t seed) {
 // Orthonormalise the k columns of X (p x k, column-major) in place by
 // classical Gram-Schmidt applied twice per column; a column that loses all
 // but 1e-10 of its norm (dependent on the previous ones) is replaced by a
-// pseudo-random vector and orthogonalised again.
-__global__ __launch_bounds__(kOneWG) void orth_cgs2_kernel(double* X, int64_t p, int k, uint64_t seed) {
+// pseudo-random vector and orthogonalised again.  With IN_LDS the columns are
+// staged in LDS for the whole sweep (every column step touches all previous
+// columns, so a global round trip per step would dominate).
+template <bool IN_LDS>
+__global__ __launch_bounds__(kOneWG) void orth_cgs2_kernel(double* Xg, int64_t p, int k, uint64_t seed) {
+  extern __shared__ __align__(16) double xs_lds[];
   __shared__ double coef[256];
   __shared__ double red[kOneWG / 64];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = kOneWG / 64;
+  double* X = IN_LDS ? xs_lds : Xg;
+  if (IN_LDS) {
+    for (int64_t e = tid; e < p * k; e += kOneWG) X[e] = Xg[e];
+    __syncthreads();
+  }
   for (int j = 0; j < k; ++j) {
     double* xj = X + (int64_t)j * p;
     for (int attempt = 0; attempt < 4; ++attempt) {
@@ -309,6 +319,10 @@ __global__ __launch_bounds__(kOneWG) void orth_cgs2_kernel(double* X, int64_t p,
       for (int64_t r = tid; r < p; r += kOneWG) xj[r] = rand_pm(seed + 7919ULL * (attempt + 1), r, j);
       __syncthreads();
     }
+  }
+  if (IN_LDS) {
+    __syncthreads();
+    for (int64_t e = tid; e < p * k; e += kOneWG) Xg[e] = X[e];
   }
 }
 
@@ -700,7 +714,17 @@ hipError_t launch_rand_fill(double* X, int64_t p, int k, uint64_t seed, hipStrea
 }
 
 hipError_t launch_orth(double* X, int64_t p, int k, uint64_t seed, hipStream_t s) {
-  hipLaunchKernelGGL(orth_cgs2_kernel, dim3(1), dim3(kOneWG), 0, s, X, p, k, seed);
+  const size_t lds = sizeof(double) * (size_t)p * (size_t)k;
+  if (lds <= kOrthMaxLds) {
+    if (!g_capturing) {
+      const hipError_t e = hipFuncSetAttribute((const void*)orth_cgs2_kernel<true>,
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(orth_cgs2_kernel<true>, dim3(1), dim3(kOneWG), lds, s, X, p, k, seed);
+  } else {
+    hipLaunchKernelGGL(orth_cgs2_kernel<false>, dim3(1), dim3(kOneWG), 0, s, X, p, k, seed);
+  }
   return hipGetLastError();
 }
 
