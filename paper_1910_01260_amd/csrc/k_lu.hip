@@ -615,32 +615,70 @@ __global__ __launch_bounds__(NT, 2) void lu_kernel(int32_t n_q, Plan plan, T* __
         typedef typename Mfma<T>::v4 v4;
         const int li = lane & 15, lk = lane >> 4;
         const int n2 = w - c0;
-        // this wave's NBO x 16 strip: in the (now free) L11 area when all strips fit there,
-        // otherwise after the inverse (the pool is sized for either case)
-        constexpr bool kStripsInL11 = NW * NBO * 16 <= NBO * LDL;
-        T* Sb = (kStripsInL11 ? L11 : Linv + NBO * LDL) + wave * NBO * 16;
-        for (int st = wave; st * 16 < n2; st += NW) {
-          const int cs = c0 + st * 16;
-          for (int e = lane; e < NBO * 16; e += 64) {
-            const int k = e >> 4, j = e & 15;
-            Sb[e] = (k < nbo && cs + j < w) ? A[(int64_t)(p0 + k) * w + cs + j] : T(0);
-          }
-          __builtin_amdgcn_wave_barrier();
-          const int col = cs + li;
-#pragma unroll 1
-          for (int it = 0; it * 16 < nbo; ++it) {
-            v4 acc = {T(0), T(0), T(0), T(0)};
-            const T* Lrow = Linv + (16 * it + li) * LDL + lk;
-            const T* Bcol = Sb + lk * 16 + li;
-            const int kend = 4 * it + 4;  // the inverse is lower triangular
-            for (int kk = 0; kk < kend; ++kk) acc = Mfma<T>::op(Lrow[4 * kk], Bcol[kk * 64], acc);
+        if constexpr (NBO <= 64) {
+          // NBO = 64: this wave's 16-column strips of A12, read straight into the B-operand
+          // layout of the MFMA (lane (li, lk) holds rows 4 kk + lk of column li); the next
+          // strip's loads are in flight while the current one is multiplied
+          constexpr int KB = NBO / 4;
+          T bcur[KB], bnxt[KB];
+          auto load_b = [&](int st, T (&b)[KB]) {
+            const int col = c0 + st * 16 + li;
+            const bool ok = st * 16 < n2 && col < w;
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-              const int row = 16 * it + Mfma<T>::row(lk, r);
-              if (row < nbo && col < w) A[(int64_t)(p0 + row) * w + col] = acc[r];
+            for (int kk = 0; kk < KB; ++kk) {
+              const int k = 4 * kk + lk;
+              b[kk] = (ok && k < nbo) ? A[(int64_t)(p0 + k) * w + col] : T(0);
             }
+          };
+          load_b(wave, bcur);
+          for (int st = wave; st * 16 < n2; st += NW) {
+            load_b(st + NW, bnxt);
+            const int col = c0 + st * 16 + li;
+#pragma unroll 1
+            for (int it = 0; it * 16 < nbo; ++it) {
+              v4 acc = {T(0), T(0), T(0), T(0)};
+              const T* Lrow = Linv + (16 * it + li) * LDL + lk;
+              const int kend = 4 * it + 4;  // the inverse is lower triangular
+#pragma unroll
+              for (int kk = 0; kk < KB; ++kk)
+                if (kk < kend) acc = Mfma<T>::op(Lrow[4 * kk], bcur[kk], acc);
+#pragma unroll
+              for (int r = 0; r < 4; ++r) {
+                const int row = 16 * it + Mfma<T>::row(lk, r);
+                if (row < nbo && col < w) A[(int64_t)(p0 + row) * w + col] = acc[r];
+              }
+            }
+#pragma unroll
+            for (int kk = 0; kk < KB; ++kk) bcur[kk] = bnxt[kk];
           }
-          __builtin_amdgcn_wave_barrier();
+        } else {
+          // NBO = 128: this wave's NBO x 16 strip staged in LDS (in the now free L11 area when
+          // all strips fit there, otherwise after the inverse; the pool is sized for either case)
+          constexpr bool kStripsInL11 = NW * NBO * 16 <= NBO * LDL;
+          T* Sb = (kStripsInL11 ? L11 : Linv + NBO * LDL) + wave * NBO * 16;
+          for (int st = wave; st * 16 < n2; st += NW) {
+            const int cs = c0 + st * 16;
+            for (int e = lane; e < NBO * 16; e += 64) {
+              const int k = e >> 4, j = e & 15;
+              Sb[e] = (k < nbo && cs + j < w) ? A[(int64_t)(p0 + k) * w + cs + j] : T(0);
+            }
+            __builtin_amdgcn_wave_barrier();
+            const int col = cs + li;
+#pragma unroll 1
+            for (int it = 0; it * 16 < nbo; ++it) {
+              v4 acc = {T(0), T(0), T(0), T(0)};
+              const T* Lrow = Linv + (16 * it + li) * LDL + lk;
+              const T* Bcol = Sb + lk * 16 + li;
+              const int kend = 4 * it + 4;  // the inverse is lower triangular
+              for (int kk = 0; kk < kend; ++kk) acc = Mfma<T>::op(Lrow[4 * kk], Bcol[kk * 64], acc);
+#pragma unroll
+              for (int r = 0; r < 4; ++r) {
+                const int row = 16 * it + Mfma<T>::row(lk, r);
+                if (row < nbo && col < w) A[(int64_t)(p0 + row) * w + col] = acc[r];
+              }
+            }
+            __builtin_amdgcn_wave_barrier();
+          }
         }
         __syncthreads();
       }
