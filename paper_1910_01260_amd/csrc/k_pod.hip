@@ -284,31 +284,46 @@ __global__ __launch_bounds__(kOneWG) void orth_cgs2_kernel(double* Xg, int64_t p
     for (int64_t e = tid; e < p * k; e += kOneWG) X[e] = Xg[e];
     __syncthreads();
   }
+  // coef[l] = x_l . x_j for l < lim (one wave per dot, lanes over the rows)
+  auto dots = [&](const double* xj, int lim) {
+    for (int l = wave; l < lim; l += nw) {
+      const double* xl = X + (int64_t)l * p;
+      double s = 0.0;
+      for (int64_t r = lane; r < p; r += 64) s = fma(xl[r], xj[r], s);
+      s = __ockl_wfred_add_f64(s);
+      if (lane == 0) coef[l] = s;
+    }
+  };
+  // x_j -= sum_{l < j} coef[l] x_l; returns this thread's share of the new squared norm
+  auto project = [&](double* xj, int j) {
+    double nn = 0.0;
+    for (int64_t r = tid; r < p; r += kOneWG) {
+      double v = xj[r];
+      for (int l = 0; l < j; ++l) v = fma(-coef[l], X[(int64_t)l * p + r], v);
+      xj[r] = v;
+      nn = fma(v, v, nn);
+    }
+    return nn;
+  };
   for (int j = 0; j < k; ++j) {
     double* xj = X + (int64_t)j * p;
     for (int attempt = 0; attempt < 4; ++attempt) {
-      double n0 = 0.0;
-      for (int64_t r = tid; r < p; r += kOneWG) n0 = fma(xj[r], xj[r], n0);
-      n0 = sqrt(block_sum(n0, red));
-      for (int pass = 0; pass < 2 && j > 0; ++pass) {
-        for (int l = wave; l < j; l += nw) {
-          const double* xl = X + (int64_t)l * p;
-          double s = 0.0;
-          for (int64_t r = lane; r < p; r += 64) s = fma(xl[r], xj[r], s);
-          s = __ockl_wfred_add_f64(s);
-          if (lane == 0) coef[l] = s;
-        }
+      // first pass: the projections and the column's own squared norm (slot j) together
+      dots(xj, j + 1);
+      __syncthreads();
+      const double n0 = sqrt(coef[j]);
+      double nn;
+      if (j > 0) {
+        project(xj, j);
         __syncthreads();
-        for (int64_t r = tid; r < p; r += kOneWG) {
-          double v = xj[r];
-          for (int l = 0; l < j; ++l) v = fma(-coef[l], X[(int64_t)l * p + r], v);
-          xj[r] = v;
-        }
+        dots(xj, j);
         __syncthreads();
+        nn = project(xj, j);
+      } else {
+        nn = 0.0;
+        for (int64_t r = tid; r < p; r += kOneWG) nn = fma(xj[r], xj[r], nn);
       }
-      double n1 = 0.0;
-      for (int64_t r = tid; r < p; r += kOneWG) n1 = fma(xj[r], xj[r], n1);
-      n1 = sqrt(block_sum(n1, red));
+      const double n1 = sqrt(block_sum(nn, red));
       if (n1 > 1e-10 * n0 && n1 > 0.0) {
         const double inv = 1.0 / n1;
         for (int64_t r = tid; r < p; r += kOneWG) xj[r] *= inv;
