@@ -18,7 +18,8 @@ namespace strom {
 namespace {
 
 constexpr int kOneWG = 1024;
-constexpr size_t kOrthMaxLds = 144 * 1024;  // columns staged in LDS up to this size
+constexpr int kTsvdThreads = 1024;  // one workgroup per mode: one wave per column pair of a round
+constexpr size_t kOrthMaxLds = 144 * 1024;  // single-workgroup kernels stage their matrices in LDS up to this size
 
 // wavefront reductions of the device library (DPP based, all lanes active)
 extern "C" __device__ double __ockl_wfred_add_f64(double);
@@ -345,14 +346,22 @@ __global__ __launch_bounds__(kOneWG) void orth_cgs2_kernel(double* Xg, int64_t p
 // cyclic Jacobi in round-robin parallel order; eigenvalues descending in
 // evals, eigenvectors in the matching columns of Zout.  Work arrays A, Z
 // (k*k each) may be global memory; k <= 256.
-__global__ __launch_bounds__(kOneWG) void jacobi_eig_kernel(int k, double* A, double* Z, double* evals, double* Zout,
+template <bool IN_LDS>
+__global__ __launch_bounds__(kOneWG) void jacobi_eig_kernel(int k, double* Ag, double* Zg, double* evals, double* Zout,
                                                             int max_sweeps) {
+  extern __shared__ __align__(16) double az_lds[];
   __shared__ int sp[128], sq[128];
   __shared__ double sc[128], ss[128];
   __shared__ double red[kOneWG / 64];
   __shared__ int s_rot;
   __shared__ int s_rank[256];
   const int tid = threadIdx.x;
+  // with IN_LDS the matrix and the rotations are kept in LDS for all sweeps (every round
+  // touches two rows and two columns of each and ends in a barrier)
+  double* A = IN_LDS ? az_lds : Ag;
+  double* Z = IN_LDS ? az_lds + (size_t)k * k : Zg;
+  if (IN_LDS)
+    for (int e = tid; e < k * k; e += kOneWG) A[e] = Ag[e];
   for (int e = tid; e < k * k; e += kOneWG) Z[e] = (e % k == e / k) ? 1.0 : 0.0;
   const int kk = k + (k & 1);
   const int m = kk - 1;
@@ -433,6 +442,11 @@ __global__ __launch_bounds__(kOneWG) void jacobi_eig_kernel(int k, double* A, do
     const int i = e % k, j = e / k;
     Zout[i + (int64_t)s_rank[j] * k] = Z[e];
   }
+  if (IN_LDS)
+    for (int e = tid; e < k * k; e += kOneWG) {
+      Ag[e] = A[e];
+      Zg[e] = Z[e];
+    }
 }
 
 // Upper Cholesky factor of S (n x n, column-major) and its inverse:
@@ -528,12 +542,13 @@ __global__ void copy_cols_kernel(const double* src, int64_t ld_src, double* dst,
 // a4: temporal bases.  One workgroup per spatial mode i: Y_i[k, q] = V[q*N_t + k, i]
 // (N_t x n_mu) in LDS, one-sided Jacobi SVD, rank cut, DCT-II completion.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void temporal_svd_kernel(const double* __restrict__ V, int64_t ldV, int N_t, int n_mu,
+__global__ __launch_bounds__(kTsvdThreads) void temporal_svd_kernel(const double* __restrict__ V, int64_t ldV, int N_t, int n_mu,
                                                            const int32_t* __restrict__ moff, double tau_t,
                                                            double* __restrict__ Phi_t, int32_t* __restrict__ rank_out) {
   extern __shared__ __align__(16) double Ys[];  // N_t * n_mu, then n_mu norms
-  __shared__ double red[4];
-  __shared__ int redi[4];
+  constexpr int NWV = kTsvdThreads / 64;
+  __shared__ double red[NWV];
+  __shared__ int redi[NWV];
   __shared__ int s_rot;
   __shared__ int s_order[64];
   __shared__ double s_coef[512];
@@ -542,7 +557,7 @@ __global__ __launch_bounds__(256) void temporal_svd_kernel(const double* __restr
   const int c0 = moff[i], nt = moff[i + 1] - c0;
   double* out = Phi_t + (int64_t)c0 * N_t;
   double* nrm = Ys + (int64_t)N_t * n_mu;
-  for (int e = tid; e < N_t * n_mu; e += 256) {
+  for (int e = tid; e < N_t * n_mu; e += kTsvdThreads) {
     const int k = e % N_t, q = e / N_t;
     Ys[e] = V[(int64_t)q * N_t + k + (int64_t)i * ldV];
   }
@@ -553,7 +568,7 @@ __global__ __launch_bounds__(256) void temporal_svd_kernel(const double* __restr
     if (tid == 0) s_rot = 0;
     __syncthreads();
     for (int rnd = 0; rnd < m; ++rnd) {
-      for (int t = wave; t < nn / 2; t += 4) {
+      for (int t = wave; t < nn / 2; t += NWV) {
         int a, b;
         if (t == 0) { a = m; b = rnd; } else { a = (rnd + t) % m; b = (rnd - t + m) % m; }
         if (a > b) { const int x = a; a = b; b = x; }
@@ -587,7 +602,7 @@ __global__ __launch_bounds__(256) void temporal_svd_kernel(const double* __restr
     __syncthreads();
   }
   // column norms = singular values; order descending
-  for (int q = wave; q < n_mu; q += 4) {
+  for (int q = wave; q < n_mu; q += NWV) {
     double s = 0.0;
     for (int k = lane; k < N_t; k += 64) s = fma(Ys[(int64_t)q * N_t + k], Ys[(int64_t)q * N_t + k], s);
     s = __ockl_wfred_add_f64(s);
@@ -612,7 +627,7 @@ __global__ __launch_bounds__(256) void temporal_svd_kernel(const double* __restr
   for (int j = 0; j < keep; ++j) {
     const int q = s_order[j];
     const double inv = 1.0 / nrm[q];
-    for (int k = tid; k < N_t; k += 256) out[(int64_t)j * N_t + k] = Ys[(int64_t)q * N_t + k] * inv;
+    for (int k = tid; k < N_t; k += kTsvdThreads) out[(int64_t)j * N_t + k] = Ys[(int64_t)q * N_t + k] * inv;
     have = j + 1;
   }
   __syncthreads();
@@ -620,21 +635,21 @@ __global__ __launch_bounds__(256) void temporal_svd_kernel(const double* __restr
   double* cand = Ys;  // reuse LDS: N_t doubles
   for (int mfreq = 0; have < nt && mfreq < N_t; ++mfreq) {
     double c2 = 0.0;
-    for (int k = tid; k < N_t; k += 256) {
+    for (int k = tid; k < N_t; k += kTsvdThreads) {
       const double v = cos(M_PI * (double)mfreq * ((double)k + 0.5) / (double)N_t);
       cand[k] = v;
       c2 = fma(v, v, c2);
     }
     c2 = sqrt(block_sum(c2, red));
     for (int pass = 0; pass < 2 && have > 0; ++pass) {
-      for (int l = wave; l < have; l += 4) {
+      for (int l = wave; l < have; l += NWV) {
         double s = 0.0;
         for (int k = lane; k < N_t; k += 64) s = fma(out[(int64_t)l * N_t + k], cand[k], s);
         s = __ockl_wfred_add_f64(s);
         if (lane == 0) s_coef[l] = s;
       }
       __syncthreads();
-      for (int k = tid; k < N_t; k += 256) {
+      for (int k = tid; k < N_t; k += kTsvdThreads) {
         double v = cand[k];
         for (int l = 0; l < have; ++l) v = fma(-s_coef[l], out[(int64_t)l * N_t + k], v);
         cand[k] = v;
@@ -642,11 +657,11 @@ __global__ __launch_bounds__(256) void temporal_svd_kernel(const double* __restr
       __syncthreads();
     }
     double n2 = 0.0;
-    for (int k = tid; k < N_t; k += 256) n2 = fma(cand[k], cand[k], n2);
+    for (int k = tid; k < N_t; k += kTsvdThreads) n2 = fma(cand[k], cand[k], n2);
     n2 = sqrt(block_sum(n2, red));
     if (n2 >= 1e-2 * c2) {
       const double inv = 1.0 / n2;
-      for (int k = tid; k < N_t; k += 256) out[(int64_t)have * N_t + k] = cand[k] * inv;
+      for (int k = tid; k < N_t; k += kTsvdThreads) out[(int64_t)have * N_t + k] = cand[k] * inv;
       ++have;
     }
     __syncthreads();
@@ -656,16 +671,16 @@ __global__ __launch_bounds__(256) void temporal_svd_kernel(const double* __restr
   for (int j = 0; j < nt; ++j) {
     double* x = out + (int64_t)j * N_t;
     double mx = 0.0;
-    for (int k = tid; k < N_t; k += 256) mx = fmax(mx, fabs(x[k]));
+    for (int k = tid; k < N_t; k += kTsvdThreads) mx = fmax(mx, fabs(x[k]));
     mx = block_max(mx, red);
     int first = 0x7fffffff;
-    for (int k = tid; k < N_t; k += 256)
+    for (int k = tid; k < N_t; k += kTsvdThreads)
       if (mx > 0.0 && fabs(x[k]) >= 0.25 * mx) { first = k; break; }
     first = block_min_i(first, redi);
     const bool flip = mx > 0.0 && x[first] < 0.0;
     __syncthreads();
     if (flip)
-      for (int k = tid; k < N_t; k += 256) x[k] = -x[k];
+      for (int k = tid; k < N_t; k += kTsvdThreads) x[k] = -x[k];
     __syncthreads();
   }
 }
@@ -744,7 +759,17 @@ hipError_t launch_orth(double* X, int64_t p, int k, uint64_t seed, hipStream_t s
 }
 
 hipError_t launch_jacobi(int k, double* A, double* Z, double* evals, double* Zout, hipStream_t s) {
-  hipLaunchKernelGGL(jacobi_eig_kernel, dim3(1), dim3(kOneWG), 0, s, k, A, Z, evals, Zout, 60);
+  const size_t lds = sizeof(double) * 2 * (size_t)k * (size_t)k;
+  if (lds <= kOrthMaxLds) {
+    if (!g_capturing) {
+      const hipError_t e = hipFuncSetAttribute((const void*)jacobi_eig_kernel<true>,
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(jacobi_eig_kernel<true>, dim3(1), dim3(kOneWG), lds, s, k, A, Z, evals, Zout, 60);
+  } else {
+    hipLaunchKernelGGL(jacobi_eig_kernel<false>, dim3(1), dim3(kOneWG), 0, s, k, A, Z, evals, Zout, 60);
+  }
   return hipGetLastError();
 }
 
@@ -786,7 +811,7 @@ hipError_t launch_temporal_svd(const double* V, int64_t ldV, int N_t, int n_mu, 
   hipError_t e = hipFuncSetAttribute((const void*)temporal_svd_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(temporal_svd_kernel, dim3(n_s), dim3(256), lds, s, V, ldV, N_t, n_mu, moff, tau_t, Phi_t,
+  hipLaunchKernelGGL(temporal_svd_kernel, dim3(n_s), dim3(kTsvdThreads), lds, s, V, ldV, N_t, n_mu, moff, tau_t, Phi_t,
                      rank_out);
   return hipGetLastError();
 }
