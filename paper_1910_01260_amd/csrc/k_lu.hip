@@ -422,7 +422,7 @@ __device__ __noinline__ void unit_lower_inverse(const T* __restrict__ L, T* __re
 }
 
 // One workgroup factors one query at a time (persistent, work queue).  Row r of
-// the query is owned by thread r % 512 in register slot r / 512 (R slots) while
+// the query is owned by thread r % NT in register slot r / NT (R slots) while
 // its sub-panel is factored.  Pivoting is LAPACK-style partial pivoting; P[i]
 // receives the row swapped with row i at step i.  Interchanges are applied
 // inside the current outer block and to the columns right of it; columns left
@@ -691,8 +691,8 @@ __global__ __launch_bounds__(NT, 2) void lu_kernel(int32_t n_q, Plan plan, T* __
 
 // Solve (P^T L U) x = b for each active query: permute b, forward
 // substitution with the unit lower factor, back substitution with the upper
-// factor, in 64-row blocks (diagonal block by one wave, the rest as wave-wide
-// coalesced row dot products).  Accumulation in FP64 whatever T is.
+// factor, in 64-row blocks (diagonal block by one wave, the rows below or above
+// it updated with 16 lanes per row).  Accumulation in FP64 whatever T is.
 constexpr int kSolveBS = 64;
 constexpr int kSolveThreads = 512;
 constexpr int kMaxSolveNbo = 128;
