@@ -697,18 +697,23 @@ constexpr int kSolveBS = 64;
 constexpr int kSolveThreads = 512;
 constexpr int kMaxSolveNbo = 128;
 
-constexpr int kSolveRowGroups = 4;  // groups of 4 rows whose loads a wave issues before reducing them
+// Groups of 4 rows whose loads a wave issues together; with the next groups in flight while
+// the current ones are reduced this keeps the solve within 128 VGPRs (two workgroups per CU).
+template <typename T>
+constexpr int solve_row_groups() {
+  return sizeof(T) == 4 ? 4 : 3;
+}
 
-// Rows [r, r + 4 kSolveRowGroups) of this wave's share of an update against the block
+// Rows [r, r + 4 solve_row_groups<T>()) of this wave's share of an update against the block
 // columns [b0, b0 + nbk): a row is spread over the 16 lanes of a DPP row (lane c holds
 // columns c, c + 16, c + 32, c + 48), so one load instruction covers 4 rows.
 template <typename T>
 struct SolveRows {
-  T a[kSolveRowGroups][4];
+  T a[solve_row_groups<T>()][4];
   __device__ __forceinline__ void fetch(const T* __restrict__ A, int w, int b0, int nbk, int r, int r_end) {
     const int lane = threadIdx.x & 63, sub = lane >> 4, c = lane & 15;
 #pragma unroll
-    for (int u = 0; u < kSolveRowGroups; ++u) {
+    for (int u = 0; u < solve_row_groups<T>(); ++u) {
       const int rr = r + 4 * u + sub;
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
@@ -721,7 +726,7 @@ struct SolveRows {
   __device__ __forceinline__ void reduce(const double (&yc)[4], int r, int r_end, double* y) const {
     const int lane = threadIdx.x & 63, sub = lane >> 4, c = lane & 15;
 #pragma unroll
-    for (int u = 0; u < kSolveRowGroups; ++u) {
+    for (int u = 0; u < solve_row_groups<T>(); ++u) {
       double p = 0.0;
 #pragma unroll
       for (int j = 0; j < 4; ++j) p += (double)a[u][j] * yc[j];
@@ -743,7 +748,7 @@ __global__ __launch_bounds__(kSolveThreads) void lu_solve_kernel(int32_t n_q, Pl
                                                                  int accumulate, const int32_t* __restrict__ active,
                                                                  int NBO) {
   // NBO: the factorisation's outer block (a multiple of kSolveBS, at most kMaxSolveNbo)
-  constexpr int NW = kSolveThreads / 64, ROWS = 4 * kSolveRowGroups, STRIDE = NW * ROWS;
+  constexpr int NW = kSolveThreads / 64, ROWS = 4 * solve_row_groups<T>(), STRIDE = NW * ROWS;
   constexpr int DPT = kSolveBS * kSolveBS / kSolveThreads;  // diagonal-block entries per thread
   extern __shared__ __align__(16) double y[];
   __shared__ T dblk[kSolveBS][kSolveBS + 1];
@@ -833,8 +838,10 @@ __global__ __launch_bounds__(kSolveThreads) void lu_solve_kernel(int32_t n_q, Pl
     double yc[4];
     y_cols(b0, nbk, yc);
     for (int r = r0; r < w; r += STRIDE) {
-      if (r != r0) rows.fetch(A, w, b0, nbk, r, w);
+      SolveRows<T> nxt;  // the wave's next row group is in flight while this one is reduced
+      if (r + STRIDE < w) nxt.fetch(A, w, b0, nbk, r + STRIDE, w);
       rows.reduce(yc, r, w, y);
+      rows = nxt;
     }
     __syncthreads();
   }
@@ -870,8 +877,10 @@ __global__ __launch_bounds__(kSolveThreads) void lu_solve_kernel(int32_t n_q, Pl
     double yc[4];
     y_cols(b0, nbk, yc);
     for (int r = r0; r < b0; r += STRIDE) {
-      if (r != r0) rows.fetch(A, w, b0, nbk, r, b0);
+      SolveRows<T> nxt;
+      if (r + STRIDE < b0) nxt.fetch(A, w, b0, nbk, r + STRIDE, b0);
       rows.reduce(yc, r, b0, y);
+      rows = nxt;
     }
     __syncthreads();
   }
