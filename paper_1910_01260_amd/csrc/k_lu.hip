@@ -238,6 +238,80 @@ __device__ __forceinline__ void tile_update(T* __restrict__ A, int w, int r_lo, 
   }
 }
 
+// C[r, c] -= sum_{k < K} A[r, k0 + k] A[k0 + k, c] for r in [r_lo, r_hi), c in [c_lo, c_hi),
+// for the narrow updates inside a 64-column outer block (K <= 16, at most 16 NCT columns):
+// straight from global memory into MFMA registers, without LDS or barriers.  Every wave holds
+// the K x (c_hi - c_lo) right factor in the B-operand layout and walks its own 16-row tiles,
+// the next tile's loads in flight while the current one is multiplied.  Ends with a barrier.
+template <typename T, int NT, int NCT>
+__device__ __forceinline__ void narrow_update(T* __restrict__ A, int w, int r_lo, int r_hi, int c_lo, int c_hi, int k0,
+                                              int K) {
+  typedef typename Mfma<T>::v4 v4;
+  constexpr int NW = NT / 64, KS = 4;  // four MFMA k-steps of 4
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  T b[NCT][KS];
+#pragma unroll
+  for (int ct = 0; ct < NCT; ++ct)
+#pragma unroll
+    for (int kk = 0; kk < KS; ++kk) {
+      const int k = 4 * kk + lk, c = c_lo + 16 * ct + li;
+      b[ct][kk] = (k < K && c < c_hi) ? A[(int64_t)(k0 + k) * w + c] : T(0);
+    }
+  auto load_a = [&](int r0, T (&a)[KS]) {
+    const int r = r0 + li;
+#pragma unroll
+    for (int kk = 0; kk < KS; ++kk) {
+      const int k = 4 * kk + lk;
+      a[kk] = (r < r_hi && k < K) ? A[(int64_t)r * w + k0 + k] : T(0);
+    }
+  };
+  auto load_c = [&](int r0, v4 (&cc)[NCT]) {
+#pragma unroll
+    for (int ct = 0; ct < NCT; ++ct)
+#pragma unroll
+      for (int rr = 0; rr < 4; ++rr) {
+        const int row = r0 + Mfma<T>::row(lk, rr), col = c_lo + 16 * ct + li;
+        cc[ct][rr] = (row < r_hi && col < c_hi) ? A[(int64_t)row * w + col] : T(0);
+      }
+  };
+  const int ntile = (r_hi - r_lo + 15) / 16;
+  T a[KS];
+  v4 cc[NCT];
+  if (wave < ntile) {
+    load_a(r_lo + 16 * wave, a);
+    load_c(r_lo + 16 * wave, cc);
+  }
+  for (int t = wave; t < ntile; t += NW) {
+    const int r0 = r_lo + 16 * t;
+    const bool more = t + NW < ntile;
+    T an[KS];
+    v4 cn[NCT];
+    if (more) {
+      load_a(r0 + 16 * NW, an);
+      load_c(r0 + 16 * NW, cn);
+    }
+#pragma unroll
+    for (int ct = 0; ct < NCT; ++ct)
+#pragma unroll
+      for (int kk = 0; kk < KS; ++kk) cc[ct] = Mfma<T>::op(-a[kk], b[ct][kk], cc[ct]);
+#pragma unroll
+    for (int ct = 0; ct < NCT; ++ct)
+#pragma unroll
+      for (int rr = 0; rr < 4; ++rr) {
+        const int row = r0 + Mfma<T>::row(lk, rr), col = c_lo + 16 * ct + li;
+        if (row < r_hi && col < c_hi) A[(int64_t)row * w + col] = cc[ct][rr];
+      }
+    if (more) {
+#pragma unroll
+      for (int kk = 0; kk < KS; ++kk) a[kk] = an[kk];
+#pragma unroll
+      for (int ct = 0; ct < NCT; ++ct) cc[ct] = cn[ct];
+    }
+  }
+  __syncthreads();
+}
+
 // Row interchanges piv[0..n) (step i swaps rows base+i and piv[i] >= base+i),
 // composed into a list of moves "row dst receives the old content of row src"
 // (a position map in LDS: thread 0 applies the swaps, all threads list the changed
@@ -589,7 +663,10 @@ __global__ __launch_bounds__(NT, 2) void lu_kernel(int32_t n_q, Plan plan, T* __
         if (cr < p0 + nbo) {
           // pivot rows: solve against the sub-panel's unit lower block; rows below: rank-nbi update
           block_row_solve<T, NBI, NT>(A, w, i0, nbi, cr, p0 + nbo, s_L, pool);
-          tile_update<T, NT>(A, w, cr, w, cr, p0 + nbo, i0, nbi, pool);
+          if constexpr (NBO <= 64 && NBI <= 16)
+            narrow_update<T, NT, (NBO - NBI + 15) / 16>(A, w, cr, w, cr, p0 + nbo, i0, nbi);
+          else
+            tile_update<T, NT>(A, w, cr, w, cr, p0 + nbo, i0, nbi, pool);
         }
       }
       const int c0 = p0 + nbo;
