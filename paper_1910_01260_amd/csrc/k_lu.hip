@@ -354,6 +354,35 @@ __device__ __forceinline__ void permute_rows(T* __restrict__ A, int w, int base,
   __syncthreads();
   const int nm = *s_nmoves;
   if (nm == 0) return;
+  if constexpr (NBO <= 64) {
+    // 64-column blocks: the moved row segments go through registers, whole columns per
+    // round (every move of a column is read before any is written, as the moves may form
+    // cycles); a round holds up to KR values per thread, so a few moves cover all columns in
+    // one or two rounds.  Rounds touch disjoint columns, so only the reads and writes of one
+    // round are separated by a barrier.
+    constexpr int KR = 16;
+    const int cpr = max(1, (KR * NT) / nm);
+    for (int cb = c_lo; cb < c_hi; cb += cpr) {
+      const int nc = min(cpr, c_hi - cb);
+      const int tot = nm * nc;
+      T v[KR];
+#pragma unroll
+      for (int k = 0; k < KR; ++k) {
+        const int e = tid + k * NT;
+        const int t = e / nc, col = cb + e % nc;
+        v[k] = (e < tot && (col < skip_lo || col >= skip_hi)) ? A[(int64_t)msrc[2 * t] * w + col] : T(0);
+      }
+      __syncthreads();
+#pragma unroll
+      for (int k = 0; k < KR; ++k) {
+        const int e = tid + k * NT;
+        const int t = e / nc, col = cb + e % nc;
+        if (e < tot && (col < skip_lo || col >= skip_hi)) A[(int64_t)msrc[2 * t + 1] * w + col] = v[k];
+      }
+    }
+    __syncthreads();
+    return;
+  }
   for (int cb = c_lo; cb < c_hi; cb += CHW) {
     if (cb + CHW > skip_lo && cb < skip_hi && cb >= skip_lo && cb + CHW <= skip_hi) continue;
     for (int e = tid; e < nm * CHW; e += NT) {
