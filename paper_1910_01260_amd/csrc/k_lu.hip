@@ -400,6 +400,38 @@ __device__ __forceinline__ void permute_rows(T* __restrict__ A, int w, int base,
   }
 }
 
+// The same for at most 64 NT / 64 columns (the block rows inside a 64-column outer block):
+// lane c of the waves holds column c_lo + c of the n rows in registers (row loads are
+// coalesced across the lanes) and substitutes down it with the unit lower block broadcast
+// from LDS; two barriers in all.
+template <typename T, int NMAX, int NT>
+__device__ __forceinline__ void block_row_solve_narrow(T* __restrict__ A, int w, int r0, int n, int c_lo, int c_hi,
+                                                       T* __restrict__ Ls) {
+  const int tid = threadIdx.x;
+  for (int e = tid; e < n * n; e += NT) {
+    const int i = e / n, k = e % n;
+    Ls[i * NMAX + k] = A[(int64_t)(r0 + i) * w + r0 + k];
+  }
+  __syncthreads();
+  const int c = c_lo + tid;
+  if (c < c_hi) {
+    T x[NMAX];
+#pragma unroll
+    for (int i = 0; i < NMAX; ++i) x[i] = i < n ? A[(int64_t)(r0 + i) * w + c] : T(0);
+#pragma unroll
+    for (int i = 1; i < NMAX; ++i) {
+      T acc = x[i];
+#pragma unroll
+      for (int k = 0; k < i; ++k) acc -= Ls[i * NMAX + k] * x[k];
+      x[i] = acc;
+    }
+#pragma unroll
+    for (int i = 0; i < NMAX; ++i)
+      if (i < n) A[(int64_t)(r0 + i) * w + c] = x[i];
+  }
+  __syncthreads();
+}
+
 // Rows [r0, r0 + n) <- L^{-1} rows for the columns [c_lo, c_hi), L the unit
 // lower n x n block at A[r0.., r0..] (n <= NMAX <= 32).  Column chunks are
 // staged through LDS with coalesced row-segment loads; each thread then
@@ -691,7 +723,11 @@ __global__ __launch_bounds__(NT, 2) void lu_kernel(int32_t n_q, Plan plan, T* __
         const int cr = i0 + nbi;
         if (cr < p0 + nbo) {
           // pivot rows: solve against the sub-panel's unit lower block; rows below: rank-nbi update
-          block_row_solve<T, NBI, NT>(A, w, i0, nbi, cr, p0 + nbo, s_L, pool);
+          // (64-column blocks: register forms while the column's rows fit in 64 bytes)
+          if constexpr (NBO <= 64 && NBI * sizeof(T) <= 64)
+            block_row_solve_narrow<T, NBI, NT>(A, w, i0, nbi, cr, p0 + nbo, s_L);
+          else
+            block_row_solve<T, NBI, NT>(A, w, i0, nbi, cr, p0 + nbo, s_L, pool);
           if constexpr (NBO <= 64 && NBI <= 16)
             narrow_update<T, NT, (NBO - NBI + 15) / 16>(A, w, cr, w, cr, p0 + nbo, i0, nbi);
           else
