@@ -113,6 +113,37 @@ def test_lu_variants_match_oracle_ragged(cb_rom, variant):
             strom.st_autotune_set(prec, n, -1)
 
 
+@pytest.mark.parametrize("variant", [0, 1, 2])
+def test_lu_variants_edge_widths(cb_rom, variant):
+    """Width 1, two-mode queries, the full width, ragged profiles with zero-width modes and
+    widths that are not multiples of any tile, for every LU configuration and precision."""
+    prob = C.problem("cb")
+    Phi_s, sigma, V, Phi_t, ranks = C.oracle_bases("cb")
+    nt = np.zeros((7, 40), dtype=np.int32)
+    nt[0, 0] = 1                                   # width 1
+    nt[1, 5] = 3; nt[1, 39] = 2                    # width 5, two modes
+    nt[2] = 32                                     # full width 1280
+    nt[3, :] = np.arange(40) % 33                  # ragged, zeros included
+    nt[4, ::3] = 17                                # 14 modes of 17: width 238
+    nt[5, :4] = [16, 16, 16, 17]                   # width 65: one column past a 64-column block
+    nt[6, :5] = [32, 32, 32, 31, 2]                # width 129
+    mus = W.sample_params(prob, len(nt), seed=49)
+    (tA, tf, t0), (dA, df, d0) = thetas_device(prob, mus)
+    ref = _oracle_coeffs(prob, Phi_s, Phi_t, tA, tf, t0, nt)
+    ntd = torch.tensor(nt, device="cuda")
+    n = cb_rom.desc.n
+    try:
+        for prec in (strom.ST_F64, strom.ST_F32):
+            strom.st_autotune_set(prec, n, variant)
+            print(f"[variant {variant}] edge widths prec={prec}", flush=True)
+            b = strom.st_solve(cb_rom.desc, cb_rom.rom, dA, df, d0, ntd, lu_prec=prec,
+                               ir_tol=1e-13 if prec == strom.ST_F32 else 0.0, ir_max=12 if prec == strom.ST_F32 else 0)
+            print(f"  max rel err {_check(b, ref):.2e}")
+    finally:
+        for prec in (strom.ST_F64, strom.ST_F32):
+            strom.st_autotune_set(prec, n, -1)
+
+
 @pytest.mark.parametrize("variant", [0, 1])
 def test_lu_variants_match_oracle_wide(wide_rom, variant):
     dr, Phi_s, Pt = wide_rom
