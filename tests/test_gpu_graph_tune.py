@@ -129,7 +129,7 @@ def test_lu_variants_edge_widths(cb_rom, variant):
     nt[6, :5] = [32, 32, 32, 31, 2]                # width 129
     mus = W.sample_params(prob, len(nt), seed=49)
     (tA, tf, t0), (dA, df, d0) = thetas_device(prob, mus)
-    ref = _oracle_coeffs(prob, Phi_s, Phi_t, tA, tf, t0, nt)
+    ref, cond = _oracle_coeffs(prob, Phi_s, Phi_t, tA, tf, t0, nt, with_cond=True)
     ntd = torch.tensor(nt, device="cuda")
     n = cb_rom.desc.n
     try:
@@ -139,6 +139,9 @@ def test_lu_variants_edge_widths(cb_rom, variant):
             b = strom.st_solve(cb_rom.desc, cb_rom.rom, dA, df, d0, ntd, lu_prec=prec,
                                ir_tol=1e-13 if prec == strom.ST_F32 else 0.0, ir_max=12 if prec == strom.ST_F32 else 0)
             print(f"  max rel err {_check(b, ref):.2e}")
+            if prec == strom.ST_F32:
+                b = strom.st_solve(cb_rom.desc, cb_rom.rom, dA, df, d0, ntd, lu_prec=prec, ir_max=0)
+                _check_f32_factors(b, ref, cond)
     finally:
         for prec in (strom.ST_F64, strom.ST_F32):
             strom.st_autotune_set(prec, n, -1)
