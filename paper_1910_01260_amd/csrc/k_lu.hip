@@ -312,6 +312,147 @@ __device__ __forceinline__ void narrow_update(T* __restrict__ A, int w, int r_lo
   __syncthreads();
 }
 
+// The same update as one flat sequence of RB x CB tiles, row-block major: the next tile's
+// operands are in flight while the current one runs on the matrix cores also across
+// row-block boundaries, where the next left-factor block comes from registers instead of a
+// fresh global round trip (one extra barrier).  Used by the 64-column FP32 trailing update.
+template <typename T, int NT>
+__device__ __forceinline__ void tile_update_flat(T* __restrict__ A, int w, int r_lo, int r_hi, int c_lo, int c_hi,
+                                                 int k0, int K, T* __restrict__ pool) {
+  using C = LuCfg<T, NT>;
+  constexpr int NBO = C::NBO, RB = C::RB, CB = C::CB;
+  constexpr int WR = NT / 128, LDK = NBO + 4, Q = NBO / 4;
+  constexpr int MR = RB / WR / 16, MC = CB / 2 / 16;
+  constexpr int PER = Vec4<T>::per, UPT = NBO * CB / NT, LPT = RB * NBO / NT;
+  static_assert(NBO * CB % NT == 0 && RB * NBO % NT == 0 && RB % (16 * WR) == 0, "update tile shape");
+  typedef typename Vec4<T>::type VT;
+  typedef typename Mfma<T>::v4 v4;
+  if (r_lo >= r_hi || c_lo >= c_hi || K <= 0) return;
+  T* Ls = pool;
+  T* Us0 = pool + RB * LDK;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int wr = (wave >> 1) * (RB / WR);
+  const int wc = (wave & 1) * (CB / 2);
+  const int ksteps = (K + 3) / 4;
+  const int kchunks = (ksteps + PER - 1) / PER;
+  const int ncb = (c_hi - c_lo + CB - 1) / CB;
+  const int ntiles = ncb * ((r_hi - r_lo + RB - 1) / RB);
+  auto load_acc = [&](int rb, int cb, v4 (&dst)[MR][MC]) {
+    const int nr = min(RB, r_hi - rb), nc = min(CB, c_hi - cb);
+#pragma unroll
+    for (int x = 0; x < MR; ++x)
+#pragma unroll
+      for (int y = 0; y < MC; ++y)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = wr + 16 * x + Mfma<T>::row(lk, r);
+          const int col = wc + 16 * y + li;
+          dst[x][y][r] = (row < nr && col < nc) ? A[(int64_t)(rb + row) * w + cb + col] : T(0);
+        }
+  };
+  T ur[UPT], lr[LPT];
+  auto load_u = [&](int cb) {
+    const int nc = min(CB, c_hi - cb);
+#pragma unroll
+    for (int t = 0; t < UPT; ++t) {
+      const int e = tid + t * NT;
+      const int k = e / CB, j = e % CB;
+      ur[t] = (k < K && j < nc) ? A[(int64_t)(k0 + k) * w + cb + j] : T(0);
+    }
+  };
+  auto store_u = [&](T* Us) {
+#pragma unroll
+    for (int t = 0; t < UPT; ++t) {
+      const int e = tid + t * NT;
+      const int k = e / CB, j = e % CB;
+      Us[j * LDK + kperm<T, NT>(k)] = ur[t];
+    }
+  };
+  auto load_l = [&](int rb) {
+    const int nr = min(RB, r_hi - rb);
+#pragma unroll
+    for (int t = 0; t < LPT; ++t) {
+      const int e = tid + t * NT;
+      const int i = e / NBO, k = e % NBO;
+      lr[t] = (i < nr && k < K) ? A[(int64_t)(rb + i) * w + k0 + k] : T(0);
+    }
+  };
+  auto store_l = [&]() {
+#pragma unroll
+    for (int t = 0; t < LPT; ++t) {
+      const int e = tid + t * NT;
+      const int i = e / NBO, k = e % NBO;
+      Ls[i * LDK + kperm<T, NT>(k)] = lr[t];
+    }
+  };
+  v4 acc[MR][MC];
+  __syncthreads();
+  load_u(c_lo);
+  load_acc(r_lo, c_lo, acc);
+  load_l(r_lo);
+  store_l();
+  store_u(Us0);
+  __syncthreads();
+  int buf = 0;
+  for (int t = 0; t < ntiles; ++t) {
+    const int rb = r_lo + (t / ncb) * RB, cb = c_lo + (t % ncb) * CB;
+    const int nr = min(RB, r_hi - rb), nc = min(CB, c_hi - cb);
+    const bool more = t + 1 < ntiles;
+    const int rbn = r_lo + ((t + 1) / ncb) * RB, cbn = c_lo + ((t + 1) % ncb) * CB;
+    const bool newrow = more && rbn != rb;
+    v4 nxt[MR][MC];
+    if (more) {  // successor tile in flight while this one runs on the matrix cores
+      load_u(cbn);
+      load_acc(rbn, cbn, nxt);
+      if (newrow) load_l(rbn);
+    }
+    const T* Us = Us0 + buf * CB * LDK;
+    for (int kc = 0; kc < kchunks; ++kc) {
+      VT av[MR], bv[MC];
+#pragma unroll
+      for (int x = 0; x < MR; ++x)
+        av[x] = *reinterpret_cast<const VT*>(Ls + (wr + 16 * x + li) * LDK + lk * Q + kc * PER);
+#pragma unroll
+      for (int y = 0; y < MC; ++y)
+        bv[y] = *reinterpret_cast<const VT*>(Us + (wc + 16 * y + li) * LDK + lk * Q + kc * PER);
+#pragma unroll
+      for (int p = 0; p < PER; ++p)
+#pragma unroll
+        for (int x = 0; x < MR; ++x)
+#pragma unroll
+          for (int y = 0; y < MC; ++y) {
+            const T a = -reinterpret_cast<const T*>(&av[x])[p];
+            const T b = reinterpret_cast<const T*>(&bv[y])[p];
+            acc[x][y] = Mfma<T>::op(a, b, acc[x][y]);
+          }
+    }
+#pragma unroll
+    for (int x = 0; x < MR; ++x)
+#pragma unroll
+      for (int y = 0; y < MC; ++y)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = wr + 16 * x + Mfma<T>::row(lk, r);
+          const int col = wc + 16 * y + li;
+          if (row < nr && col < nc) A[(int64_t)(rb + row) * w + cb + col] = acc[x][y][r];
+        }
+    if (more) {
+      store_u(Us0 + (buf ^ 1) * CB * LDK);
+#pragma unroll
+      for (int x = 0; x < MR; ++x)
+#pragma unroll
+        for (int y = 0; y < MC; ++y) acc[x][y] = nxt[x][y];
+    }
+    buf ^= 1;
+    __syncthreads();
+    if (newrow) {  // every wave is done with the current left-factor block
+      store_l();
+      __syncthreads();
+    }
+  }
+}
+
 // Row interchanges piv[0..n) (step i swaps rows base+i and piv[i] >= base+i),
 // composed into a list of moves "row dst receives the old content of row src"
 // (a position map in LDS: thread 0 applies the swaps, all threads list the changed
@@ -825,7 +966,10 @@ __global__ __launch_bounds__(NT, 2) void lu_kernel(int32_t n_q, Plan plan, T* __
         __syncthreads();
       }
       // ===================== trailing update A22 -= L21 U12 with K = nbo
-      tile_update<T, NT>(A, w, c0, w, c0, w, p0, nbo, pool);
+      if constexpr (NBO <= 64 && sizeof(T) == 4)
+        tile_update_flat<T, NT>(A, w, c0, w, c0, w, p0, nbo, pool);
+      else
+        tile_update<T, NT>(A, w, c0, w, c0, w, p0, nbo, pool);
     }
     if (tid == 0 && zero_piv) plan.info[q] = zero_piv;
   }
