@@ -300,6 +300,7 @@ __global__ __launch_bounds__(kOneWG) void orth_cgs2_kernel(double* Xg, int64_t p
     double nn = 0.0;
     for (int64_t r = tid; r < p; r += kOneWG) {
       double v = xj[r];
+#pragma unroll 8
       for (int l = 0; l < j; ++l) v = fma(-coef[l], X[(int64_t)l * p + r], v);
       xj[r] = v;
       nn = fma(v, v, nn);
