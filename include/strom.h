@@ -150,11 +150,19 @@ st_status st_rom_layout(const st_rom_desc* d, st_rom_layout_t* out);
  * tau_t    relative threshold of the numerical rank of each temporal
  *          snapshot matrix (singular values <= tau_t * largest are dropped).
  *
- * The POD is computed by the method of snapshots: the smaller of U^T U and
- * U U^T is formed, its leading n_s eigenpairs are found in FP64, the
- * spatial basis is re-orthonormalised (two Cholesky-QR passes), and each
- * temporal snapshot matrix Y_i (N_t x n_mu, Y_i[k,p] = v_i(p N_t + k)) is
- * decomposed by one-sided Jacobi.  Temporal bases keep the left singular
+ * The POD is computed by the method of snapshots, then refined to the SVD
+ * of U itself: the smaller of U^T U and U U^T is formed, its leading
+ * eigenpairs are found in FP64 by subspace iteration (n_s + min(32, extra)
+ * vectors, 10 iterations, Rayleigh-Ritz), and - because the Gram squares
+ * the condition number of U - two FP64 passes through U refine them: with
+ * X0 the leading k = n_s + (up to 16) eigenvectors, C1 = op(U) X0 and
+ * C2 = op(U)^T Y1 are each orthonormalised by a one-sided Jacobi SVD (Y1 the
+ * normalised columns of the first), which yields Phi_s, sigma and the right
+ * singular vectors.  The singular vectors then carry the accuracy of an SVD
+ * of U (error ~ eps sigma_1 / gap) rather than of its Gram (~ eps sigma_1^2
+ * / gap^2), down to modes at round-off.  Each temporal snapshot matrix Y_i
+ * (N_t x n_mu, Y_i[k,p] = v_i(p N_t + k)) is decomposed by one-sided Jacobi.
+ * If U has exact rank r < n_s the trailing columns are zero (sigma = 0).  Temporal bases keep the left singular
  * vectors above tau_t and are completed, when n_t[i] exceeds that rank,
  * with DCT-II vectors cos(pi m (k+1/2)/N_t), m = 0,1,..., each orthogonalised
  * twice against the kept vectors and accepted if >= 1e-2 of its norm
@@ -163,14 +171,29 @@ st_status st_rom_layout(const st_rom_desc* d, st_rom_layout_t* out);
  *
  * Outputs [dev]: Phi_s N_s x n_s (ld N_s); Phi_t N_t x n (ld N_t),
  * mode-major columns; sigma n_s singular values; rank_t n_s numerical ranks
- * of the temporal snapshot matrices (may be NULL).
+ * of the temporal snapshot matrices (may be NULL); diag ST_POD_DIAG doubles
+ * (may be NULL):
+ *   diag[0]  max_{i<n_s} ||G y_i - lambda_i y_i|| / lambda_1 of the Ritz pairs
+ *            of the subspace iteration (its convergence; the refinement
+ *            does not depend on it being small)
+ *   diag[1]  sweeps of the refinement's one-sided Jacobi that rotated (the
+ *            larger of its two runs; 30 means the sweep limit was reached)
+ *   diag[2]  largest |cos| between two columns seen in the last sweep of
+ *            either run (<= 1e-14 max(1, sqrt(rows / 65536)) once converged)
+ *   diag[3]  number of columns k of the refinement
+ *
+ * Limits (ST_EUNSUPPORTED beyond them): n_mu <= 64; N_t n_mu <= 15360
+ * (a temporal snapshot matrix is staged in 120 KB of LDS); n_t[i] <= 512;
+ * n_s <= 224 (n_s plus the 32 guard vectors of the subspace iteration
+ * <= 256); min(N_s, n_mu N_t) < 2^31.
  * ====================================================================== */
+#define ST_POD_DIAG 4
 size_t st_build_bases_workspace(int64_t N_s, int32_t N_t, int32_t n_mu, int32_t n_s, const int32_t* n_t,
                                 int32_t gram_prec);
 
 st_status st_build_bases(const void* U, int32_t U_prec, int64_t ldU, int64_t N_s, int32_t N_t, int32_t n_mu,
                          int32_t n_s, const int32_t* n_t, int32_t gram_prec, double tau_t,
-                         double* Phi_s, double* Phi_t, double* sigma, int32_t* rank_t,
+                         double* Phi_s, double* Phi_t, double* sigma, int32_t* rank_t, double* diag,
                          void* ws, size_t ws_bytes, void* stream);
 
 /* ========================================================================

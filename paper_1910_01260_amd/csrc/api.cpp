@@ -127,7 +127,7 @@ const char* st_strerror(st_status s) {
   }
 }
 
-int32_t st_version(void) { return 1; }
+int32_t st_version(void) { return 2; }
 
 st_status st_rom_layout(const st_rom_desc* d, st_rom_layout_t* out) {
   if (!desc_ok(d) || !out) return ST_EINVAL;
@@ -625,9 +625,12 @@ namespace {
 constexpr int kSubspaceIters = 10;
 constexpr int kMaxSubspace = 256;
 
+constexpr int kRefineExtra = 16;    // columns beyond n_s carried into the SVD refinement
+constexpr int kRefineSweeps = 30;   // sweep limit of the refinement's one-sided Jacobi
+
 struct PodDims {
   int64_t N_s, m, p;
-  int n_s, k, n;
+  int n_s, k, kr, n;
   bool transposed;  // Gram is U U^T (N_s < m)
 };
 
@@ -641,6 +644,7 @@ bool pod_dims(int64_t N_s, int32_t N_t, int32_t n_mu, int32_t n_s, const int32_t
   int64_t extra = d->p - n_s;
   if (extra > 32) extra = 32;
   d->k = (int)(n_s + (extra > 0 ? extra : 0));
+  d->kr = d->k < n_s + kRefineExtra ? d->k : n_s + kRefineExtra;
   int64_t n = 0;
   for (int i = 0; i < n_s; ++i) n += n_t[i];
   d->n = (int)n;
@@ -648,8 +652,9 @@ bool pod_dims(int64_t N_s, int32_t N_t, int32_t n_mu, int32_t n_s, const int32_t
 }
 
 struct PodWs {
-  double *G, *X, *Y, *H, *Z, *Zs, *evals, *sig, *V, *P, *S, *Rinv, *part;
-  int32_t* moff;
+  double *G, *X, *Y, *H, *Z, *Zs, *evals, *sig, *V, *part;
+  double *C1, *C2, *Y1, *Y2, *J, *Jp, *sigk, *offmax, *diag;
+  int32_t *moff, *perm, *rot;
   size_t part_elems, total;
 };
 
@@ -665,15 +670,23 @@ PodWs pod_ws(const PodDims& d, void* base) {
   w.evals = c.take<double>(d.k);
   w.sig = c.take<double>(d.n_s);
   w.V = c.take<double>((size_t)d.m * d.n_s);
-  w.P = c.take<double>((size_t)d.N_s * d.n_s);
-  w.S = c.take<double>((size_t)d.n_s * d.n_s);
-  w.Rinv = c.take<double>((size_t)d.n_s * d.n_s);
+  w.C1 = c.take<double>((size_t)d.N_s * d.kr);
+  w.Y1 = c.take<double>((size_t)d.N_s * d.kr);
+  w.C2 = c.take<double>((size_t)d.m * d.kr);
+  w.Y2 = c.take<double>((size_t)d.m * d.kr);
+  w.J = c.take<double>((size_t)d.kr * d.kr);
+  w.Jp = c.take<double>((size_t)d.kr * d.n_s);
+  w.sigk = c.take<double>(d.k);
+  w.offmax = c.take<double>(kRefineSweeps);
+  w.diag = c.take<double>(ST_POD_DIAG);
   w.moff = c.take<int32_t>(d.n_s + 1);
+  w.perm = c.take<int32_t>(d.kr);
+  w.rot = c.take<int32_t>(kRefineSweeps);
   size_t pe = gram_partial_elems(d.transposed ? d.m : d.N_s, (int)d.p);
   const size_t cands[] = {tsgemm_partial_elems(d.p, (int)d.p, d.k), tsgemm_partial_elems(d.p, d.k, d.k),
-                          tsgemm_partial_elems(d.k, (int)d.p, d.k), tsgemm_partial_elems(d.N_s, (int)d.m, d.n_s),
-                          tsgemm_partial_elems(d.m, (int)d.N_s, d.n_s), tsgemm_partial_elems(d.N_s, d.n_s, d.n_s),
-                          tsgemm_partial_elems(d.n_s, (int)d.N_s, d.n_s)};
+                          tsgemm_partial_elems(d.k, (int)d.p, d.k), tsgemm_partial_elems(d.N_s, (int)d.m, d.kr),
+                          tsgemm_partial_elems(d.m, (int)d.N_s, d.kr), tsgemm_partial_elems(d.kr, (int)d.N_s, d.n_s),
+                          tsgemm_partial_elems(d.kr, (int)d.m, d.n_s)};
   for (size_t v : cands) pe = v > pe ? v : pe;
   w.part = c.take<double>(pe);
   w.part_elems = pe;
@@ -695,7 +708,8 @@ size_t st_build_bases_workspace(int64_t N_s, int32_t N_t, int32_t n_mu, int32_t 
 
 st_status st_build_bases(const void* U, int32_t U_prec, int64_t ldU, int64_t N_s, int32_t N_t, int32_t n_mu,
                          int32_t n_s, const int32_t* n_t, int32_t gram_prec, double tau_t, double* Phi_s,
-                         double* Phi_t, double* sigma, int32_t* rank_t, void* ws, size_t ws_bytes, void* stream) {
+                         double* Phi_t, double* sigma, int32_t* rank_t, double* diag, void* ws, size_t ws_bytes,
+                         void* stream) {
   PodDims d;
   if (!U || !Phi_s || !Phi_t || !sigma || !ws || !pod_dims(N_s, N_t, n_mu, n_s, n_t, &d)) return ST_EINVAL;
   if (U_prec != ST_F64 && U_prec != ST_F32) return ST_EINVAL;
@@ -711,7 +725,7 @@ st_status st_build_bases(const void* U, int32_t U_prec, int64_t ldU, int64_t N_s
   if (ws_bytes < st_build_bases_workspace(N_s, N_t, n_mu, n_s, n_t, gram_prec)) return ST_EWORKSPACE;
   hipStream_t s = static_cast<hipStream_t>(stream);
   PodWs w = pod_ws(d, ws);
-  const int p = (int)d.p, k = d.k, ns = d.n_s;
+  const int p = (int)d.p, k = d.k, ns = d.n_s, kr = d.kr;
   const bool f32in = U_prec == ST_F32;
 
   // a1: Gram of the snapshots (small side)
@@ -733,42 +747,77 @@ st_status st_build_bases(const void* U, int32_t U_prec, int64_t ldU, int64_t N_s
   ST_TRY(launch_tsgemm(p, k, k, w.X, 1, p, w.Y, 1, p, w.H, k, w.part, w.part_elems, s));    // H = X^T G X
   ST_TRY(launch_jacobi(k, w.H, w.Z, w.evals, w.Zs, s));
   ST_TRY(launch_tsgemm(k, p, k, w.X, p, 1, w.Zs, 1, k, w.Y, p, w.part, w.part_elems, s));   // Ritz vectors Y = X Zs
-  ST_TRY(launch_sqrt_clamp(w.evals, w.sig, ns, s));
+  // eigen-residual of the leading Ritz pairs (reported; the refinement below
+  // makes the result independent of how far the iteration converged)
+  ST_TRY(launch_tsgemm(p, p, ns, w.G, 1, p, w.Y, 1, p, w.X, p, w.part, w.part_elems, s));   // X = G Y (n_s cols)
+  ST_TRY(launch_ritz_residual(w.X, w.Y, p, ns, w.evals, w.diag, s));
 
-  // a3: spatial basis and right singular vectors
-  if (d.transposed) {
-    // eigenvectors of U U^T are the left singular vectors
-    ST_TRY(launch_copy_cols(w.Y, p, Phi_s, N_s, N_s, ns, s));
-    ST_TRY(launch_sign_fix(Phi_s, N_s, ns, nullptr, 0, s));
-    // V = U^T Phi_s diag(1/sigma)
+  // a3: SVD refinement in FP64.  The Gram squares the condition number of U
+  // (its eigenvectors carry errors ~ eps sigma_1^2 / sigma_i^2, and modes below
+  // ~sqrt(eps) sigma_1 are noise), so two half-steps of a subspace iteration in
+  // factored form follow, each through U itself and each orthonormalised by a
+  // one-sided Jacobi SVD (robust to the graded and nearly dependent columns
+  // that plain Cholesky-QR would break down on):
+  //   X0 = leading kr eigenvectors of the Gram (orthonormal, on its side)
+  //   C1 = op(U) X0      -> Jacobi -> Y1 = normalised columns (other side)
+  //   C2 = op(U)^T Y1    -> Jacobi with rotations J -> Z = normalised columns,
+  //                         sigma = column norms, and Y1 J on the first side.
+  // With a Gram U^T U (m <= N_s) the first side is R^m, so Phi_s = Z and V = Y1 J;
+  // with U U^T the first side is R^N_s, so Phi_s = Y1 J and V = Z.
+  // Jacobi stops when every pair has |cos| <= tol: 1e-14, widened for very long
+  // columns where the rounding of the inner products themselves approaches it
+  const double tol_s = 1e-14 * fmax(1.0, sqrt((double)N_s / 65536.0));
+  const double tol_m = 1e-14 * fmax(1.0, sqrt((double)d.m / 65536.0));
+  if (!d.transposed) {
+    // C1 = U X0 (N_s x kr), X0 = Y[:, :kr] in R^m
     if (f32in)
-      ST_TRY(launch_tsgemm_xf(N_s, (int)d.m, ns, (const float*)U, 1, ldU, Phi_s, 1, N_s, w.V, (int)d.m, w.part,
+      ST_TRY(launch_tsgemm_xf(d.m, (int)N_s, kr, (const float*)U, ldU, 1, w.Y, 1, p, w.C1, (int)N_s, w.part,
                               w.part_elems, s));
     else
-      ST_TRY(launch_tsgemm(N_s, (int)d.m, ns, (const double*)U, 1, ldU, Phi_s, 1, N_s, w.V, (int)d.m, w.part,
+      ST_TRY(launch_tsgemm(d.m, (int)N_s, kr, (const double*)U, ldU, 1, w.Y, 1, p, w.C1, (int)N_s, w.part,
                            w.part_elems, s));
-    ST_TRY(launch_scale_or_refill(w.V, d.m, ns, w.sig, 0.0, seed + 101, s));
+    ST_TRY(launch_tall_jacobi(w.C1, N_s, kr, nullptr, w.rot, w.offmax, kRefineSweeps, tol_s, s));
+    ST_TRY(launch_tall_jacobi_finish(w.C1, N_s, kr, nullptr, kr, w.rot, w.offmax, kRefineSweeps, w.sigk, w.perm, w.Y1,
+                                     nullptr, w.diag, s));
+    // C2 = U^T Y1 (m x kr)
+    if (f32in)
+      ST_TRY(launch_tsgemm_xf(N_s, (int)d.m, kr, (const float*)U, 1, ldU, w.Y1, 1, N_s, w.C2, (int)d.m, w.part,
+                              w.part_elems, s));
+    else
+      ST_TRY(launch_tsgemm(N_s, (int)d.m, kr, (const double*)U, 1, ldU, w.Y1, 1, N_s, w.C2, (int)d.m, w.part,
+                           w.part_elems, s));
+    ST_TRY(launch_tall_jacobi(w.C2, d.m, kr, w.J, w.rot, w.offmax, kRefineSweeps, tol_m, s));
+    ST_TRY(launch_tall_jacobi_finish(w.C2, d.m, kr, w.J, ns, w.rot, w.offmax, kRefineSweeps, w.sig, w.perm, w.V,
+                                     w.Jp, w.diag, s));
+    // Phi_s = Y1 Jp (N_s x n_s)
+    ST_TRY(launch_tsgemm(kr, (int)N_s, ns, w.Y1, N_s, 1, w.Jp, 1, kr, Phi_s, (int)N_s, w.part, w.part_elems, s));
   } else {
-    // eigenvectors of U^T U are the right singular vectors; Phi_s = U V diag(1/sigma), re-orthonormalised
-    ST_TRY(launch_copy_cols(w.Y, p, w.V, d.m, d.m, ns, s));
+    // C1 = U^T X0 (m x kr), X0 = Y[:, :kr] in R^N_s
     if (f32in)
-      ST_TRY(launch_tsgemm_xf(d.m, (int)N_s, ns, (const float*)U, ldU, 1, w.V, 1, d.m, w.P, (int)N_s, w.part,
+      ST_TRY(launch_tsgemm_xf(N_s, (int)d.m, kr, (const float*)U, 1, ldU, w.Y, 1, p, w.C2, (int)d.m, w.part,
                               w.part_elems, s));
     else
-      ST_TRY(launch_tsgemm(d.m, (int)N_s, ns, (const double*)U, ldU, 1, w.V, 1, d.m, w.P, (int)N_s, w.part,
+      ST_TRY(launch_tsgemm(N_s, (int)d.m, kr, (const double*)U, 1, ldU, w.Y, 1, p, w.C2, (int)d.m, w.part,
                            w.part_elems, s));
-    ST_TRY(launch_scale_or_refill(w.P, N_s, ns, w.sig, 1e-13, seed + 102, s));
-    for (int pass = 0; pass < 2; ++pass) {
-      double* src = pass == 0 ? w.P : Phi_s;
-      double* dst = pass == 0 ? Phi_s : w.P;
-      ST_TRY(launch_tsgemm(N_s, ns, ns, src, 1, N_s, src, 1, N_s, w.S, ns, w.part, w.part_elems, s));
-      ST_TRY(launch_chol_inv(ns, w.S, w.Rinv, s));
-      ST_TRY(launch_tsgemm(ns, (int)N_s, ns, src, N_s, 1, w.Rinv, 1, ns, dst, (int)N_s, w.part, w.part_elems, s));
-    }
-    ST_TRY(launch_copy_cols(w.P, N_s, Phi_s, N_s, N_s, ns, s));
-    ST_TRY(launch_sign_fix(Phi_s, N_s, ns, w.V, d.m, s));
+    ST_TRY(launch_tall_jacobi(w.C2, d.m, kr, nullptr, w.rot, w.offmax, kRefineSweeps, tol_m, s));
+    ST_TRY(launch_tall_jacobi_finish(w.C2, d.m, kr, nullptr, kr, w.rot, w.offmax, kRefineSweeps, w.sigk, w.perm,
+                                     w.Y2, nullptr, w.diag, s));
+    // C2 = U Y1 (N_s x kr), Y1 in R^m
+    if (f32in)
+      ST_TRY(launch_tsgemm_xf(d.m, (int)N_s, kr, (const float*)U, ldU, 1, w.Y2, 1, d.m, w.C1, (int)N_s, w.part,
+                              w.part_elems, s));
+    else
+      ST_TRY(launch_tsgemm(d.m, (int)N_s, kr, (const double*)U, ldU, 1, w.Y2, 1, d.m, w.C1, (int)N_s, w.part,
+                           w.part_elems, s));
+    ST_TRY(launch_tall_jacobi(w.C1, N_s, kr, w.J, w.rot, w.offmax, kRefineSweeps, tol_s, s));
+    ST_TRY(launch_tall_jacobi_finish(w.C1, N_s, kr, w.J, ns, w.rot, w.offmax, kRefineSweeps, w.sig, w.perm, Phi_s,
+                                     w.Jp, w.diag, s));
+    // V = Y1 Jp (m x n_s)
+    ST_TRY(launch_tsgemm(kr, (int)d.m, ns, w.Y2, d.m, 1, w.Jp, 1, kr, w.V, (int)d.m, w.part, w.part_elems, s));
   }
+  ST_TRY(launch_sign_fix(Phi_s, N_s, ns, w.V, d.m, s));
   ST_TRY(launch_copy_cols(w.sig, ns, sigma, ns, ns, 1, s));
+  if (diag) ST_TRY(launch_copy_cols(w.diag, ST_POD_DIAG, diag, ST_POD_DIAG, ST_POD_DIAG, 1, s));
 
   // a4: temporal bases
   ModeTable mt;

@@ -93,6 +93,14 @@ hipError_t launch_sqrt_clamp(const double* lam, double* sigma, int n, hipStream_
 hipError_t launch_sign_fix(double* X, int64_t p, int k, double* Y, int64_t py, hipStream_t s);
 hipError_t launch_copy_cols(const double* src, int64_t ld_src, double* dst, int64_t ld_dst, int64_t p, int n,
                             hipStream_t s);
+// one-sided Jacobi SVD of the tall m x k matrix A (in place), rotations accumulated in J
+hipError_t launch_tall_jacobi(double* A, int64_t m, int k, double* J, int* rot, double* offmax, int max_sweeps,
+                              double tol, hipStream_t s);
+hipError_t launch_tall_jacobi_finish(const double* A, int64_t m, int k, const double* J, int n_out, const int* rot,
+                                     const double* offmax, int max_sweeps, double* sigma, int* perm, double* V,
+                                     double* Jp, double* diag, hipStream_t s);
+hipError_t launch_ritz_residual(const double* GY, const double* Y, int64_t p, int n, const double* evals, double* diag,
+                                hipStream_t s);
 hipError_t launch_temporal_svd(const double* V, int64_t ldV, int N_t, int n_mu, int n_s, const int32_t* moff,
                                double tau_t, double* Phi_t, int32_t* rank_out, hipStream_t s);
 

@@ -19,7 +19,8 @@ namespace {
 
 constexpr int kOneWG = 1024;
 constexpr int kTsvdThreads = 1024;  // one workgroup per mode: one wave per column pair of a round
-constexpr size_t kOrthMaxLds = 144 * 1024;  // single-workgroup kernels stage their matrices in LDS up to this size
+constexpr size_t kOrthMaxLds = 144 * 1024;
+constexpr int kMaxSubspaceDev = 256;  // column limit of the subspace kernels (k <= 256)  // single-workgroup kernels stage their matrices in LDS up to this size
 
 // wavefront reductions of the device library (DPP based, all lanes active)
 extern "C" __device__ double __ockl_wfred_add_f64(double);
@@ -540,6 +541,188 @@ __global__ void copy_cols_kernel(const double* src, int64_t ld_src, double* dst,
 }
 
 // ---------------------------------------------------------------------------
+// a3 refinement: one-sided (Hestenes) Jacobi SVD of the tall matrix B^T = U^T Q
+// (m x k, column-major in global memory), with Q an orthonormal basis of the
+// leading left singular subspace.  Because Q comes from the Gram eigenvectors,
+// the columns of B^T are already nearly orthogonal (preconditioned Jacobi): the
+// resolved modes converge in one or two sweeps, and the Gram's squaring of the
+// condition number is undone - the singular vectors are those of U itself, not
+// of U^T U.  The rotations are accumulated in J (k x k), so that the refined
+// left singular vectors are Q J and the right ones the normalised columns.
+// One launch per round of the round-robin (tournament) ordering, one workgroup
+// per column pair; rounds of a sweep touch disjoint pairs.
+// ---------------------------------------------------------------------------
+constexpr int kTallThreads = 256;
+
+// Pair `pr` of round `round` over kk (even) players: player 0 stays, the others rotate.
+__device__ inline void tournament_pair(int round, int pr, int kk, int& a, int& b) {
+  const int L = kk - 1;
+  if (pr == 0) {
+    a = 0;
+    b = 1 + round % L;
+  } else {
+    a = 1 + (round + pr) % L;
+    b = 1 + (round - pr + L) % L;
+  }
+}
+
+// atomic max of a non-negative double through its bit pattern (monotone for x >= 0)
+__device__ inline void atomic_max_nonneg(double* addr, double v) {
+  atomicMax(reinterpret_cast<unsigned long long*>(addr), (unsigned long long)__double_as_longlong(v));
+}
+
+__global__ __launch_bounds__(kTallThreads) void tall_jacobi_round_kernel(double* __restrict__ A, int64_t m, int k,
+                                                                          int kk, double* __restrict__ J, int round,
+                                                                          int sweep, int* __restrict__ rot,
+                                                                          double* __restrict__ offmax, double tol) {
+  __shared__ double red[3][kTallThreads / 64];
+  if (sweep > 0 && rot[sweep - 1] == 0) return;  // the previous sweep rotated nothing: converged
+  int a, b;
+  tournament_pair(round, blockIdx.x, kk, a, b);
+  if (a >= k || b >= k) return;  // padding player of an odd k
+  double* x = A + (int64_t)a * m;
+  double* y = A + (int64_t)b * m;
+  double saa = 0.0, sbb = 0.0, sab = 0.0;
+  for (int64_t r = threadIdx.x; r < m; r += kTallThreads) {
+    const double u = x[r], v = y[r];
+    saa = fma(u, u, saa);
+    sbb = fma(v, v, sbb);
+    sab = fma(u, v, sab);
+  }
+  saa = __ockl_wfred_add_f64(saa);
+  sbb = __ockl_wfred_add_f64(sbb);
+  sab = __ockl_wfred_add_f64(sab);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) {
+    red[0][wave] = saa;
+    red[1][wave] = sbb;
+    red[2][wave] = sab;
+  }
+  __syncthreads();
+  saa = sbb = sab = 0.0;
+  for (int w = 0; w < kTallThreads / 64; ++w) {
+    saa += red[0][w];
+    sbb += red[1][w];
+    sab += red[2][w];
+  }
+  const double scale = sqrt(saa) * sqrt(sbb);
+  const double off = scale > 0.0 ? fabs(sab) / scale : 0.0;
+  if (threadIdx.x == 0) atomic_max_nonneg(&offmax[sweep], off);
+  if (!(off > tol)) return;  // already orthogonal to the tolerance (uniform decision)
+  // rotation that zeroes the inner product of the pair
+  const double zeta = (sbb - saa) / (2.0 * sab);
+  const double t = copysign(1.0, zeta) / (fabs(zeta) + hypot(1.0, zeta));
+  const double c = 1.0 / sqrt(fma(t, t, 1.0));
+  const double s = c * t;
+  for (int64_t r = threadIdx.x; r < m; r += kTallThreads) {
+    const double u = x[r], v = y[r];
+    x[r] = c * u - s * v;
+    y[r] = s * u + c * v;
+  }
+  if (J)
+    for (int r = threadIdx.x; r < k; r += kTallThreads) {
+      const double u = J[r + (int64_t)a * k], v = J[r + (int64_t)b * k];
+      J[r + (int64_t)a * k] = c * u - s * v;
+      J[r + (int64_t)b * k] = s * u + c * v;
+    }
+  if (threadIdx.x == 0) atomicAdd(&rot[sweep], 1);
+}
+
+// After the sweeps: column norms (singular values), descending order (ties by
+// index), sigma and the permutation of the leading n_out; diagnostics
+// (accumulated over calls by maximum) diag[1] = sweeps that rotated, diag[2] =
+// largest |cos| between column pairs seen in the last sweep that ran; diag[3] = k.
+__global__ __launch_bounds__(kOneWG) void tall_jacobi_finish_kernel(const double* __restrict__ A, int64_t m, int k,
+                                                                     int n_out, const int* __restrict__ rot,
+                                                                     const double* __restrict__ offmax, int max_sweeps,
+                                                                     double* __restrict__ sigma, int* __restrict__ perm,
+                                                                     double* __restrict__ diag) {
+  __shared__ double nrm[kMaxSubspaceDev];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int j = wave; j < k; j += kOneWG / 64) {
+    const double* x = A + (int64_t)j * m;
+    double s = 0.0;
+    for (int64_t r = lane; r < m; r += 64) s = fma(x[r], x[r], s);
+    s = __ockl_wfred_add_f64(s);
+    if (lane == 0) nrm[j] = sqrt(s);
+  }
+  __syncthreads();
+  for (int j = tid; j < k; j += kOneWG) {
+    int rank = 0;
+    for (int l = 0; l < k; ++l) rank += (nrm[l] > nrm[j]) || (nrm[l] == nrm[j] && l < j);
+    if (rank < n_out) {
+      sigma[rank] = nrm[j];
+      perm[rank] = j;
+    }
+  }
+  if (tid == 0 && diag) {
+    int used = 0;
+    while (used < max_sweeps && rot[used] > 0) ++used;
+    const int last = used < max_sweeps ? used : max_sweeps - 1;
+    diag[1] = fmax(diag[1], (double)used);
+    diag[2] = fmax(diag[2], offmax[last]);
+    diag[3] = (double)k;
+  }
+}
+
+// V[:, r] = A[:, perm[r]] / sigma[r] (m rows; zero when sigma[r] = 0) and,
+// when J is given, Jp[:, r] = J[:, perm[r]] (k rows), r < n.
+__global__ void tall_jacobi_gather_kernel(const double* __restrict__ A, int64_t m, const double* __restrict__ J, int k,
+                                          const int* __restrict__ perm, const double* __restrict__ sigma, int n,
+                                          double* __restrict__ V, double* __restrict__ Jp) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t rows = m + k;
+  if (e >= rows * n) return;
+  const int r = (int)(e / rows);
+  const int64_t i = e % rows;
+  const int src = perm[r];
+  if (i < m) {
+    const double sg = sigma[r];
+    V[i + (int64_t)r * m] = sg > 0.0 ? A[i + (int64_t)src * m] / sg : 0.0;
+  } else if (J) {
+    const int64_t ii = i - m;
+    Jp[ii + (int64_t)r * k] = J[ii + (int64_t)src * k];
+  }
+}
+
+// J (k x k, if given) <- identity; rot[0..ns) <- 0, offmax[0..ns) <- 0
+__global__ void tall_jacobi_init_kernel(double* J, int k, int* rot, double* offmax, int ns) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (J && e < (int64_t)k * k) J[e] = (e % k == e / k) ? 1.0 : 0.0;
+  if (e < ns) {
+    rot[e] = 0;
+    offmax[e] = 0.0;
+  }
+}
+
+// diag[0] = max_{i < n} ||GY_i - lambda_i Y_i|| / lambda_0: the eigen-residual of
+// the Ritz pairs (Y p x n column-major, unit columns; GY = G Y).
+__global__ __launch_bounds__(kOneWG) void ritz_residual_kernel(const double* __restrict__ GY,
+                                                                const double* __restrict__ Y, int64_t p, int n,
+                                                                const double* __restrict__ evals,
+                                                                double* __restrict__ diag) {
+  __shared__ double red[kOneWG / 64];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  double worst = 0.0;
+  for (int j = wave; j < n; j += kOneWG / 64) {
+    const double lam = evals[j];
+    double s = 0.0;
+    for (int64_t r = lane; r < p; r += 64) {
+      const double d = GY[r + (int64_t)j * p] - lam * Y[r + (int64_t)j * p];
+      s = fma(d, d, s);
+    }
+    s = __ockl_wfred_add_f64(s);
+    worst = fmax(worst, sqrt(s));
+  }
+  worst = block_max(worst, red);
+  if (tid == 0) {
+    diag[0] = evals[0] > 0.0 ? worst / evals[0] : worst;
+    diag[1] = 0.0;
+    diag[2] = 0.0;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // a4: temporal bases.  One workgroup per spatial mode i: Y_i[k, q] = V[q*N_t + k, i]
 // (N_t x n_mu) in LDS, one-sided Jacobi SVD, rank cut, DCT-II completion.
 // ---------------------------------------------------------------------------
@@ -803,6 +986,44 @@ hipError_t launch_copy_cols(const double* src, int64_t ld_src, double* dst, int6
   if (e == 0) return hipSuccess;
   hipLaunchKernelGGL(copy_cols_kernel, dim3((unsigned)((e + 255) / 256)), dim3(256), 0, s, src, ld_src, dst, ld_dst, p,
                      n);
+  return hipGetLastError();
+}
+
+hipError_t launch_tall_jacobi(double* A, int64_t m, int k, double* J, int* rot, double* offmax, int max_sweeps,
+                              double tol, hipStream_t s) {
+  if (k < 1 || k > kMaxSubspaceDev || m < 1) return hipErrorInvalidValue;
+  const int64_t init = (int64_t)k * k > max_sweeps ? (int64_t)k * k : max_sweeps;
+  hipLaunchKernelGGL(tall_jacobi_init_kernel, dim3((unsigned)((init + 255) / 256)), dim3(256), 0, s, J, k, rot, offmax,
+                     max_sweeps);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || k < 2) return e;
+  const int kk = (k + 1) / 2 * 2;
+  for (int sw = 0; sw < max_sweeps; ++sw)
+    for (int r = 0; r < kk - 1; ++r) {
+      hipLaunchKernelGGL(tall_jacobi_round_kernel, dim3(kk / 2), dim3(kTallThreads), 0, s, A, m, k, kk, J, r, sw, rot,
+                         offmax, tol);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+  return hipSuccess;
+}
+
+hipError_t launch_tall_jacobi_finish(const double* A, int64_t m, int k, const double* J, int n_out, const int* rot,
+                                     const double* offmax, int max_sweeps, double* sigma, int* perm, double* V,
+                                     double* Jp, double* diag, hipStream_t s) {
+  if (k < 1 || k > kMaxSubspaceDev || n_out > k) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(tall_jacobi_finish_kernel, dim3(1), dim3(kOneWG), 0, s, A, m, k, n_out, rot, offmax, max_sweeps,
+                     sigma, perm, diag);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int64_t n = (m + k) * n_out;
+  hipLaunchKernelGGL(tall_jacobi_gather_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, A, m, J, k, perm,
+                     sigma, n_out, V, Jp);
+  return hipGetLastError();
+}
+
+hipError_t launch_ritz_residual(const double* GY, const double* Y, int64_t p, int n, const double* evals, double* diag,
+                                hipStream_t s) {
+  hipLaunchKernelGGL(ritz_residual_kernel, dim3(1), dim3(kOneWG), 0, s, GY, Y, p, n, evals, diag);
   return hipGetLastError();
 }
 

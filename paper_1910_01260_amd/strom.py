@@ -56,7 +56,8 @@ _SIGNATURES = {
     "st_version": (_I32, []),
     "st_rom_layout": (_I32, [ctypes.POINTER(st_rom_desc), ctypes.POINTER(st_rom_layout_t)]),
     "st_build_bases_workspace": (_SZ, [_I64, _I32, _I32, _I32, _P, _I32]),
-    "st_build_bases": (_I32, [_P, _I32, _I64, _I64, _I32, _I32, _I32, _P, _I32, _D, _P, _P, _P, _P, _P, _SZ, _P]),
+    "st_build_bases": (_I32, [_P, _I32, _I64, _I64, _I32, _I32, _I32, _P, _I32, _D, _P, _P, _P, _P, _P, _P, _SZ,
+                              _P]),
     "st_assemble_workspace": (_SZ, [ctypes.POINTER(st_rom_desc), _I64]),
     "st_assemble": (_I32, [ctypes.POINTER(st_rom_desc), _I64, _P, _P, _P, ctypes.POINTER(st_csr), _P, _P, _P, _P, _SZ,
                            _P, _SZ, _P]),
@@ -179,10 +180,15 @@ def csr_to_device(row_ptr, col_idx, val, device="cuda"):
     return d, (rp, ci, va)
 
 
+POD_DIAG = ("ritz_residual", "jacobi_sweeps", "jacobi_off", "refine_cols")
+
+
 def st_build_bases(U: torch.Tensor, N_t: int, n_mu: int, n_s: int, n_t: Sequence[int], gram_prec: int = ST_F64,
-                   tau_t: float = 1e-7):
+                   tau_t: float = 1e-7, diag: Optional[torch.Tensor] = None):
     """POD on the device.  U: (N_s, n_mu*N_t) column-major, i.e. a tensor whose
     transpose is contiguous (pass U.T.contiguous().T or torch.empty((m, N_s)).T).
+    diag: optional device float64 tensor of len(POD_DIAG) receiving the
+    convergence diagnostics.
     Returns (Phi_s (N_s x n_s, column-major view), Phi_t (N_t x n), sigma, rank_t)."""
     N_s = U.shape[0]
     if U.T.is_contiguous():
@@ -201,7 +207,8 @@ def st_build_bases(U: torch.Tensor, N_t: int, n_mu: int, n_s: int, n_t: Sequence
     sigma = torch.empty(n_s, dtype=torch.float64, device=U.device)
     rank = torch.empty(n_s, dtype=torch.int32, device=U.device)
     _check(lib().st_build_bases(ctypes.c_void_p(U.data_ptr()), prec, ld, N_s, N_t, n_mu, n_s, nt.ctypes.data, gram_prec,
-                                float(tau_t), _ptr(Phi_s), _ptr(Phi_t), _ptr(sigma), _ptr(rank), _ptr(ws), ws_bytes,
+                                float(tau_t), _ptr(Phi_s), _ptr(Phi_t), _ptr(sigma), _ptr(rank), _ptr(diag), _ptr(ws),
+                                ws_bytes,
                                 _stream()), "st_build_bases")
     return Phi_s.T, Phi_t.T, sigma, rank
 

@@ -42,7 +42,7 @@ def test_binding_names_match_header():
 
 
 def test_strerror_and_version():
-    assert strom.st_version() == 1
+    assert strom.st_version() == 2
     assert "workspace" in strom.st_strerror(-3)
     assert strom.st_strerror(12345) == "unknown status"
 

@@ -51,7 +51,7 @@ def c2s_rom():
 
 
 def test_library_version():
-    assert strom.st_version() == 1
+    assert strom.st_version() == 2
 
 
 @pytest.mark.parametrize("name", ["c1", "cb", "c2s"])

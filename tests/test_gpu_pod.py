@@ -1,11 +1,12 @@
 """GPU POD (st_build_bases) against the oracle's thin SVD.
 
 The oracle takes the SVD of U directly; the device path forms the snapshot
-Gram and solves its eigenproblem, which squares the condition number.  So
-singular values and vectors are compared on the well-resolved leading modes
-(sigma_i / sigma_1 above a floor and with a clear gap), and every basis is
-checked for orthonormality.  End to end, the ST-ROM solution built from the
-device bases is compared with the oracle's solution from the oracle bases.
+Gram, solves its eigenproblem, then refines in FP64 through U itself (a
+one-sided Jacobi SVD of U^T Q), so its singular vectors carry the accuracy of
+an SVD of U.  Singular values are compared on every mode, singular vectors
+within the SVD perturbation bound of each mode, and every basis is checked for
+orthonormality.  End to end, the ST-ROM solution built from the device bases is
+compared with the oracle's solution from the oracle bases.
 """
 import numpy as np
 import pytest
@@ -30,11 +31,132 @@ def _device_pod(name, gram_prec=strom.ST_F64, f32_storage=False):
     if f32_storage:
         Ud = torch.tensor(np.ascontiguousarray(U.T), dtype=torch.float32, device="cuda").T
     print(f"[{name}] st_build_bases N_s={U.shape[0]} m={U.shape[1]} n_s={n_s} prec={gram_prec}", flush=True)
-    Phi_s, Phi_t, sigma, rank = strom.st_build_bases(Ud, prob.N_t, len(prob.train_mu), n_s, [n_t] * n_s, gram_prec)
+    diag = torch.zeros(len(strom.POD_DIAG), dtype=torch.float64, device="cuda")
+    Phi_s, Phi_t, sigma, rank = strom.st_build_bases(Ud, prob.N_t, len(prob.train_mu), n_s, [n_t] * n_s, gram_prec,
+                                                     diag=diag)
     torch.cuda.synchronize()
+    dg = dict(zip(strom.POD_DIAG, diag.cpu().numpy().tolist()))
+    print(f"[{name}] diagnostics {dg}", flush=True)
     Pt = Phi_t.cpu().numpy()
     return (Phi_s.cpu().numpy(), [Pt[:, i * n_t:(i + 1) * n_t] for i in range(n_s)], sigma.cpu().numpy(),
-            rank.cpu().numpy())
+            rank.cpu().numpy(), dg)
+
+
+def _svd_vector_tol(osig, i, floor=1e-12):
+    """First-order perturbation bound of a singular vector of U under a backward
+    error ||E|| <= 2e-14 ||U||_2 (each side's SVD carries such an error):
+    sin(angle) <= 2 ||E|| / gap_i with gap_i the absolute distance of sigma_i
+    to its neighbours (Wedin)."""
+    s = osig
+    gap = min(s[i - 1] - s[i] if i > 0 else np.inf, s[i] - s[i + 1] if i + 1 < len(s) else np.inf)
+    return max(floor, 4e-14 * s[0] / gap) if gap > 0 else np.inf
+
+
+@pytest.mark.parametrize("name", ["c1", "cb", "c2_small", "c2"])
+def test_pod_matches_svd(name):
+    """Singular values to 1e-12 sigma_1 on every mode; singular vectors within the
+    SVD perturbation bound of each mode (1e-12 where the gap allows it)."""
+    Phi_s, Phi_t, sigma, rank, dg = _device_pod(name)
+    oPhi, osig, oV, oPt, oranks = C.oracle_bases(name)
+    n_s = Phi_s.shape[1]
+    np.testing.assert_allclose(Phi_s.T @ Phi_s, np.eye(n_s), atol=1e-13)
+    for P in Phi_t:
+        np.testing.assert_allclose(P.T @ P, np.eye(P.shape[1]), atol=1e-13)
+    rows = max(Phi_s.shape[0], len(oV))
+    assert dg["jacobi_sweeps"] < 30 and dg["jacobi_off"] <= 1e-14 * max(1.0, np.sqrt(rows / 65536)), dg
+    np.testing.assert_allclose(sigma, osig[:n_s], rtol=0, atol=1e-12 * osig[0])
+    checked = 0
+    worst = 0.0
+    for i in range(n_s):
+        tol = _svd_vector_tol(osig, i)
+        if tol > 1e-3:
+            continue
+        err = np.linalg.norm(Phi_s[:, i] - oPhi[:, i])
+        assert err <= tol, (i, err, tol)
+        worst = max(worst, err / tol)
+        checked += 1
+    print(f"[{name}] {checked} of {n_s} spatial vectors within their bound (worst {worst:.2f} of it)")
+    assert checked >= min(8, n_s)
+
+
+def _e2e(name, n_q=4, seed=21):
+    """Device POD -> device ROM -> device solve, against oracle POD (SVD) -> oracle
+    ROM -> LAPACK solve; both reconstructed on the space-time grid (the
+    comparison is independent of the basis).  Also the full-order trajectory."""
+    prob = C.problem(name)
+    Phi_s, Phi_t, sigma, rank, _ = _device_pod(name)
+    oPhi, osig, oV, oPt, _ = C.oracle_bases(name)
+    dr = DeviceRom(prob, Phi_s, Phi_t)
+    mus = W.sample_params(prob, n_q, seed=seed)
+    (tA, tf, t0), (dA, df, d0) = thetas_device(prob, mus)
+    out = strom.st_solve(dr.desc, dr.rom, dA, df, d0)
+    torch.cuda.synchronize()
+    assert (out.info.cpu().numpy()[:n_q] == 0).all()
+    coeff = out.coeff.cpu().numpy()
+    off = out.coeff_off.cpu().numpy()
+    Ahat, bhat, u0hat = C.oracle_spatial(name)
+    rows = []
+    for q in range(n_q):
+        M, b = orom.reduced_system(Ahat, tA[q], bhat, tf[q], prob.g, u0hat, t0[q], oPt, prob.dt)
+        ref = orom.reconstruct(oPhi, oPt, orom.solve(M, b))
+        got = orom.reconstruct(Phi_s, Phi_t, coeff[off[q]:off[q + 1]])
+        fom = W.march(prob, mus[q])
+        nf = np.linalg.norm(fom)
+        rows.append((np.linalg.norm(got - ref) / np.linalg.norm(ref), np.linalg.norm(ref - fom) / nf,
+                     np.linalg.norm(got - fom) / nf))
+    rows = np.array(rows)
+    print(f"[{name}] end-to-end: max rel diff device vs oracle ROM {rows[:, 0].max():.3e}; "
+          f"ROM error vs full order: oracle {rows[:, 1].max():.3e}, device {rows[:, 2].max():.3e}")
+    return rows, osig
+
+
+@pytest.mark.parametrize("name", ["c1", "c2"])
+def test_pod_end_to_end_solution(name):
+    """C1 and the full-size transport problem (64 x 64 x 12 unknowns, 200 steps,
+    40 modes x 20 temporal vectors): device ROM = oracle ROM to 1e-10."""
+    rows, _ = _e2e(name)
+    assert rows[:, 0].max() <= 1e-10
+
+
+def test_pod_cb_end_to_end_floor():
+    """The batching model has n_s = 40 spatial modes but only ~27 above round-off:
+    modes with sigma_i ~ eps sigma_1 are arbitrary directions in both PODs (any
+    SVD returns some orthonormal completion), so the two ROMs are different
+    Galerkin approximations and agree only to what those directions carry.
+    Floor: each ROM solution is a Galerkin approximation of the full-order one,
+    so ||u_dev - u_orc|| <= ||u_dev - u|| + ||u_orc - u||; the device ROM must be
+    as accurate as the oracle's (within a factor 2 + 1e-10), and the difference of
+    the two within that floor plus 1e-10."""
+    rows, osig = _e2e("cb")
+    n_round = int(np.sum(osig[:40] < 1e-13 * osig[0]))
+    print(f"[cb] {n_round} of 40 modes below 1e-13 sigma_1")
+    assert (rows[:, 2] <= 2 * rows[:, 1] + 1e-10).all()
+    assert (rows[:, 0] <= rows[:, 1] + rows[:, 2] + 1e-10).all()
+    # with the SVD refinement even the round-off modes agree within their
+    # perturbation bounds, and what they carry is below the FP64 parity bar
+    assert rows[:, 0].max() <= 1e-10
+
+
+def test_temporal_ranks_and_completion_c1():
+    """Every mode of C1 has rank(Y_i) = n_mu = 4 data vectors; the rest is the
+    DCT completion.  The data vectors match the oracle's within the SVD bound of
+    the temporal snapshot matrix (its input V carries ~1e-14 sigma_1/sigma_i)."""
+    Phi_s, Phi_t, sigma, rank, _ = _device_pod("c1")
+    oPhi, osig, oV, oPt, oranks = C.oracle_bases("c1")
+    np.testing.assert_array_equal(rank, oranks)
+    for i in range(8):
+        Y = opod.temporal_snapshot(oV, i, 128, 4)
+        sv = np.linalg.svd(Y, compute_uv=False)
+        eV = 1e-13 * osig[0] / osig[i]     # error of v_i, a unit vector
+        for j in range(min(int(rank[i]), 8)):
+            gap = min(sv[j - 1] - sv[j] if j else np.inf, sv[j] - sv[j + 1] if j + 1 < len(sv) else np.inf)
+            tol = max(1e-12, 4 * eV * sv[0] / gap)
+            if tol > 1e-3:
+                continue
+            assert np.linalg.norm(Phi_t[i][:, j] - oPt[i][:, j]) <= tol, (i, j, tol)
+        # completion vectors: same rule on both sides
+        np.testing.assert_allclose(Phi_t[i].T @ Phi_t[i], np.eye(8), atol=1e-13)
+        np.testing.assert_allclose(Phi_t[i][:, int(rank[i]):], oPt[i][:, int(rank[i]):], atol=1e-8)
 
 
 def _well_resolved(sigma, floor=1e-4, gap=1e-3):
@@ -48,68 +170,6 @@ def _well_resolved(sigma, floor=1e-4, gap=1e-3):
         if min(g_lo, g_hi) >= gap:
             out.append(i)
     return out
-
-
-@pytest.mark.parametrize("name", ["c1", "cb", "c2_small"])
-def test_pod_matches_svd_on_resolved_modes(name):
-    Phi_s, Phi_t, sigma, rank = _device_pod(name)
-    oPhi, osig, oV, oPt, oranks = C.oracle_bases(name)
-    n_s = Phi_s.shape[1]
-    np.testing.assert_allclose(Phi_s.T @ Phi_s, np.eye(n_s), atol=1e-12)
-    for P in Phi_t:
-        np.testing.assert_allclose(P.T @ P, np.eye(P.shape[1]), atol=1e-12)
-    good = _well_resolved(osig[:n_s])
-    assert len(good) >= min(4, n_s)
-    for i in good:
-        assert abs(sigma[i] - osig[i]) <= 1e-10 * osig[0], (i, sigma[i], osig[i])
-        # eigenvector accuracy of the Gram route: eps * sigma_1^2 / (sigma_i^2 gap)
-        tol = max(1e-10, 1e-13 * (osig[0] / osig[i]) ** 2)
-        assert np.linalg.norm(Phi_s[:, i] - oPhi[:, i]) <= tol, (i, np.linalg.norm(Phi_s[:, i] - oPhi[:, i]))
-
-
-def test_pod_c1_end_to_end_solution():
-    """Device bases + device ROM vs oracle bases + oracle ROM, compared on the
-    reconstructed space-time trajectories (basis-independent)."""
-    name = "c1"
-    prob = C.problem(name)
-    Phi_s, Phi_t, sigma, rank = _device_pod(name)
-    oPhi, osig, oV, oPt, _ = C.oracle_bases(name)
-    dr = DeviceRom(prob, Phi_s, Phi_t)
-    mus = W.sample_params(prob, 4, seed=21)
-    (tA, tf, t0), (dA, df, d0) = thetas_device(prob, mus)
-    out = strom.st_solve(dr.desc, dr.rom, dA, df, d0)
-    torch.cuda.synchronize()
-    coeff = out.coeff.cpu().numpy()
-    off = out.coeff_off.cpu().numpy()
-    Ahat, bhat, u0hat = C.oracle_spatial(name)
-    worst = 0.0
-    for q in range(4):
-        M, b = orom.reduced_system(Ahat, tA[q], bhat, tf[q], prob.g, u0hat, t0[q], oPt, prob.dt)
-        ref = orom.reconstruct(oPhi, oPt, orom.solve(M, b))
-        got = orom.reconstruct(Phi_s, Phi_t, coeff[off[q]:off[q + 1]])
-        worst = max(worst, np.linalg.norm(got - ref) / np.linalg.norm(ref))
-    print(f"[c1] end-to-end trajectory rel diff {worst:.3e}")
-    assert worst <= 1e-9
-
-
-def test_temporal_ranks_and_completion_c1():
-    """Every mode of C1 has rank(Y_i) = n_mu = 4 data vectors; the rest is the
-    DCT completion, so the leading 4 temporal vectors match the oracle's."""
-    Phi_s, Phi_t, sigma, rank = _device_pod("c1")
-    oPhi, osig, oV, oPt, oranks = C.oracle_bases("c1")
-    np.testing.assert_array_equal(rank, oranks)
-    good = _well_resolved(osig[:8], floor=1e-3)
-    for i in good:
-        Y = opod.temporal_snapshot(oV, i, 128, 4)
-        sv = np.linalg.svd(Y, compute_uv=False)
-        keep = int(rank[i])
-        for j in range(min(keep, 8)):
-            if sv[j] < 1e-6 * sv[0]:
-                break
-            gap = min(abs(sv[j] - sv[j - 1]) if j else np.inf, abs(sv[j] - sv[j + 1]) if j + 1 < len(sv) else np.inf)
-            if gap < 1e-3 * sv[0]:
-                continue
-            assert np.linalg.norm(Phi_t[i][:, j] - oPt[i][:, j]) <= 1e-7, (i, j)
 
 
 # unit roundoff of the Gram arithmetic: FP32 products/accumulation, or split-BF16
@@ -128,7 +188,7 @@ def test_pod_reduced_precision_gram_reports_error(prec, f32):
     c u (||U||_F / sigma_i)^2 / 2, and the eigenvector angle by ||E|| / gap_i.
     c = 8 allows for the reduction length; the errors are printed for the record."""
     name = "c2_small"
-    Phi_s, Phi_t, sigma, rank = _device_pod(name, prec, f32)
+    Phi_s, Phi_t, sigma, rank, _ = _device_pod(name, prec, f32)
     oPhi, osig, oV, oPt, _ = C.oracle_bases(name)
     U = C.snapshots(name)
     fro2 = float(np.sum(U * U))
