@@ -302,6 +302,26 @@ st_status st_solve(const st_rom_desc* d, const void* rom, int32_t n_q, const dou
                    void* stream);
 
 /* ========================================================================
+ * st_solve_noalloc - st_solve for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same arguments, kernels, outputs and info codes as st_solve,
+ * without ws/ws_bytes: the workspace is a static device array of
+ * ST_NOALLOC_SCRATCH_BYTES inside the library (one per GPU, held until the
+ * process ends).  The caller still passes inputs and outputs.  The batch must
+ * fit with every query at full width n: st_solve_workspace(d, n_q, coeff_cap,
+ * n_q * n * n, lu_prec) <= ST_NOALLOC_SCRATCH_BYTES, else ST_EWORKSPACE is
+ * returned before any launch.  The call allocates nothing (no hipMalloc,
+ * hipFree or allocating library routine).  All calls on one GPU share that
+ * GPU's array: calls that overlap in time on one GPU (different streams or
+ * threads) race on it and must be serialised by the caller.
+ * ====================================================================== */
+#define ST_NOALLOC_SCRATCH_BYTES (64u << 20)
+st_status st_solve_noalloc(const st_rom_desc* d, const void* rom, int32_t n_q, const double* theta_A,
+                           const double* theta_f, const double* theta_0, const int32_t* nt_q, const int32_t* skip,
+                           int32_t lu_prec, double ir_tol, int32_t ir_max, double* coeff, int64_t coeff_cap,
+                           int64_t* coeff_off, double* relres, int32_t* info, int32_t* iters, void* stream);
+
+/* ========================================================================
  * Surrogate network (not part of the paper).  A multilayer perceptron maps a
  * (scaled) parameter vector to standardized reduced space-time coefficients:
  * x (d_in) -> [Linear + GELU] x n_hidden -> Linear -> y (d_out), GELU in its

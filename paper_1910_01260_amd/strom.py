@@ -67,6 +67,8 @@ _SIGNATURES = {
     "st_solve_workspace": (_SZ, [ctypes.POINTER(st_rom_desc), _I32, _I64, _I64, _I32]),
     "st_solve": (_I32, [ctypes.POINTER(st_rom_desc), _P, _I32, _P, _P, _P, _P, _P, _I32, _D, _I32, _P, _I64, _P, _P,
                         _P, _P, _P, _SZ, _P]),
+    "st_solve_noalloc": (_I32, [ctypes.POINTER(st_rom_desc), _P, _I32, _P, _P, _P, _P, _P, _I32, _D, _I32, _P, _I64,
+                                _P, _P, _P, _P, _P]),
     "st_reconstruct": (_I32, [ctypes.POINTER(st_rom_desc), _P, _I64, _P, _I64, _P, _I64, _I32, _P, _P, _P, _P, _I64,
                               _P]),
     "st_graph_enable": (_I32, [_I32]),
@@ -310,6 +312,27 @@ def st_solve(desc: RomDesc, rom: torch.Tensor, theta_A: torch.Tensor, theta_f: O
                           _ptr(skip), lu_prec, float(ir_tol), int(ir_max), _ptr(bufs.coeff), bufs.sum_w, _ptr(bufs.coeff_off),
                           _ptr(bufs.relres), _ptr(bufs.info), _ptr(bufs.iters), _ptr(bufs.ws), bufs.ws_bytes,
                           _stream()), "st_solve")
+    return bufs
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20
+
+
+def st_solve_noalloc(desc: RomDesc, rom: torch.Tensor, theta_A: torch.Tensor, theta_f: Optional[torch.Tensor] = None,
+                     theta_0: Optional[torch.Tensor] = None, nt_q: Optional[torch.Tensor] = None,
+                     lu_prec: int = ST_F64, ir_tol: float = 0.0, ir_max: int = 0, bufs: Optional[SolveBuffers] = None,
+                     widths: Optional[np.ndarray] = None, skip: Optional[torch.Tensor] = None) -> SolveBuffers:
+    """st_solve with the library's static workspace (no workspace argument).
+    Output buffers as st_solve's (bufs.ws is not used)."""
+    n_q = int(theta_A.shape[0])
+    if bufs is None:
+        if widths is None:
+            widths = query_widths(desc, None if nt_q is None else nt_q.cpu().numpy(), n_q)
+        bufs = SolveBuffers(desc, n_q, widths, lu_prec, theta_A.device)
+    _check(lib().st_solve_noalloc(desc.ref(), _ptr(rom), n_q, _ptr(theta_A), _ptr(theta_f), _ptr(theta_0), _ptr(nt_q),
+                                  _ptr(skip), lu_prec, float(ir_tol), int(ir_max), _ptr(bufs.coeff), bufs.sum_w,
+                                  _ptr(bufs.coeff_off), _ptr(bufs.relres), _ptr(bufs.info), _ptr(bufs.iters),
+                                  _stream()), "st_solve_noalloc")
     return bufs
 
 
