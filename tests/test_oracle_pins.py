@@ -359,6 +359,42 @@ def test_error_bounds_hold():
     assert true <= bounds.theorem3_bound(A_st, f_st, u0_st, ust, prob.N_s) * (1 + 1e-12)
 
 
+def test_error_bounds_hand_derived_scalar():
+    """Theorems 1-3 on scalar systems du/dt = -2u (golden values derived by hand
+    in tests/golden/error_bounds_scalar.json).  Theorem 1 is attained when the
+    residuals share a sign, so it is checked for equality with the exact error;
+    each value would move under a wrong product range, a wrong step index, a
+    dropped sqrt(N_t) or a space-time inf-norm grouped by dof instead of step."""
+    with open(os.path.join(GOLDEN, "error_bounds_scalar.json")) as f:
+        g = json.load(f)
+    for key in ("theorem1_uniform", "theorem1_variable"):
+        case = g[key]
+        sy = case["system"]
+        A = np.array([[sy["A"]]])
+        dt = np.array(sy["dt"])
+        F = np.zeros((1, len(dt)))
+        Ua = np.array([case["approx"]])
+        got = bounds.theorem1_bound(A, F, Ua, np.array([sy["u0"]]), dt)
+        np.testing.assert_allclose(got, case["bound"], rtol=1e-14)
+        exact = fom.backward_euler(A, F, np.array([sy["u0"]]), dt)
+        np.testing.assert_allclose(np.abs(exact - Ua)[0], case["true_error"], rtol=1e-14)
+    case = g["theorem2"]
+    sy = case["system"]
+    got = bounds.theorem2_bound(np.array([[sy["A"]]]), np.zeros((1, 2)), np.array([case["approx"]]),
+                                np.array(sy["dt"]))
+    np.testing.assert_allclose(got, case["bound"], rtol=1e-14)
+    case = g["theorem3_scalar"]
+    u0_st = np.array([1.0, 0.0])
+    got = bounds.theorem3_bound(np.array(case["A_st"]), np.zeros(2), u0_st, np.array(case["approx"]), 1)
+    assert abs(got - case["bound"]) <= 1e-14 * case["bound"]
+    assert case["true_error_inf"] <= got
+    case = g["theorem3_two_dofs"]
+    A_st = np.kron(np.array(g["theorem3_scalar"]["A_st"]), np.eye(2))     # time-major stacking
+    u0_st = np.array([1.0, 1.0, 0.0, 0.0])
+    got = bounds.theorem3_bound(A_st, np.zeros(4), u0_st, np.array(case["approx_time_major"]), 2)
+    assert abs(got - case["bound"]) <= 1e-14 * case["bound"]
+
+
 @pytest.mark.parametrize("problem", ["advdiff", "transport"])
 def test_symmetric_part_positive_definite(problem):
     """P12: sym(A) <= 0 gives lambda_min(sym Ahat_st) >= 1 - cos(pi/(N_t+1)) > 0."""
