@@ -39,7 +39,11 @@
  *       k>0 the LU met an exactly zero pivot at step k (1-based); the
  *           query's coefficients are set to NaN
  *       -1  iterative refinement did not reach ir_tol in ir_max steps (the
- *           last iterate is returned)
+ *           last iterate is returned); with an FP32 LU only when the FP64
+ *           re-solve below did not fit in the workspace
+ *       -6  the FP32-LU refinement did not reach ir_tol; the query was
+ *           re-formed and re-solved with an FP64 LU (a valid result: relres
+ *           is the FP64 solution's residual)
  *       -2  not solved: skipped on request (st_solve's skip mask)
  *       -3  the query did not fit in the coefficient or workspace capacity
  *       -4  invalid per-query temporal profile (nt_q out of range)
@@ -278,7 +282,11 @@ st_status st_form(const st_rom_desc* d, const void* rom, int32_t n_q, const doub
  * ||r||_2 <= ir_tol ||b||_2 or ir_max refinement steps were taken.  With
  * ST_F64, ir_max extra refinement steps (usually 0) are taken the same way.
  * The final relative residual ||b - Ahat_st x|| / ||b|| (FP64) is written
- * to relres in both cases.
+ * to relres in both cases.  With ST_F32 and ir_tol > 0, every query still
+ * above ir_tol after ir_max steps is re-formed in FP64 inside the matrix
+ * workspace (its FP32 factors are no longer needed), factored by the FP64 LU
+ * and solved (info = -6); queries whose FP64 system does not fit after the
+ * earlier ones (in query order) keep info = -1.
  *
  * skip     [dev] n_q int32 or NULL: a query with skip[q] != 0 is not solved
  *          (info = -2); it keeps its place in coeff (whatever the caller put
@@ -367,6 +375,33 @@ st_status st_surrogate_check(const st_rom_desc* d, const void* rom, int32_t n_q,
                              const double* theta_f, const double* theta_0, const float* Y, const double* mean,
                              const double* scale, double gamma, double tol, double* coeff, double* cert,
                              int32_t* accept, void* ws, size_t ws_bytes, void* stream);
+
+/* ========================================================================
+ * Residual certificate of reduced coefficients (any source: st_solve, the
+ * surrogate, a caller's iterate), for ragged batches.
+ *
+ * st_coercivity_floor(N_t) = 1 - cos(pi / (N_t + 1)): a lower bound of
+ * lambda_min(sym Ahat_st(mu)) whenever sym(A(mu)) <= 0.  The backward-Euler
+ * space-time matrix (Sec. 2, Eq. (stsystemmat)) then has a symmetric part that
+ * dominates the tridiagonal Toeplitz matrix (1 on the diagonal, -1/2 beside
+ * it) Kronecker I, whose smallest eigenvalue this is, and the Galerkin
+ * projection with orthonormal Phi_st (Sec. 3.2) keeps the bound.
+ *
+ * st_certify: for each query, r = b(mu) - Ahat_st(mu) c in FP64 from the ROM
+ * pieces (the reduced form of the space-time residual, Sec. 5.2, Eq.
+ * (stresidual)); relres[q] = ||r|| / ||b||; cert[q] = e / (1 - e) with
+ * e = ||r|| / (gamma ||c||) (+inf if e >= 1 or c = 0), which bounds
+ * ||c - c*|| / ||c*|| against the exact reduced solution c* when gamma <=
+ * lambda_min(sym Ahat_st(mu)).  gamma = 0 selects st_coercivity_floor(N_t).
+ * coeff [dev] packed as st_solve packs the same queries (nt_q as there).
+ * relres, cert [dev] n_q doubles (NaN / +inf for invalid queries).
+ * ====================================================================== */
+double st_coercivity_floor(int32_t N_t);
+size_t st_certify_workspace(const st_rom_desc* d, int32_t n_q, int64_t coeff_cap);
+st_status st_certify(const st_rom_desc* d, const void* rom, int32_t n_q, const double* theta_A,
+                     const double* theta_f, const double* theta_0, const int32_t* nt_q, const double* coeff,
+                     int64_t coeff_cap, double gamma, double* relres, double* cert, void* ws, size_t ws_bytes,
+                     void* stream);
 
 /* ========================================================================
  * Phase timing (measurement tools).  After st_timing_enable(1), every st_solve

@@ -294,6 +294,9 @@ size_t st_solve_workspace(const st_rom_desc* d, int32_t n_q, int64_t sum_w, int6
   o = align_up(o + sizeof(double) * sum_w);          // b
   o = align_up(o + sizeof(double) * sum_w);          // r
   o = align_up(o + sizeof(int32_t) * sum_w);         // permutations
+  o = align_up(o + sizeof(int64_t) * (n_q + 1));     // FP64 re-solve: matrix offsets
+  o = align_up(o + sizeof(int32_t) * n_q);           //                info
+  o = align_up(o + sizeof(int32_t) * 4);             //                counters
   o = align_up(o + el * (size_t)sum_w2);             // matrices
   return o;
 }
@@ -325,6 +328,7 @@ struct SolveArgs {
 // Workspace sections of st_solve.
 struct SolveWs {
   Plan plan;
+  Plan fb;  // FP64 re-solve of unconverged queries (shares width, order, coeff_off)
   int32_t* active;
   double *bnorm, *rnorm, *b, *r;
   int32_t* perm;
@@ -345,9 +349,16 @@ SolveWs solve_ws(const SolveArgs& a) {
   w.b = c.take<double>(a.coeff_cap);
   w.r = c.take<double>(a.coeff_cap);
   w.perm = c.take<int32_t>(a.coeff_cap);
+  w.fb = w.plan;
+  w.fb.mat_off = c.take<int64_t>(a.n_q + 1);
+  w.fb.info = c.take<int32_t>(a.n_q);
+  w.fb.counter = c.take<int32_t>(4);
   w.mats = c.base + c.used;
   w.plan.coeff_off = a.coeff_off;
   w.plan.info = a.info;
+  w.fb.width = w.plan.width;
+  w.fb.order = w.plan.order;
+  w.fb.coeff_off = a.coeff_off;
   (void)el;
   return w;
 }
@@ -407,6 +418,22 @@ hipError_t solve_launches(const SolveArgs& a, hipStream_t s) {
   SL_TRY(launch_residual(rv, n_q, a.thA, a.nt_q, plan, w.b, a.coeff, w.r, w.rnorm, w.active, n_max, s));
   const int flag = (a.lu_prec == ST_F32 || a.ir_max > 0) ? 2 : 1;
   SL_TRY(launch_ir_check(n_q, plan, w.rnorm, w.bnorm, a.ir_tol, a.ir_max, flag, w.active, a.relres, a.iters, s));
+  if (a.lu_prec == ST_F32 && a.ir_tol > 0.0) {
+    // queries whose refinement did not converge (info -1): re-form their systems in
+    // FP64 in the matrix space (the FP32 factors are no longer needed), factor, solve,
+    // and record the FP64 residual (info -6)
+    const Plan fb = w.fb;
+    const int v64 = lu_choice(ST_F64, n_max);
+    const int nbo64 = lu_outer_block(ST_F64, n_max, v64);
+    const int64_t cap64 = solve_mats_cap(a) * (int64_t)sizeof(float) / (int64_t)sizeof(double);
+    SL_TRY(launch_fallback_plan(n_q, plan, fb, w.active, cap64, s));
+    SL_TRY(launch_form(rv, n_q, a.thA, a.thf, a.th0, a.nt_q, fb, ST_F64, w.mats, w.b, n_max, s));
+    SL_TRY(launch_lu(n_q, fb, ST_F64, w.mats, w.perm, n_max, v64, s));
+    SL_TRY(launch_lu_solve(n_q, fb, ST_F64, w.mats, w.perm, w.b, a.coeff, 0, w.active, n_max, nbo64, s));
+    SL_TRY(launch_residual(rv, n_q, a.thA, a.nt_q, fb, w.b, a.coeff, w.r, w.rnorm, w.active, n_max, s));
+    SL_TRY(launch_ir_check(n_q, fb, w.rnorm, w.bnorm, a.ir_tol, a.ir_max, 1, w.active, a.relres, a.iters, s));
+    SL_TRY(launch_fallback_finish(n_q, plan, fb, w.active, s));
+  }
   SL_TRY(launch_finalize(n_q, plan, a.coeff, a.info, s));
   SL_TRY(mark(7, s));
 #undef SL_TRY
@@ -438,6 +465,7 @@ std::vector<uint64_t> graph_key(const SolveArgs& a, int device) {
   ptr(a.coeff); put((uint64_t)a.coeff_cap); ptr(a.coeff_off); ptr(a.relres); ptr(a.info); ptr(a.iters); ptr(a.ws);
   put((uint64_t)a.ws_bytes);
   put((uint64_t)lu_choice(a.lu_prec, (int32_t)total_nt(a.d)));
+  put((uint64_t)lu_choice(ST_F64, (int32_t)total_nt(a.d)));
   return k;
 }
 
@@ -952,7 +980,63 @@ st_status st_surrogate_check(const st_rom_desc* d, const void* rom, int32_t n_q,
   ST_TRY(launch_rhs(rv, n_q, theta_f, theta_0, nullptr, plan, b, (int32_t)n, s));
   ST_TRY(launch_residual(rv, n_q, theta_A, nullptr, plan, b, coeff, r, rnorm, nullptr, (int32_t)n, s));
   ST_TRY(launch_vec_norms(n_q, plan, coeff, cnorm, s));
-  ST_TRY(launch_certificate(n_q, plan, rnorm, cnorm, gamma, tol, cert, accept, s));
+  ST_TRY(launch_certificate(n_q, plan, rnorm, cnorm, gamma, tol, cert, accept, nullptr, nullptr, s));
+  return ST_OK;
+}
+
+double st_coercivity_floor(int32_t N_t) {
+  if (N_t < 1) return 0.0;
+  return 1.0 - cos(M_PI / (N_t + 1.0));
+}
+
+size_t st_certify_workspace(const st_rom_desc* d, int32_t n_q, int64_t coeff_cap) {
+  if (!desc_ok(d) || n_q < 0 || coeff_cap < 0) return 0;
+  size_t o = plan_bytes(n_q);
+  o = align_up(o + sizeof(int64_t) * (n_q + 1));  // coeff offsets
+  o = align_up(o + sizeof(int64_t) * (n_q + 1));  // matrix offsets (unused)
+  o = align_up(o + sizeof(int32_t) * n_q);        // info
+  o = align_up(o + sizeof(double) * n_q);         // ||r||
+  o = align_up(o + sizeof(double) * n_q);         // ||c||
+  o = align_up(o + sizeof(double) * n_q);         // ||b||
+  o = align_up(o + sizeof(double) * coeff_cap);   // b
+  o = align_up(o + sizeof(double) * coeff_cap);   // r
+  return o;
+}
+
+st_status st_certify(const st_rom_desc* d, const void* rom, int32_t n_q, const double* theta_A, const double* theta_f,
+                     const double* theta_0, const int32_t* nt_q, const double* coeff, int64_t coeff_cap, double gamma,
+                     double* relres, double* cert, void* ws, size_t ws_bytes, void* stream) {
+  if (!query_args_ok(d, rom, n_q, theta_A, theta_f, theta_0)) return ST_EINVAL;
+  if (!(gamma >= 0.0) || coeff_cap < 0) return ST_EINVAL;
+  if (d->n_s > kMaxFormModes) return ST_EUNSUPPORTED;
+  if (n_q == 0) return ST_OK;
+  if (!coeff || !relres || !cert || !ws) return ST_EINVAL;
+  const int64_t n = total_nt(d);
+  if (n > kMaxWidth) return ST_EUNSUPPORTED;
+  if (ws_bytes < st_certify_workspace(d, n_q, coeff_cap)) return ST_EWORKSPACE;
+  if (gamma == 0.0) gamma = st_coercivity_floor(d->N_t);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  RomView rv = view_of(d, rom);
+  Carver c(ws);
+  Plan plan;
+  plan.width = c.take<int32_t>(n_q);
+  plan.order = c.take<int32_t>(n_q);
+  plan.counter = c.take<int32_t>(4);
+  plan.coeff_off = c.take<int64_t>(n_q + 1);
+  plan.mat_off = c.take<int64_t>(n_q + 1);
+  plan.info = c.take<int32_t>(n_q);
+  double* rnorm = c.take<double>(n_q);
+  double* cnorm = c.take<double>(n_q);
+  double* bnorm = c.take<double>(n_q);
+  double* b = c.take<double>(coeff_cap);
+  double* r = c.take<double>(coeff_cap);
+  ST_TRY(launch_plan(n_q, d->n_s, rv.moff, nt_q, nullptr, theta_A, theta_f, theta_0, d->Q, d->Qf, d->Q0, coeff_cap,
+                     (int64_t)1 << 62, plan, s));
+  ST_TRY(launch_rhs(rv, n_q, theta_f, theta_0, nt_q, plan, b, (int32_t)n, s));
+  ST_TRY(launch_residual(rv, n_q, theta_A, nt_q, plan, b, coeff, r, rnorm, nullptr, (int32_t)n, s));
+  ST_TRY(launch_vec_norms(n_q, plan, coeff, cnorm, s));
+  ST_TRY(launch_vec_norms(n_q, plan, b, bnorm, s));
+  ST_TRY(launch_certificate(n_q, plan, rnorm, cnorm, gamma, 0.0, cert, nullptr, bnorm, relres, s));
   return ST_OK;
 }
 

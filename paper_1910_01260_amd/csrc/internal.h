@@ -113,7 +113,7 @@ hipError_t launch_rhs(const RomView& rom, int32_t n_q, const double* thf, const 
 hipError_t launch_destandardize(int32_t n_q, int32_t n, const float* Y, const double* mean, const double* scale,
                                 Plan plan, double* coeff, hipStream_t s);
 hipError_t launch_certificate(int32_t n_q, Plan plan, const double* rnorm, const double* cnorm, double gamma, double tol,
-                              double* cert, int32_t* accept, hipStream_t s);
+                              double* cert, int32_t* accept, const double* bnorm, double* relres, hipStream_t s);
 hipError_t launch_form(const RomView& rom, int32_t n_q, const double* thA, const double* thf, const double* th0,
                        const int32_t* nt_q, Plan plan, int32_t out_prec, void* mats, double* rhs, int32_t n_max,
                        hipStream_t s);
@@ -144,6 +144,9 @@ hipError_t launch_ir_check(int32_t n_q, Plan plan, const double* rnorm, const do
 hipError_t launch_vec_norms(int32_t n_q, Plan plan, const double* v, double* norms, hipStream_t s);
 hipError_t launch_finalize(int32_t n_q, Plan plan, double* coeff, int32_t* info_out, hipStream_t s);
 hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
+// FP64 re-solve of queries whose FP32 refinement did not converge (info -1 -> -6)
+hipError_t launch_fallback_plan(int32_t n_q, Plan plan, Plan fb, int32_t* active, int64_t mat_cap, hipStream_t s);
+hipError_t launch_fallback_finish(int32_t n_q, Plan plan, Plan fb, const int32_t* active, hipStream_t s);
 
 // k_mlp.hip: surrogate network
 int mlp_layers(const st_mlp_shape& s);

@@ -388,6 +388,54 @@ __global__ void ir_check_kernel(int32_t n_q, Plan plan, const double* __restrict
   }
 }
 
+// FP64 re-solve plan of the queries whose FP32-LU refinement did not converge
+// (plan.info == -1).  One workgroup.  fb shares width, order and coeff_off with
+// plan; fb.info is 0 for a query to re-solve and -2 (skip) otherwise, also when
+// its FP64 system does not fit in mat_cap elements after the earlier ones;
+// fb.mat_off packs the FP64 systems in query order; active marks the queries
+// re-solved.
+__global__ __launch_bounds__(kPlanThreads) void fallback_plan_kernel(int32_t n_q, Plan plan, Plan fb,
+                                                                     int32_t* __restrict__ active, int64_t mat_cap) {
+  __shared__ int64_t s_w2[kPlanThreads];
+  const int tid = threadIdx.x;
+  const int per = (n_q + kPlanThreads - 1) / kPlanThreads;
+  const int qb = min(n_q, tid * per), qe = min(n_q, qb + per);
+  int64_t sw2 = 0;
+  for (int q = qb; q < qe; ++q)
+    if (plan.info[q] == -1) sw2 += (int64_t)plan.width[q] * plan.width[q];
+  s_w2[tid] = sw2;
+  __syncthreads();
+  for (int off = 1; off < kPlanThreads; off <<= 1) {
+    const int64_t a = tid >= off ? s_w2[tid - off] : 0;
+    __syncthreads();
+    s_w2[tid] += a;
+    __syncthreads();
+  }
+  int64_t cw2 = s_w2[tid] - sw2;
+  for (int q = qb; q < qe; ++q) {
+    int32_t code = -2;
+    fb.mat_off[q] = cw2;
+    if (plan.info[q] == -1) {
+      cw2 += (int64_t)plan.width[q] * plan.width[q];
+      code = cw2 <= mat_cap ? 0 : -2;
+    }
+    fb.info[q] = code;
+    active[q] = code == 0;
+  }
+  if (tid == kPlanThreads - 1) fb.mat_off[n_q] = s_w2[tid];
+  if (tid < 4) fb.counter[tid] = 0;
+}
+
+// After the FP64 re-solve: queries re-solved get info -6 (or the FP64 LU's zero
+// pivot); those that did not fit keep -1 and their FP32 iterate and residual.
+__global__ void fallback_finish_kernel(int32_t n_q, Plan plan, Plan fb, const int32_t* __restrict__ active) {
+  const int32_t q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= n_q || plan.info[q] != -1 || !active[q]) return;
+  const int32_t c = fb.info[q];
+  if (c == 0) plan.info[q] = -6;
+  else if (c > 0) plan.info[q] = c;
+}
+
 __global__ void finalize_kernel(int32_t n_q, Plan plan, double* __restrict__ coeff) {
   const int32_t q = blockIdx.y;
   if (plan.info[q] <= 0) return;
@@ -414,6 +462,29 @@ __global__ __launch_bounds__(256) void rhs_kernel(RomView rom, int32_t n_q, cons
   rhs[plan.coeff_off[q] + a] = fma(rom.P1[a], u0, b);
 }
 
+// right-hand side of queries with per-mode prefixes: one workgroup per (mode,
+// query); mode i's local block starts at the sum of the query's earlier prefixes
+__global__ __launch_bounds__(256) void rhs_prefix_kernel(RomView rom, int32_t n_q, const double* __restrict__ thf,
+                                                         const double* __restrict__ th0,
+                                                         const int32_t* __restrict__ nt_q, Plan plan,
+                                                         double* __restrict__ rhs) {
+  const int32_t i = blockIdx.x, q = blockIdx.y;
+  if (plan.info[q] != 0) return;
+  const int32_t* ntq = nt_q + (int64_t)q * rom.n_s;
+  int64_t loff = 0;
+  for (int l = 0; l < i; ++l) loff += ntq[l];
+  double u0 = 0.0;
+  for (int k = 0; k < rom.Q0; ++k) u0 = fma(th0[(int64_t)q * rom.Q0 + k], rom.u0hat[(int64_t)k * rom.n_s + i], u0);
+  const int32_t a0 = rom.moff[i];
+  for (int j = threadIdx.x; j < ntq[i]; j += 256) {
+    const int a = a0 + j;
+    double b = 0.0;
+    for (int k = 0; k < rom.Qf; ++k)
+      b = fma(thf[(int64_t)q * rom.Qf + k] * rom.Wf[(int64_t)k * rom.n + a], rom.bhat[(int64_t)k * rom.n_s + i], b);
+    rhs[plan.coeff_off[q] + loff + j] = fma(rom.P1[a], u0, b);
+  }
+}
+
 // coeff[coeff_off[q] + a] = mean[a] + scale[a] * Y[q * n + a] for valid queries
 __global__ void destandardize_kernel(int64_t total, int32_t n, const float* __restrict__ Y,
                                      const double* __restrict__ mean, const double* __restrict__ scale, Plan plan,
@@ -428,7 +499,8 @@ __global__ void destandardize_kernel(int64_t total, int32_t n, const float* __re
 
 __global__ void certificate_kernel(int32_t n_q, Plan plan, const double* __restrict__ rnorm,
                                    const double* __restrict__ cnorm, double gamma, double tol, double* __restrict__ cert,
-                                   int32_t* __restrict__ accept) {
+                                   int32_t* __restrict__ accept, const double* __restrict__ bnorm,
+                                   double* __restrict__ relres) {
   const int32_t q = blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= n_q) return;
   double c = __longlong_as_double(0x7ff0000000000000LL);  // +inf
@@ -437,7 +509,10 @@ __global__ void certificate_kernel(int32_t n_q, Plan plan, const double* __restr
     if (e < 1.0) c = e / (1.0 - e);
   }
   cert[q] = c;
-  accept[q] = (c <= tol) ? 1 : 0;
+  if (accept) accept[q] = (c <= tol) ? 1 : 0;
+  if (relres)
+    relres[q] = plan.info[q] != 0 ? __longlong_as_double(0x7ff8000000000000LL)
+                                   : (bnorm[q] > 0.0 ? rnorm[q] / bnorm[q] : rnorm[q]);
 }
 
 __global__ void fill_i32_kernel(int32_t* p, int64_t n, int32_t v) {
@@ -556,9 +631,11 @@ hipError_t launch_plan(int32_t n_q, int32_t n_s, const int32_t* moff, const int3
 
 hipError_t launch_rhs(const RomView& rom, int32_t n_q, const double* thf, const double* th0, const int32_t* nt_q,
                       Plan plan, double* rhs, int32_t n_max, hipStream_t s) {
-  if (nt_q) return hipErrorInvalidValue;  // full-width queries only
   if (n_q == 0 || n_max == 0) return hipSuccess;
-  hipLaunchKernelGGL(rhs_kernel, dim3((n_max + 255) / 256, n_q), dim3(256), 0, s, rom, n_q, thf, th0, plan, rhs);
+  if (nt_q)
+    hipLaunchKernelGGL(rhs_prefix_kernel, dim3(rom.n_s, n_q), dim3(256), 0, s, rom, n_q, thf, th0, nt_q, plan, rhs);
+  else
+    hipLaunchKernelGGL(rhs_kernel, dim3((n_max + 255) / 256, n_q), dim3(256), 0, s, rom, n_q, thf, th0, plan, rhs);
   return hipGetLastError();
 }
 
@@ -572,10 +649,10 @@ hipError_t launch_destandardize(int32_t n_q, int32_t n, const float* Y, const do
 }
 
 hipError_t launch_certificate(int32_t n_q, Plan plan, const double* rnorm, const double* cnorm, double gamma, double tol,
-                              double* cert, int32_t* accept, hipStream_t s) {
+                              double* cert, int32_t* accept, const double* bnorm, double* relres, hipStream_t s) {
   if (n_q == 0) return hipSuccess;
   hipLaunchKernelGGL(certificate_kernel, dim3((n_q + 255) / 256), dim3(256), 0, s, n_q, plan, rnorm, cnorm, gamma, tol,
-                     cert, accept);
+                     cert, accept, bnorm, relres);
   return hipGetLastError();
 }
 
@@ -652,6 +729,18 @@ hipError_t launch_finalize(int32_t n_q, Plan plan, double* coeff, int32_t* info_
   (void)info_out;
   if (n_q == 0) return hipSuccess;
   hipLaunchKernelGGL(finalize_kernel, dim3(4, n_q), dim3(256), 0, s, n_q, plan, coeff);
+  return hipGetLastError();
+}
+
+hipError_t launch_fallback_plan(int32_t n_q, Plan plan, Plan fb, int32_t* active, int64_t mat_cap, hipStream_t s) {
+  if (n_q == 0) return hipSuccess;
+  hipLaunchKernelGGL(fallback_plan_kernel, dim3(1), dim3(kPlanThreads), 0, s, n_q, plan, fb, active, mat_cap);
+  return hipGetLastError();
+}
+
+hipError_t launch_fallback_finish(int32_t n_q, Plan plan, Plan fb, const int32_t* active, hipStream_t s) {
+  if (n_q == 0) return hipSuccess;
+  hipLaunchKernelGGL(fallback_finish_kernel, dim3((n_q + 255) / 256), dim3(256), 0, s, n_q, plan, fb, active);
   return hipGetLastError();
 }
 

@@ -87,6 +87,9 @@ _SIGNATURES = {
     "st_surrogate_check_workspace": (_SZ, [ctypes.POINTER(st_rom_desc), _I32]),
     "st_surrogate_check": (_I32, [ctypes.POINTER(st_rom_desc), _P, _I32, _P, _P, _P, _P, _P, _P, _D, _D, _P, _P, _P,
                                   _P, _SZ, _P]),
+    "st_coercivity_floor": (_D, [_I32]),
+    "st_certify_workspace": (_SZ, [ctypes.POINTER(st_rom_desc), _I32, _I64]),
+    "st_certify": (_I32, [ctypes.POINTER(st_rom_desc), _P, _I32, _P, _P, _P, _P, _P, _I64, _D, _P, _P, _P, _SZ, _P]),
     "st_timing_enable": (_I32, [_I32]),
     "st_timing_read": (_I32, [ctypes.POINTER(ctypes.c_double), _I32]),
 }
@@ -463,3 +466,25 @@ def st_surrogate_check(desc: RomDesc, rom: torch.Tensor, theta_A: torch.Tensor, 
     _check(lib().st_surrogate_check(desc.ref(), _ptr(rom), n_q, _ptr(theta_A), _ptr(theta_f), _ptr(theta_0), _ptr(Y),
                                     _ptr(mean), _ptr(scale), float(gamma), float(tol), _ptr(coeff), _ptr(cert),
                                     _ptr(accept), _ptr(ws), nb, _stream()), "st_surrogate_check")
+
+
+def st_coercivity_floor(N_t: int) -> float:
+    return float(lib().st_coercivity_floor(int(N_t)))
+
+
+def st_certify(desc: RomDesc, rom: torch.Tensor, theta_A: torch.Tensor, theta_f: Optional[torch.Tensor],
+               theta_0: Optional[torch.Tensor], coeff: torch.Tensor, nt_q: Optional[torch.Tensor] = None,
+               gamma: float = 0.0, coeff_cap: Optional[int] = None):
+    """Per-query FP64 residual and relative-error certificate of packed
+    coefficients.  Returns (relres, cert) device tensors of n_q entries."""
+    n_q = int(theta_A.shape[0])
+    dev = theta_A.device
+    cap = int(coeff.numel()) if coeff_cap is None else int(coeff_cap)
+    relres = torch.empty(max(n_q, 1), dtype=torch.float64, device=dev)
+    cert = torch.empty(max(n_q, 1), dtype=torch.float64, device=dev)
+    ws_bytes = lib().st_certify_workspace(desc.ref(), n_q, cap)
+    ws = torch.empty(max(ws_bytes, 1), dtype=torch.uint8, device=dev)
+    _check(lib().st_certify(desc.ref(), _ptr(rom), n_q, _ptr(theta_A), _ptr(theta_f), _ptr(theta_0), _ptr(nt_q),
+                            _ptr(coeff), cap, float(gamma), _ptr(relres), _ptr(cert), _ptr(ws), ws_bytes, _stream()),
+           "st_certify")
+    return relres[:n_q], cert[:n_q]

@@ -271,3 +271,100 @@ def test_exactly_singular_query_reports_pivot():
     coeff = out.coeff.cpu().numpy()
     assert info[0] == 1 and np.isnan(coeff[0])
     assert info[1] == 0 and abs(coeff[1] - 1.0 / (1.0 - 0.5)) < 1e-15
+
+
+def test_unconverged_refinement_falls_back_to_fp64(cb_rom):
+    """FP32 LU with no refinement steps and a tolerance the FP32 solve cannot meet:
+    every query ends unconverged and is re-formed and re-solved with the FP64 LU
+    (info -6); the results then meet the FP64 parity bar."""
+    prob = C.problem("cb")
+    nt = W.ragged_profiles(12, 40, seed=41)
+    mus = W.sample_params(prob, 12, seed=42)
+    (tA, tf, t0), (dA, df, d0) = thetas_device(prob, mus)
+    print("[cb] st_solve FP32, ir_max=0, ir_tol=1e-14 (forced FP64 re-solve)", flush=True)
+    # a workspace sized for FP64 systems holds every re-solve
+    bufs = strom.SolveBuffers(cb_rom.desc, 12, nt.sum(axis=1), strom.ST_F64)
+    b = strom.st_solve(cb_rom.desc, cb_rom.rom, dA, df, d0, torch.tensor(nt, device="cuda"), lu_prec=strom.ST_F32,
+                       ir_tol=1e-14, ir_max=0, bufs=bufs)
+    torch.cuda.synchronize()
+    info = b.info.cpu().numpy()[:12]
+    relres = b.relres.cpu().numpy()[:12]
+    coeff, off = b.coeff.cpu().numpy(), b.coeff_off.cpu().numpy()
+    assert (info == -6).all(), info
+    assert relres.max() <= 1e-12, relres
+    for q in range(12):
+        M, rhs = C.oracle_system("cb", tA[q], tf[q], t0[q], nt[q])
+        assert _rel(coeff[off[q]:off[q + 1]], orom.solve(M, rhs)) <= RTOL
+
+
+def test_fp64_resolve_that_does_not_fit_keeps_minus_one(cb_rom):
+    """A workspace sized for the FP32 systems only holds FP64 copies of about half
+    of them: the first unconverged queries (in query order) are re-solved in FP64
+    (info -6, FP64 accuracy), the rest keep info -1 and the FP32 iterate."""
+    prob = C.problem("cb")
+    n_q = 6
+    nt = np.full((n_q, 40), 32, dtype=np.int32)
+    mus = W.sample_params(prob, n_q, seed=44)
+    (tA, tf, t0), (dA, df, d0) = thetas_device(prob, mus)
+    print("[cb] st_solve FP32 with an FP32-sized workspace, forced FP64 re-solve", flush=True)
+    b = strom.st_solve(cb_rom.desc, cb_rom.rom, dA, df, d0, torch.tensor(nt, device="cuda"), lu_prec=strom.ST_F32,
+                       ir_tol=1e-14, ir_max=0)
+    torch.cuda.synchronize()
+    info = b.info.cpu().numpy()[:n_q]
+    relres = b.relres.cpu().numpy()[:n_q]
+    coeff, off = b.coeff.cpu().numpy(), b.coeff_off.cpu().numpy()
+    k = int(np.sum(info == -6))
+    assert 1 <= k < n_q and (info[:k] == -6).all() and (info[k:] == -1).all(), info
+    for q in range(n_q):
+        M, rhs = C.oracle_system("cb", tA[q], tf[q], t0[q], nt[q])
+        err = _rel(coeff[off[q]:off[q + 1]], orom.solve(M, rhs))
+        if q < k:
+            assert err <= RTOL and relres[q] <= 1e-12
+        else:
+            assert relres[q] > 1e-14 and err <= 1e-3     # the FP32 solve, unrefined
+
+
+def test_certify_ragged_matches_oracle_certificate(cb_rom):
+    """st_certify on perturbed solutions of ragged queries: relative residual and
+    certificate equal the oracle's (bounds.certificate), and the certificate bounds
+    the true relative error."""
+    from oracle import bounds
+    prob = C.problem("cb")
+    n_q = 10
+    nt = W.ragged_profiles(n_q, 40, seed=45)
+    mus = W.sample_params(prob, n_q, seed=46)
+    (tA, tf, t0), (dA, df, d0) = thetas_device(prob, mus)
+    widths = nt.sum(axis=1)
+    off = np.concatenate([[0], np.cumsum(widths)])
+    rng = np.random.default_rng(47)
+    gamma = bounds.coercivity_floor(prob.N_t)
+    assert abs(strom.st_coercivity_floor(prob.N_t) - gamma) <= 1e-16
+    packed, exact, systems = [], [], []
+    for q in range(n_q):
+        M, rhs = C.oracle_system("cb", tA[q], tf[q], t0[q], nt[q])
+        c = orom.solve(M, rhs)
+        pert = 10.0 ** rng.uniform(-10, -4)
+        packed.append(c + pert * np.linalg.norm(c) * rng.standard_normal(len(c)) / np.sqrt(len(c)))
+        exact.append(c)
+        systems.append((M, rhs))
+    coeff = torch.tensor(np.concatenate(packed), device="cuda")
+    print(f"[cb] st_certify n_q={n_q}", flush=True)
+    relres, cert = strom.st_certify(cb_rom.desc, cb_rom.rom, dA, df, d0, coeff, torch.tensor(nt, device="cuda"))
+    torch.cuda.synchronize()
+    relres, cert = relres.cpu().numpy(), cert.cpu().numpy()
+    for q in range(n_q):
+        M, rhs = systems[q]
+        x = packed[q]
+        ref_rel = np.linalg.norm(rhs - M @ x) / np.linalg.norm(rhs)
+        ref_cert = bounds.certificate(M, rhs, x, gamma)
+        assert abs(relres[q] - ref_rel) <= 1e-8 * ref_rel + 1e-13 * (1 + np.linalg.norm(M) * np.linalg.norm(x)
+                                                                     / np.linalg.norm(rhs)), (q, relres[q], ref_rel)
+        # the residual of a near-solution is a cancellation: both sides round it to
+        # ~eps (||b|| + ||M|| ||x||) absolutely, which the certificate divides by gamma ||x||
+        slack = 1e-13 * (np.linalg.norm(rhs) + np.linalg.norm(M) * np.linalg.norm(x)) / (gamma * np.linalg.norm(x))
+        if np.isinf(ref_cert):
+            assert np.isinf(cert[q]) or cert[q] >= 1.0 / slack, (q, cert[q])
+        else:
+            assert abs(cert[q] - ref_cert) <= 1e-8 * ref_cert + slack * (1 + ref_cert) ** 2, (q, cert[q], ref_cert)
+        assert _rel(x, exact[q]) <= cert[q]
+    assert np.isfinite(cert).sum() >= n_q // 2
