@@ -404,6 +404,34 @@ st_status st_certify(const st_rom_desc* d, const void* rom, int32_t n_q, const d
                      void* stream);
 
 /* ========================================================================
+ * st_fom_bound - certified full-order error bound of space-time ROM solutions
+ * (Sec. 5.2, Theorem (res-basedErrorBoundforSpaceTime)):
+ *   ||u_st - u~_st||_inf <= sqrt(N_t) ||A_st^{-1}||_2 ||r_st(u~_st)||_inf,
+ * u~_st = Phi_st c the reconstructed space-time state of each query,
+ * r_st = A_st u~_st - f_st - u0_st its full-order space-time residual
+ * (Eq. (stresidual)), ||.||_inf = max over time steps of the 2-norm
+ * (Eq. (spacetimeinfnorm)).  The residual is evaluated exactly in FP64 on
+ * the full N_s x N_t grid (never stored): r^(k) = Phi_s (y_k - y_{k-1})
+ * - dt_k A(mu) Phi_s y_k - dt_k B f^(k)(mu) (- u0(mu) at the first step),
+ * y_k = the query's temporal coefficients at step k.
+ *
+ * Inputs as st_assemble (N_s, Phi_s, the CSR terms A, Bf, g, u0) plus the
+ * ROM buffer (temporal bases, steps) and the packed coefficients of n_q
+ * queries (nt_q, coeff, coeff_cap as st_solve).
+ * inv_norm  an upper bound of ||A_st(mu)^{-1}||_2 for every query, or 0 for
+ *           1 / st_coercivity_floor(N_t), valid whenever sym(A(mu)) <= 0.
+ * Outputs [dev] n_q doubles each: res_inf = ||r_st||_inf, u_inf =
+ * ||u~_st||_inf, bound = sqrt(N_t) inv_norm res_inf (NaN for invalid queries).
+ * Limits: n_s <= 128 and (33 n_s + 32 (n_s (Q+1) + Qf + Q0)) 8 bytes <= 160 KB.
+ * ====================================================================== */
+size_t st_fom_bound_workspace(const st_rom_desc* d, int64_t N_s, int32_t n_q);
+st_status st_fom_bound(const st_rom_desc* d, const void* rom, int64_t N_s, const double* Phi_s, const st_csr* A,
+                       const double* Bf, const double* g, const double* u0, int32_t n_q, const double* theta_A,
+                       const double* theta_f, const double* theta_0, const int32_t* nt_q, const double* coeff,
+                       int64_t coeff_cap, double inv_norm, double* res_inf, double* u_inf, double* bound, void* ws,
+                       size_t ws_bytes, void* stream);
+
+/* ========================================================================
  * Phase timing (measurement tools).  After st_timing_enable(1), every st_solve
  * records HIP events on its stream at its phase boundaries; after the caller
  * has synchronised that stream, st_timing_read fills ms[p] with the elapsed

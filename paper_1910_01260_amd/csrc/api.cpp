@@ -1003,6 +1003,62 @@ size_t st_certify_workspace(const st_rom_desc* d, int32_t n_q, int64_t coeff_cap
   return o;
 }
 
+namespace {
+int32_t dict_cols(const st_rom_desc* d) { return d->n_s * (d->Q + 1) + d->Qf + d->Q0; }
+}  // namespace
+
+size_t st_fom_bound_workspace(const st_rom_desc* d, int64_t N_s, int32_t n_q) {
+  if (!desc_ok(d) || N_s < 1 || n_q < 0) return 0;
+  size_t o = plan_bytes(n_q);
+  o = align_up(o + sizeof(int64_t) * (n_q + 1));                 // coeff offsets
+  o = align_up(o + sizeof(int64_t) * (n_q + 1));                 // matrix offsets (unused)
+  o = align_up(o + sizeof(int32_t) * n_q);                       // info
+  o = align_up(o + sizeof(double) * (size_t)N_s * dict_cols(d));  // dictionary D
+  return o;
+}
+
+st_status st_fom_bound(const st_rom_desc* d, const void* rom, int64_t N_s, const double* Phi_s, const st_csr* A,
+                       const double* Bf, const double* g, const double* u0, int32_t n_q, const double* theta_A,
+                       const double* theta_f, const double* theta_0, const int32_t* nt_q, const double* coeff,
+                       int64_t coeff_cap, double inv_norm, double* res_inf, double* u_inf, double* bound, void* ws,
+                       size_t ws_bytes, void* stream) {
+  if (!query_args_ok(d, rom, n_q, theta_A, theta_f, theta_0)) return ST_EINVAL;
+  if (N_s < 1 || N_s > 0x7fffffff || !Phi_s || !A || coeff_cap < 0 || !(inv_norm >= 0.0)) return ST_EINVAL;
+  if (d->n_s > N_s) return ST_ERANK;
+  if (d->Qf > 0 && !Bf) return ST_EINVAL;
+  if (d->Q0 > 0 && !u0) return ST_EINVAL;
+  for (int q = 0; q < d->Q; ++q) {
+    if (A[q].n_rows != N_s || A[q].nnz < 0 || !A[q].row_ptr) return ST_EINVAL;
+    if (A[q].nnz > 0 && (!A[q].col_idx || !A[q].val)) return ST_EINVAL;
+  }
+  if (d->n_s > kMaxFormModes) return ST_EUNSUPPORTED;
+  if (fom_bound_lds_bytes(d->n_s, dict_cols(d)) > 160 * 1024) return ST_EUNSUPPORTED;
+  if (n_q == 0) return ST_OK;
+  if (!coeff || !res_inf || !u_inf || !bound || !ws) return ST_EINVAL;
+  const int64_t n = total_nt(d);
+  if (n > kMaxWidth) return ST_EUNSUPPORTED;
+  if (ws_bytes < st_fom_bound_workspace(d, N_s, n_q)) return ST_EWORKSPACE;
+  if (inv_norm == 0.0) inv_norm = 1.0 / st_coercivity_floor(d->N_t);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  RomView rv = view_of(d, rom);
+  Carver c(ws);
+  Plan plan;
+  plan.width = c.take<int32_t>(n_q);
+  plan.order = c.take<int32_t>(n_q);
+  plan.counter = c.take<int32_t>(4);
+  plan.coeff_off = c.take<int64_t>(n_q + 1);
+  plan.mat_off = c.take<int64_t>(n_q + 1);
+  plan.info = c.take<int32_t>(n_q);
+  const int32_t m_D = dict_cols(d);
+  double* D = c.take<double>((size_t)N_s * m_D);
+  ST_TRY(launch_plan(n_q, d->n_s, rv.moff, nt_q, nullptr, theta_A, theta_f, theta_0, d->Q, d->Qf, d->Q0, coeff_cap,
+                     (int64_t)1 << 62, plan, s));
+  ST_TRY(launch_fom_dict(N_s, d->n_s, d->Q, A, d->Qf, d->Q0, Phi_s, Bf, u0, D, m_D, s));
+  ST_TRY(launch_fom_residual(rv, N_s, D, m_D, n_q, theta_A, theta_f, theta_0, g, nt_q, plan, coeff, inv_norm, res_inf,
+                             u_inf, bound, s));
+  return ST_OK;
+}
+
 st_status st_certify(const st_rom_desc* d, const void* rom, int32_t n_q, const double* theta_A, const double* theta_f,
                      const double* theta_0, const int32_t* nt_q, const double* coeff, int64_t coeff_cap, double gamma,
                      double* relres, double* cert, void* ws, size_t ws_bytes, void* stream) {

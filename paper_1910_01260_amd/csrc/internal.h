@@ -127,6 +127,16 @@ int lu_outer_block(int32_t prec, int32_t n_max, int variant);
 hipError_t launch_lu(int32_t n_q, Plan plan, int32_t prec, void* mats, int32_t* piv, int32_t n_max, int variant,
                      hipStream_t s);
 
+// k_bound.hip: full-order space-time residual and Theorem-3 bound per query
+size_t fom_bound_lds_bytes(int n_s, int m_D);
+hipError_t launch_fom_dict(int64_t N_s, int32_t n_s, int32_t Q, const st_csr* A, int32_t Qf, int32_t Q0,
+                           const double* Phi_s, const double* Bf, const double* u0, double* D, int32_t m_D,
+                           hipStream_t s);
+hipError_t launch_fom_residual(const RomView& rom, int64_t N_s, const double* D, int32_t m_D, int32_t n_q,
+                               const double* thA, const double* thf, const double* th0, const double* g,
+                               const int32_t* nt_q, Plan plan, const double* coeff, double inv_norm, double* res_inf,
+                               double* u_inf, double* bound, hipStream_t s);
+
 hipError_t launch_reconstruct(int64_t N_s, int32_t N_t, int32_t n_s, const double* Phi_s, int64_t ldp,
                               const double* Phi_t, int64_t ldt, const int32_t* moff, const int32_t* nt_q, int32_t n_q,
                               const double* coeff, const int64_t* coeff_off, double* out, int64_t ldo,

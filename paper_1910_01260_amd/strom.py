@@ -90,6 +90,9 @@ _SIGNATURES = {
     "st_coercivity_floor": (_D, [_I32]),
     "st_certify_workspace": (_SZ, [ctypes.POINTER(st_rom_desc), _I32, _I64]),
     "st_certify": (_I32, [ctypes.POINTER(st_rom_desc), _P, _I32, _P, _P, _P, _P, _P, _I64, _D, _P, _P, _P, _SZ, _P]),
+    "st_fom_bound_workspace": (_SZ, [ctypes.POINTER(st_rom_desc), _I64, _I32]),
+    "st_fom_bound": (_I32, [ctypes.POINTER(st_rom_desc), _P, _I64, _P, ctypes.POINTER(st_csr), _P, _P, _P, _I32, _P,
+                            _P, _P, _P, _P, _I64, _D, _P, _P, _P, _P, _SZ, _P]),
     "st_timing_enable": (_I32, [_I32]),
     "st_timing_read": (_I32, [ctypes.POINTER(ctypes.c_double), _I32]),
 }
@@ -488,3 +491,32 @@ def st_certify(desc: RomDesc, rom: torch.Tensor, theta_A: torch.Tensor, theta_f:
                             _ptr(coeff), cap, float(gamma), _ptr(relres), _ptr(cert), _ptr(ws), ws_bytes, _stream()),
            "st_certify")
     return relres[:n_q], cert[:n_q]
+
+
+def st_fom_bound(desc: RomDesc, rom: torch.Tensor, Phi_s: torch.Tensor, A_csr: list, Bf: Optional[torch.Tensor],
+                 g: Optional[torch.Tensor], u0: Optional[torch.Tensor], theta_A: torch.Tensor,
+                 theta_f: Optional[torch.Tensor], theta_0: Optional[torch.Tensor], coeff: torch.Tensor,
+                 nt_q: Optional[torch.Tensor] = None, inv_norm: float = 0.0, coeff_cap: Optional[int] = None):
+    """Full-order space-time residual and Theorem-3 bound per query.  Phi_s, Bf, g,
+    u0 column-major as for st_assemble.  Returns (res_inf, u_inf, bound)."""
+    n_q = int(theta_A.shape[0])
+    dev = theta_A.device
+    N_s = int(Phi_s.shape[0])
+    cap = int(coeff.numel()) if coeff_cap is None else int(coeff_cap)
+
+    def colmajor(t):
+        if t is None:
+            return None
+        if not t.T.is_contiguous():
+            raise ValueError("expected a column-major tensor (transpose contiguous)")
+        return ctypes.c_void_p(t.data_ptr())
+
+    out = [torch.empty(max(n_q, 1), dtype=torch.float64, device=dev) for _ in range(3)]
+    ws_bytes = lib().st_fom_bound_workspace(desc.ref(), N_s, n_q)
+    ws = torch.empty(max(ws_bytes, 1), dtype=torch.uint8, device=dev)
+    arr = (st_csr * len(A_csr))(*A_csr)
+    _check(lib().st_fom_bound(desc.ref(), _ptr(rom), N_s, colmajor(Phi_s), arr, colmajor(Bf), colmajor(g), colmajor(u0),
+                              n_q, _ptr(theta_A), _ptr(theta_f), _ptr(theta_0), _ptr(nt_q), _ptr(coeff), cap,
+                              float(inv_norm), _ptr(out[0]), _ptr(out[1]), _ptr(out[2]), _ptr(ws), ws_bytes,
+                              _stream()), "st_fom_bound")
+    return tuple(o[:n_q] for o in out)
