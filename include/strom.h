@@ -220,13 +220,20 @@ st_status st_build_bases(const void* U, int32_t U_prec, int64_t ldU, int64_t N_s
  * Bf       [dev] N_s x Qf (ld N_s) input vectors, or NULL when Qf = 0.
  * g        [dev] N_t x Qf (ld N_t) input time profiles, or NULL (all ones).
  * u0       [dev] N_s x Q0 (ld N_s) initial-state terms, or NULL when Q0 = 0.
+ * proj_prec  arithmetic of the projection Ahat_q = Phi_s^T (A_q Phi_s):
+ *          ST_F64: FP64 CSR SpMM and FP64 tall-skinny product;
+ *          ST_F32: FP32 SpMM (values and basis rounded to FP32, FP32
+ *          accumulation), then Phi_s^T (A_q Phi_s) on the matrix cores in FP32
+ *          (as a block of the Gram of [Phi_s, A_q Phi_s]), FP32 accumulation;
+ *          ST_BF16X3: the same with split-BF16 products (hi*hi + hi*lo + lo*hi).
+ *          bhat, u0hat and every temporal contraction are FP64 in all cases.
  * rom      [dev] output buffer of st_rom_layout(d).total bytes.
  * ====================================================================== */
 size_t st_assemble_workspace(const st_rom_desc* d, int64_t N_s);
 
 st_status st_assemble(const st_rom_desc* d, int64_t N_s, const double* Phi_s, const double* Phi_t,
                       const double* dt, const st_csr* A, const double* Bf, const double* g, const double* u0,
-                      void* rom, size_t rom_bytes, void* ws, size_t ws_bytes, void* stream);
+                      int32_t proj_prec, void* rom, size_t rom_bytes, void* ws, size_t ws_bytes, void* stream);
 
 /* ========================================================================
  * Per-query inputs shared by st_form and st_solve.

@@ -143,13 +143,19 @@ size_t st_assemble_workspace(const st_rom_desc* d, int64_t N_s) {
   part = part > tsgemm_partial_elems(N_s, d->n_s, d->Q0) ? part : tsgemm_partial_elems(N_s, d->n_s, d->Q0);
   part = part > tsgemm_partial_elems(d->N_t, (int32_t)n, (int32_t)n) ? part
                                                                       : tsgemm_partial_elems(d->N_t, (int32_t)n, (int32_t)n);
-  return align_up(sizeof(double) * (size_t)N_s * d->n_s) * 2 + align_up(sizeof(double) * part);
+  const size_t fp64 = align_up(sizeof(double) * (size_t)N_s * d->n_s) * 2 + align_up(sizeof(double) * part);
+  // reduced-precision projection: Z (N_s x 2 n_s FP32), its Gram and the Gram's partials
+  const int32_t p2 = 2 * d->n_s;
+  const size_t red = align_up(sizeof(float) * (size_t)N_s * p2) + align_up(sizeof(double) * (size_t)p2 * p2) +
+                     align_up(sizeof(double) * gram_partial_elems(N_s, p2));
+  return fp64 > red ? fp64 : red;
 }
 
 st_status st_assemble(const st_rom_desc* d, int64_t N_s, const double* Phi_s, const double* Phi_t, const double* dt,
-                      const st_csr* A, const double* Bf, const double* g, const double* u0, void* rom,
-                      size_t rom_bytes, void* ws, size_t ws_bytes, void* stream) {
+                      const st_csr* A, const double* Bf, const double* g, const double* u0, int32_t proj_prec,
+                      void* rom, size_t rom_bytes, void* ws, size_t ws_bytes, void* stream) {
   if (!desc_ok(d) || N_s < 1 || N_s > 0x7fffffff || !Phi_s || !Phi_t || !dt || !A || !rom || !ws) return ST_EINVAL;
+  if (proj_prec != ST_F64 && proj_prec != ST_F32 && proj_prec != ST_BF16X3) return ST_EINVAL;
   if (d->n_s > N_s) return ST_ERANK;
   if (d->Qf > 0 && !Bf) return ST_EINVAL;
   if (d->Q0 > 0 && !u0) return ST_EINVAL;
@@ -193,10 +199,30 @@ st_status st_assemble(const st_rom_desc* d, int64_t N_s, const double* Phi_s, co
   ST_TRY(launch_index_tables(mt, d->N_t, mv, s));
   const int32_t ns = d->n_s;
   // projection: Ahat_q = Phi_s^T (A_q Phi_s)
-  ST_TRY(launch_transpose(Phi_s, N_s, ns, N_s, Phir, s));
-  for (int q = 0; q < d->Q; ++q) {
-    ST_TRY(launch_spmm_rowmajor(A[q], Phir, ns, Y, s));
-    ST_TRY(launch_tsgemm(N_s, ns, ns, Phir, ns, 1, Y, ns, 1, mv.Ahat + (size_t)q * ns * ns, ns, part, part_elems, s));
+  if (proj_prec == ST_F64) {
+    ST_TRY(launch_transpose(Phi_s, N_s, ns, N_s, Phir, s));
+    for (int q = 0; q < d->Q; ++q) {
+      ST_TRY(launch_spmm_rowmajor(A[q], Phir, ns, Y, s));
+      ST_TRY(launch_tsgemm(N_s, ns, ns, Phir, ns, 1, Y, ns, 1, mv.Ahat + (size_t)q * ns * ns, ns, part, part_elems,
+                           s));
+    }
+  } else {
+    // FP32 SpMM into Z = [Phi_s, A_q Phi_s] (FP32, row-major), then Phi_s^T (A_q Phi_s) as the
+    // off-diagonal block of the Gram of Z on the matrix cores (FP32 or split-BF16 MFMA, FP32
+    // accumulation); the rest of the ROM stays FP64
+    Carver r(ws);
+    const int32_t p2 = 2 * ns;
+    float* Z = r.take<float>((size_t)N_s * p2);
+    double* G = r.take<double>((size_t)p2 * p2);
+    double* gpart = r.take<double>(gram_partial_elems(N_s, p2));
+    ST_TRY(launch_pack_basis_f32(Phi_s, N_s, ns, Z, s));
+    for (int q = 0; q < d->Q; ++q) {
+      ST_TRY(launch_spmm_f32(A[q], ns, Z, s));
+      ST_TRY(launch_gram(N_s, p2, Z, ST_F32, p2, 1, proj_prec, G, gpart, gram_partial_elems(N_s, p2), s));
+      ST_TRY(launch_extract_block(G, ns, mv.Ahat + (size_t)q * ns * ns, s));
+    }
+    // the row-major FP64 basis for bhat and u0hat below (it reuses Z's memory)
+    ST_TRY(launch_transpose(Phi_s, N_s, ns, N_s, Phir, s));
   }
   if (d->Qf > 0) ST_TRY(launch_tsgemm(N_s, ns, d->Qf, Phir, ns, 1, Bf, 1, N_s, mv.bhat, ns, part, part_elems, s));
   if (d->Q0 > 0) ST_TRY(launch_tsgemm(N_s, ns, d->Q0, Phir, ns, 1, u0, 1, N_s, mv.u0hat, ns, part, part_elems, s));

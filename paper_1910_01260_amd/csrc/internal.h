@@ -75,6 +75,11 @@ hipError_t launch_tsgemm_xf(int64_t N, int32_t p, int32_t q, const float* X, int
                             const double* Y, int64_t yrs, int64_t ycs, double* C, int32_t ldc, double* partial,
                             size_t partial_elems, hipStream_t s);
 size_t tsgemm_partial_elems(int64_t N, int32_t p, int32_t q);
+// reduced-precision projection: Z = [Phi_s, A Phi_s] in FP32 (row-major N x 2p), then the
+// Phi_s^T (A Phi_s) block of its Gram
+hipError_t launch_pack_basis_f32(const double* Phi, int64_t N, int32_t p, float* Z, hipStream_t s);
+hipError_t launch_spmm_f32(const st_csr& A, int32_t p, float* Z, hipStream_t s);
+hipError_t launch_extract_block(const double* G, int32_t p, double* Ahat, hipStream_t s);
 hipError_t launch_mode_offsets(const ModeTable& mt, int32_t* moff, hipStream_t s);
 hipError_t launch_temporal(const double* Phi_t, int32_t N_t, int32_t n, const double* dt, const double* g, int32_t Qf,
                            const ModeTable& mt, MutRomView rom, hipStream_t s);

@@ -81,6 +81,43 @@ __global__ __launch_bounds__(256) void spmm_rowmajor_kernel(int32_t n_rows, cons
   }
 }
 
+// Reduced-precision projection.  Z (N x 2p, row-major FP32) holds [Phi_s, A Phi_s]:
+// Z[x, m] = Phi_s[x, m] (from the column-major FP64 basis, ld N) ...
+__global__ void pack_basis_f32_kernel(const double* __restrict__ Phi, int64_t N, int32_t p, float* __restrict__ Z) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= N * p) return;
+  const int64_t x = e / p;
+  const int32_t m = (int32_t)(e % p);
+  Z[x * 2 * p + m] = (float)Phi[x + (int64_t)m * N];
+}
+
+// ... and Z[x, p + m] = (A Phi_s)[x, m] with FP32 products and FP32 accumulation (the
+// CSR values rounded to FP32), one wave per row, lanes over m.
+__global__ __launch_bounds__(256) void spmm_f32_kernel(int32_t n_rows, const int32_t* __restrict__ row_ptr,
+                                                       const int32_t* __restrict__ col_idx,
+                                                       const double* __restrict__ val, int32_t p,
+                                                       float* __restrict__ Z) {
+  const int lane = threadIdx.x & 63;
+  const int64_t row = (int64_t)blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;
+  if (row >= n_rows) return;
+  const int32_t b = row_ptr[row], e = row_ptr[row + 1];
+  for (int m0 = 0; m0 < p; m0 += 64) {
+    const int m = m0 + lane;
+    if (m >= p) continue;
+    float acc = 0.f;
+    for (int32_t z = b; z < e; ++z) acc = fmaf((float)val[z], Z[(int64_t)col_idx[z] * 2 * p + m], acc);
+    Z[row * 2 * p + p + m] = acc;
+  }
+}
+
+// Ahat[a + b p] = G[a + (p + b) 2p]: the Phi_s^T (A Phi_s) block of the Gram of Z
+__global__ void extract_block_kernel(const double* __restrict__ G, int32_t p, double* __restrict__ Ahat) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= p * p) return;
+  const int a = e % p, b = e / p;
+  Ahat[e] = G[a + (int64_t)(p + b) * 2 * p];
+}
+
 // Split-K tall-skinny product: partial[z] (p x q, column-major) = sum over the
 // z-th row range of w[r] X[r,:]^T Y[r,:].  32 x 32 output tile per workgroup.
 template <typename TX>
@@ -210,6 +247,23 @@ hipError_t launch_spmm_rowmajor(const st_csr& A, const double* Xr, int32_t p, do
   const int rows_per_block = 4;
   dim3 grid((unsigned)((A.n_rows + rows_per_block - 1) / rows_per_block));
   hipLaunchKernelGGL(spmm_rowmajor_kernel, grid, dim3(256), 0, s, A.n_rows, A.row_ptr, A.col_idx, A.val, Xr, p, Yr);
+  return hipGetLastError();
+}
+
+hipError_t launch_pack_basis_f32(const double* Phi, int64_t N, int32_t p, float* Z, hipStream_t s) {
+  const int64_t e = N * p;
+  hipLaunchKernelGGL(pack_basis_f32_kernel, dim3((unsigned)((e + 255) / 256)), dim3(256), 0, s, Phi, N, p, Z);
+  return hipGetLastError();
+}
+
+hipError_t launch_spmm_f32(const st_csr& A, int32_t p, float* Z, hipStream_t s) {
+  hipLaunchKernelGGL(spmm_f32_kernel, dim3((unsigned)((A.n_rows + 3) / 4)), dim3(256), 0, s, A.n_rows, A.row_ptr,
+                     A.col_idx, A.val, p, Z);
+  return hipGetLastError();
+}
+
+hipError_t launch_extract_block(const double* G, int32_t p, double* Ahat, hipStream_t s) {
+  hipLaunchKernelGGL(extract_block_kernel, dim3((p * p + 255) / 256), dim3(256), 0, s, G, p, Ahat);
   return hipGetLastError();
 }
 

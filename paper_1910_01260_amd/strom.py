@@ -59,8 +59,8 @@ _SIGNATURES = {
     "st_build_bases": (_I32, [_P, _I32, _I64, _I64, _I32, _I32, _I32, _P, _I32, _D, _P, _P, _P, _P, _P, _P, _SZ,
                               _P]),
     "st_assemble_workspace": (_SZ, [ctypes.POINTER(st_rom_desc), _I64]),
-    "st_assemble": (_I32, [ctypes.POINTER(st_rom_desc), _I64, _P, _P, _P, ctypes.POINTER(st_csr), _P, _P, _P, _P, _SZ,
-                           _P, _SZ, _P]),
+    "st_assemble": (_I32, [ctypes.POINTER(st_rom_desc), _I64, _P, _P, _P, ctypes.POINTER(st_csr), _P, _P, _P, _I32, _P,
+                           _SZ, _P, _SZ, _P]),
     "st_form_workspace": (_SZ, [ctypes.POINTER(st_rom_desc), _I32]),
     "st_form": (_I32, [ctypes.POINTER(st_rom_desc), _P, _I32, _P, _P, _P, _P, _I32, _P, _I64, _P, _I64, _P, _P, _P,
                        _P, _SZ, _P]),
@@ -223,7 +223,7 @@ def st_build_bases(U: torch.Tensor, N_t: int, n_mu: int, n_s: int, n_t: Sequence
 
 def st_assemble(desc: RomDesc, Phi_s: torch.Tensor, Phi_t: torch.Tensor, dt: torch.Tensor, A_csr: list,
                 Bf: Optional[torch.Tensor] = None, g: Optional[torch.Tensor] = None,
-                u0: Optional[torch.Tensor] = None) -> torch.Tensor:
+                u0: Optional[torch.Tensor] = None, proj_prec: int = ST_F64) -> torch.Tensor:
     """Offline ROM buffer.  Phi_s (N_s x n_s) and Phi_t (N_t x n) column-major
     (transposes contiguous); Bf (N_s x Qf), g (N_t x Qf), u0 (N_s x Q0)
     column-major likewise; A_csr a list of st_csr descriptors."""
@@ -242,7 +242,8 @@ def st_assemble(desc: RomDesc, Phi_s: torch.Tensor, Phi_t: torch.Tensor, dt: tor
     ws = torch.empty(max(ws_bytes, 1), dtype=torch.uint8, device=Phi_s.device)
     arr = (st_csr * len(A_csr))(*A_csr)
     _check(lib().st_assemble(desc.ref(), N_s, colmajor(Phi_s), colmajor(Phi_t), _ptr(dt), arr, colmajor(Bf),
-                             colmajor(g), colmajor(u0), _ptr(rom), lay["total"], _ptr(ws), ws_bytes, _stream()),
+                             colmajor(g), colmajor(u0), int(proj_prec), _ptr(rom), lay["total"], _ptr(ws), ws_bytes,
+                             _stream()),
            "st_assemble")
     return rom
 

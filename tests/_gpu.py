@@ -18,7 +18,7 @@ def colmajor(a: np.ndarray) -> torch.Tensor:
 class DeviceRom:
     """ROM buffer built on the device from given bases (st_assemble)."""
 
-    def __init__(self, prob, Phi_s: np.ndarray, Phi_t_list):
+    def __init__(self, prob, Phi_s: np.ndarray, Phi_t_list, proj_prec=strom.ST_F64):
         self.prob = prob
         n_t = [P.shape[1] for P in Phi_t_list]
         self.desc = strom.RomDesc(n_t, prob.N_t, prob.Q, prob.Qf, prob.Q0)
@@ -30,7 +30,7 @@ class DeviceRom:
         self.g = colmajor(prob.g) if prob.Qf else None
         self.u0 = colmajor(prob.u0) if prob.Q0 else None
         self.rom = strom.st_assemble(self.desc, self.Phi_s, self.Phi_t, self.dt, [c[0] for c in self.csr], self.Bf,
-                                     self.g, self.u0)
+                                     self.g, self.u0, proj_prec)
         torch.cuda.synchronize()
 
     def section(self, name):

@@ -98,10 +98,12 @@ def test_host_validation_rejects_bad_arguments():
                      1 << 20, None) == -1
     # st_assemble: rank and CSR shape checks
     csr = (strom.st_csr * 2)(strom.st_csr(16, 0, 0x1000, 0, 0), strom.st_csr(16, 0, 0x1000, 0, 0))
-    assert L.st_assemble(good.ref(), 1, fake, fake, fake, csr, None, None, fake, fake, 1 << 20, fake, 1 << 20,
+    assert L.st_assemble(good.ref(), 1, fake, fake, fake, csr, None, None, fake, 0, fake, 1 << 20, fake, 1 << 20,
                          None) == -4                 # n_s = 2 > N_s = 1
-    assert L.st_assemble(good.ref(), 8, fake, fake, fake, csr, None, None, fake, fake, 1 << 20, fake, 1 << 20,
+    assert L.st_assemble(good.ref(), 8, fake, fake, fake, csr, None, None, fake, 0, fake, 1 << 20, fake, 1 << 20,
                          None) == -1                 # CSR rows 16 != N_s 8
+    assert L.st_assemble(good.ref(), 16, fake, fake, fake, csr, None, None, fake, 9, fake, 1 << 20, fake, 1 << 20,
+                         None) == -1                 # bad projection precision
 
 
 def test_workspace_sizes_with_empty_term_lists():

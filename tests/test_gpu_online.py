@@ -368,3 +368,45 @@ def test_certify_ragged_matches_oracle_certificate(cb_rom):
             assert abs(cert[q] - ref_cert) <= 1e-8 * ref_cert + slack * (1 + ref_cert) ** 2, (q, cert[q], ref_cert)
         assert _rel(x, exact[q]) <= cert[q]
     assert np.isfinite(cert).sum() >= n_q // 2
+
+
+@pytest.mark.parametrize("prec", [strom.ST_F32, strom.ST_BF16X3])
+def test_reduced_precision_projection_reports_error(prec):
+    """Projection in reduced precision (FP32 SpMM with FP32 accumulation, then
+    Phi_s^T (A_q Phi_s) on the matrix cores in FP32 or split-BF16) on the transport
+    problem's three affine terms, against the FP64 oracle (Sec. 3.1, Eq. (galerkin)).
+
+    Elementwise a priori bound (deterministic): the FP32 rounding of the values and
+    the basis, the SpMM's FP32 sums of nnz_row terms and the product's sums of N_s
+    terms each add at most (k + 2) u relative to |Phi|^T |A_q| |Phi|, with u = 2^-24,
+    or u = 2^-16 for the split-BF16 products.  Errors and the resulting ROM solution
+    error are printed against FP64."""
+    name = "c2_small"
+    prob = C.problem(name)
+    Phi_s, sigma, V, Phi_t, ranks = C.oracle_bases(name)
+    print(f"[{name}] st_assemble proj_prec={prec}", flush=True)
+    dr = DeviceRom(prob, Phi_s, Phi_t, proj_prec=prec)
+    n_s = Phi_s.shape[1]
+    got = dr.section("Ahat").cpu().numpy()[: prob.Q * n_s * n_s].reshape(prob.Q, n_s, n_s)
+    Ahat, bhat, u0hat = C.oracle_spatial(name)
+    u_prod = 2.0 ** -16 if prec == strom.ST_BF16X3 else 2.0 ** -24
+    worst = 0.0
+    for q, Aq in enumerate(prob.terms):
+        absA = abs(Aq)
+        scale = np.abs(Phi_s).T @ (absA @ np.abs(Phi_s))
+        nnz_row = int(np.diff(Aq.indptr).max())
+        bound = ((nnz_row + 4) * 2.0 ** -24 + (prob.N_s + 2) * u_prod) * scale
+        err = np.abs(got[q].T - Ahat[q])
+        assert (err <= bound + 1e-300).all(), (q, float((err / np.maximum(bound, 1e-300)).max()))
+        worst = max(worst, float(err.max() / np.abs(Ahat[q]).max()))
+    # the ROM solution from the reduced-precision operators, against FP64
+    ref = DeviceRom(prob, Phi_s, Phi_t)
+    mus = W.sample_params(prob, 4, seed=61)
+    (tA, tf, t0), (dA, df, d0) = thetas_device(prob, mus)
+    b1 = strom.st_solve(dr.desc, dr.rom, dA, df, d0)
+    b0 = strom.st_solve(ref.desc, ref.rom, dA, df, d0)
+    torch.cuda.synchronize()
+    c1, c0 = b1.coeff.cpu().numpy(), b0.coeff.cpu().numpy()
+    sol = _rel(c1, c0)
+    print(f"[{name}] proj_prec={prec}: max |dAhat|/max|Ahat| {worst:.2e}, ROM solution rel err {sol:.2e}")
+    assert sol <= 1e-2
