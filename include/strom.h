@@ -439,6 +439,37 @@ st_status st_fom_bound(const st_rom_desc* d, const void* rom, int64_t N_s, const
                        size_t ws_bytes, void* stream);
 
 /* ========================================================================
+ * Spatial Galerkin ROM (Sec. 3.1): the paper's point of comparison for the
+ * space-time ROM.
+ *
+ * st_spatial_march: for each query, the backward-Euler march of Eq.
+ * (space_reduced_discretized_ODE) with u_ref = 0,
+ *   (I - dt_k Ahat(mu)) uhat^(k) = uhat^(k-1) + dt_k sum_q theta_f[q] g[k,q] bhat_q,
+ *   uhat^(0) = sum_q theta_0[q] u0hat_q,
+ * from the ROM buffer's Ahat_q, bhat_q, u0hat_q and steps, and the reduced
+ * outputs of Eq. (outputFromReducedsol), y^(k) = Chat^T uhat^(k).
+ * g        [dev] N_t x Qf input time profiles (ld N_t) or NULL (all ones).
+ * Chat     [dev] n_s x n_out (ld n_s) reduced output matrix Phi_s^T C (see
+ *          st_project), or NULL when outputs is NULL.
+ * traj     [dev] n_q x N_t x n_s (query, step, mode; uhat^(1..N_t)) or NULL.
+ * outputs  [dev] n_q x N_t x n_out or NULL.
+ * info     [dev] n_q: 0, -5 (non-finite parameter coefficient), or k > 0 when
+ *          I - dt_k Ahat(mu) is singular (its entries are then NaN).
+ * Each query factors I - dt Ahat(mu) once per distinct step size (an explicit
+ * inverse by Gauss-Jordan elimination with partial pivoting, FP64), then
+ * marches.  n_s <= 128 and (n_s^2 + (3 + Qf) n_s) 8 bytes <= 160 KB.
+ *
+ * st_project: out (n_s x k, ld n_s) = Phi_s^T X, X N_s x k (ld N_s), FP64,
+ * e.g. Chat = Phi_s^T C (Eq. (galerkin)).
+ * ====================================================================== */
+st_status st_spatial_march(const st_rom_desc* d, const void* rom, int32_t n_q, const double* theta_A,
+                           const double* theta_f, const double* theta_0, const double* g, int32_t n_out,
+                           const double* Chat, double* traj, double* outputs, int32_t* info, void* stream);
+size_t st_project_workspace(int64_t N_s, int32_t n_s, int32_t k);
+st_status st_project(int64_t N_s, int32_t n_s, const double* Phi_s, int32_t k, const double* X, double* out, void* ws,
+                     size_t ws_bytes, void* stream);
+
+/* ========================================================================
  * Phase timing (measurement tools).  After st_timing_enable(1), every st_solve
  * records HIP events on its stream at its phase boundaries; after the caller
  * has synchronised that stream, st_timing_read fills ms[p] with the elapsed

@@ -49,6 +49,13 @@ def spatial_rom_march(Ahat, BF_hat, u0hat, dt):
     return out
 
 
+def spatial_rom_output(Chat, U_hat):
+    """Eq. (outputFromReducedsol) with u_ref = 0: y^(k) = Chat^T uhat^(k),
+    Chat = Phi_s^T C (N_s x n_out output matrix C).  U_hat is n_s x N_t;
+    returns n_out x N_t."""
+    return np.asarray(Chat).T @ np.asarray(U_hat)
+
+
 # ----------------------------------------------------------------------------
 # explicit space-time basis (small sizes), Sec. 3.2 / 4.1
 # ----------------------------------------------------------------------------

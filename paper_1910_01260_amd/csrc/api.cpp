@@ -1085,6 +1085,34 @@ st_status st_fom_bound(const st_rom_desc* d, const void* rom, int64_t N_s, const
   return ST_OK;
 }
 
+st_status st_spatial_march(const st_rom_desc* d, const void* rom, int32_t n_q, const double* theta_A,
+                           const double* theta_f, const double* theta_0, const double* g, int32_t n_out,
+                           const double* Chat, double* traj, double* outputs, int32_t* info, void* stream) {
+  if (!query_args_ok(d, rom, n_q, theta_A, theta_f, theta_0) || n_out < 0) return ST_EINVAL;
+  if (d->n_s > kMaxFormModes || spatial_march_lds_bytes(d->n_s, d->Qf) > 160 * 1024) return ST_EUNSUPPORTED;
+  if (n_q == 0) return ST_OK;
+  if (!info || (outputs && (n_out < 1 || !Chat))) return ST_EINVAL;
+  ST_TRY(launch_spatial_march(view_of(d, rom), n_q, theta_A, theta_f, theta_0, g, outputs ? n_out : 0, Chat, traj,
+                              outputs, info, static_cast<hipStream_t>(stream)));
+  return ST_OK;
+}
+
+size_t st_project_workspace(int64_t N_s, int32_t n_s, int32_t k) {
+  if (N_s < 1 || n_s < 1 || k < 0) return 0;
+  return align_up(sizeof(double) * tsgemm_partial_elems(N_s, n_s, k)) + 256;
+}
+
+st_status st_project(int64_t N_s, int32_t n_s, const double* Phi_s, int32_t k, const double* X, double* out, void* ws,
+                     size_t ws_bytes, void* stream) {
+  if (N_s < 1 || n_s < 1 || k < 0 || n_s > N_s) return ST_EINVAL;
+  if (k == 0) return ST_OK;
+  if (!Phi_s || !X || !out || !ws) return ST_EINVAL;
+  if (ws_bytes < st_project_workspace(N_s, n_s, k)) return ST_EWORKSPACE;
+  ST_TRY(launch_tsgemm(N_s, n_s, k, Phi_s, 1, N_s, X, 1, N_s, out, n_s, static_cast<double*>(ws),
+                       (ws_bytes - 256) / sizeof(double), static_cast<hipStream_t>(stream)));
+  return ST_OK;
+}
+
 st_status st_certify(const st_rom_desc* d, const void* rom, int32_t n_q, const double* theta_A, const double* theta_f,
                      const double* theta_0, const int32_t* nt_q, const double* coeff, int64_t coeff_cap, double gamma,
                      double* relres, double* cert, void* ws, size_t ws_bytes, void* stream) {

@@ -142,6 +142,12 @@ hipError_t launch_fom_residual(const RomView& rom, int64_t N_s, const double* D,
                                const int32_t* nt_q, Plan plan, const double* coeff, double inv_norm, double* res_inf,
                                double* u_inf, double* bound, hipStream_t s);
 
+// k_spatial.hip: spatial-ROM time march and outputs
+size_t spatial_march_lds_bytes(int n_s, int Qf);
+hipError_t launch_spatial_march(const RomView& rom, int32_t n_q, const double* thA, const double* thf,
+                                const double* th0, const double* g, int32_t n_out, const double* Chat, double* traj,
+                                double* outs, int32_t* info, hipStream_t s);
+
 hipError_t launch_reconstruct(int64_t N_s, int32_t N_t, int32_t n_s, const double* Phi_s, int64_t ldp,
                               const double* Phi_t, int64_t ldt, const int32_t* moff, const int32_t* nt_q, int32_t n_q,
                               const double* coeff, const int64_t* coeff_off, double* out, int64_t ldo,

@@ -93,6 +93,9 @@ _SIGNATURES = {
     "st_fom_bound_workspace": (_SZ, [ctypes.POINTER(st_rom_desc), _I64, _I32]),
     "st_fom_bound": (_I32, [ctypes.POINTER(st_rom_desc), _P, _I64, _P, ctypes.POINTER(st_csr), _P, _P, _P, _I32, _P,
                             _P, _P, _P, _P, _I64, _D, _P, _P, _P, _P, _SZ, _P]),
+    "st_spatial_march": (_I32, [ctypes.POINTER(st_rom_desc), _P, _I32, _P, _P, _P, _P, _I32, _P, _P, _P, _P, _P]),
+    "st_project_workspace": (_SZ, [_I64, _I32, _I32]),
+    "st_project": (_I32, [_I64, _I32, _P, _I32, _P, _P, _P, _SZ, _P]),
     "st_timing_enable": (_I32, [_I32]),
     "st_timing_read": (_I32, [ctypes.POINTER(ctypes.c_double), _I32]),
 }
@@ -160,6 +163,14 @@ class RomDesc:
         self.n_t_arr = np.ascontiguousarray(np.asarray(n_t, dtype=np.int32))
         self.n_t_ptr = self.n_t_arr.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
         self.c = st_rom_desc(len(self.n_t_arr), int(N_t), int(Q), int(Qf), int(Q0), self.n_t_ptr)
+
+    @property
+    def N_t(self):
+        return int(self.c.N_t)
+
+    @property
+    def n_t(self):
+        return self.n_t_arr.tolist()
 
     @property
     def n_s(self):
@@ -521,3 +532,42 @@ def st_fom_bound(desc: RomDesc, rom: torch.Tensor, Phi_s: torch.Tensor, A_csr: l
                               float(inv_norm), _ptr(out[0]), _ptr(out[1]), _ptr(out[2]), _ptr(ws), ws_bytes,
                               _stream()), "st_fom_bound")
     return tuple(o[:n_q] for o in out)
+
+
+def st_project(Phi_s: torch.Tensor, X: torch.Tensor) -> torch.Tensor:
+    """Phi_s^T X (n_s x k, column-major view) for column-major Phi_s (N_s x n_s) and X (N_s x k)."""
+    N_s, n_s = int(Phi_s.shape[0]), int(Phi_s.shape[1])
+    k = int(X.shape[1])
+    if not (Phi_s.T.is_contiguous() and X.T.is_contiguous()):
+        raise ValueError("expected column-major tensors (transpose contiguous)")
+    out = torch.empty((k, n_s), dtype=torch.float64, device=Phi_s.device)
+    ws_bytes = lib().st_project_workspace(N_s, n_s, k)
+    ws = torch.empty(max(ws_bytes, 1), dtype=torch.uint8, device=Phi_s.device)
+    _check(lib().st_project(N_s, n_s, ctypes.c_void_p(Phi_s.data_ptr()), k, ctypes.c_void_p(X.data_ptr()), _ptr(out),
+                            _ptr(ws), ws_bytes, _stream()), "st_project")
+    return out.T
+
+
+def st_spatial_march(desc: RomDesc, rom: torch.Tensor, theta_A: torch.Tensor, theta_f: Optional[torch.Tensor],
+                     theta_0: Optional[torch.Tensor], g: Optional[torch.Tensor] = None,
+                     Chat: Optional[torch.Tensor] = None, want_traj: bool = True):
+    """Batched spatial-ROM march.  g (N_t x Qf) and Chat (n_s x n_out) column-major.
+    Returns (traj (n_q, N_t, n_s) or None, outputs (n_q, N_t, n_out) or None, info)."""
+    n_q = int(theta_A.shape[0])
+    dev = theta_A.device
+    traj = torch.empty((n_q, desc.N_t, desc.n_s), dtype=torch.float64, device=dev) if want_traj else None
+    n_out = int(Chat.shape[1]) if Chat is not None else 0
+    outs = torch.empty((n_q, desc.N_t, n_out), dtype=torch.float64, device=dev) if Chat is not None else None
+    info = torch.empty(max(n_q, 1), dtype=torch.int32, device=dev)
+
+    def colmajor(t):
+        if t is None:
+            return None
+        if not t.T.is_contiguous():
+            raise ValueError("expected a column-major tensor (transpose contiguous)")
+        return ctypes.c_void_p(t.data_ptr())
+
+    _check(lib().st_spatial_march(desc.ref(), _ptr(rom), n_q, _ptr(theta_A), _ptr(theta_f), _ptr(theta_0), colmajor(g),
+                                  n_out, colmajor(Chat), _ptr(traj), _ptr(outs), _ptr(info), _stream()),
+           "st_spatial_march")
+    return traj, outs, info[:n_q]

@@ -323,6 +323,20 @@ def test_complete_spatial_basis_spatial_rom_is_fom():
     np.testing.assert_allclose(Q @ march, _fom(prob, mu), atol=1e-13)
 
 
+def test_spatial_rom_output_complete_basis_is_fom_output():
+    """P13 for the outputs: with n_s = N_s, y^(k) = Chat^T uhat^(k) equals C^T u^(k)
+    of the full-order march (Eq. (outputFromReducedsol), u_ref = 0)."""
+    prob = _tiny_transport(nx=3, ndir=4, N_t=5)
+    mu = W.sample_params(prob, 1, seed=14)[0]
+    N = prob.N_s
+    Q = np.linalg.qr(np.random.default_rng(15).standard_normal((N, N)))[0]
+    C = np.random.default_rng(16).standard_normal((N, 3))
+    A = prob.operator(mu).toarray()
+    Uh = rom.spatial_rom_march(Q.T @ A @ Q, Q.T @ prob.forcing(mu), Q.T @ prob.initial(mu), prob.dt)
+    y = rom.spatial_rom_output(Q.T @ C, Uh)
+    np.testing.assert_allclose(y, C.T @ _fom(prob, mu), atol=1e-12 * np.abs(C.T @ _fom(prob, mu)).max())
+
+
 def test_galerkin_orthogonality():
     """P10: Phi_st^T r_st(Phi_st c) = 0 for the ST-ROM solution c."""
     prob = _tiny_transport()
