@@ -116,7 +116,7 @@ typedef struct {
 } st_rom_desc;
 
 /* Byte offsets of the sections of a ROM buffer (filled by st_rom_layout).
- * All sections are FP64 except the two index tables (int32).
+ * All sections are FP64 except the index tables (int32, int64) and T32.
  *   Ahat   Q  x (n_s x n_s)  Ahat_q = Phi_s^T A_q Phi_s           (Eq. (galerkin))
  *   bhat   Qf x n_s          Phi_s^T Bf_q
  *   u0hat  Q0 x n_s          Phi_s^T u0_q
@@ -130,10 +130,11 @@ typedef struct {
  *   koff   n_s + 1 (int64)   element offsets of each K_i inside K
  *   Phit   N_t x n           the concatenated temporal bases, column-major (Phit[k + N_t a] = phi_a(k))
  *   dt     N_t               the time steps
+ *   T32    n x n (FP32)      T rounded to FP32 (read by the FP32 assembly)
  * where phi_a is column a of the concatenated temporal bases (mode-major).
  */
 typedef struct {
-  size_t Ahat, bhat, u0hat, T, K, Wf, P1, mode, moff, koff, Phit, dt, total;
+  size_t Ahat, bhat, u0hat, T, K, Wf, P1, mode, moff, koff, Phit, dt, T32, total;
 } st_rom_layout_t;
 
 st_status st_rom_layout(const st_rom_desc* d, st_rom_layout_t* out);

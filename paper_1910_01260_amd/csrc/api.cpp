@@ -47,6 +47,7 @@ void layout_of(const st_rom_desc* d, st_rom_layout_t* L) {
   L->koff = o;  o = align_up(o + sizeof(int64_t) * (n_s + 1));
   L->Phit = o;  o = align_up(o + sizeof(double) * d->N_t * n);
   L->dt = o;    o = align_up(o + sizeof(double) * d->N_t);
+  L->T32 = o;   o = align_up(o + sizeof(float) * n * n);
   L->total = o;
 }
 
@@ -67,6 +68,7 @@ RomView view_of(const st_rom_desc* d, const void* rom) {
   v.koff = reinterpret_cast<const int64_t*>(b + L.koff);
   v.Phit = reinterpret_cast<const double*>(b + L.Phit);
   v.dt = reinterpret_cast<const double*>(b + L.dt);
+  v.T32 = reinterpret_cast<const float*>(b + L.T32);
   v.n_s = d->n_s;
   v.N_t = d->N_t;
   v.n = (int32_t)total_nt(d);
@@ -185,6 +187,7 @@ st_status st_assemble(const st_rom_desc* d, int64_t N_s, const double* Phi_s, co
   mv.koff = reinterpret_cast<int64_t*>(rb + L.koff);
   mv.Phit = reinterpret_cast<double*>(rb + L.Phit);
   mv.dt = reinterpret_cast<double*>(rb + L.dt);
+  mv.T32 = reinterpret_cast<float*>(rb + L.T32);
 
   Carver c(ws);
   double* Phir = c.take<double>((size_t)N_s * d->n_s);
@@ -230,6 +233,7 @@ st_status st_assemble(const st_rom_desc* d, int64_t N_s, const double* Phi_s, co
   ST_TRY(launch_tsgemm_w(d->N_t, (int32_t)n, (int32_t)n, Phi_t, 1, d->N_t, Phi_t, 1, d->N_t, dt, mv.T, (int32_t)n, part,
                          part_elems, s));
   ST_TRY(launch_temporal(Phi_t, d->N_t, (int32_t)n, dt, g, d->Qf, mt, mv, s));
+  ST_TRY(launch_round_f32(mv.T, (int64_t)n * n, mv.T32, s));
   // the bases and steps themselves, for the residual evaluated on the time grid
   ST_TRY(launch_copy_cols(Phi_t, d->N_t, mv.Phit, d->N_t, d->N_t, (int)n, s));
   ST_TRY(launch_copy_cols(dt, d->N_t, mv.dt, d->N_t, d->N_t, 1, s));

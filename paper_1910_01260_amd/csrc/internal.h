@@ -34,6 +34,7 @@ struct RomView {
   const int64_t* koff;  // n_s + 1
   const double* Phit;   // N_t x n, column-major (the concatenated temporal bases)
   const double* dt;     // N_t
+  const float* T32;     // n x n, T rounded to FP32 (read by the FP32 assembly)
   int32_t n_s, N_t, n, Q, Qf, Q0;
 };
 
@@ -42,6 +43,7 @@ struct MutRomView {
   int32_t *mode, *moff;
   int64_t* koff;
   double *Phit, *dt;
+  float* T32;
 };
 
 inline size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
@@ -81,6 +83,7 @@ hipError_t launch_pack_basis_f32(const double* Phi, int64_t N, int32_t p, float*
 hipError_t launch_spmm_f32(const st_csr& A, int32_t p, float* Z, hipStream_t s);
 hipError_t launch_extract_block(const double* G, int32_t p, double* Ahat, hipStream_t s);
 hipError_t launch_mode_offsets(const ModeTable& mt, int32_t* moff, hipStream_t s);
+hipError_t launch_round_f32(const double* src, int64_t n, float* dst, hipStream_t s);
 hipError_t launch_temporal(const double* Phi_t, int32_t N_t, int32_t n, const double* dt, const double* g, int32_t Qf,
                            const ModeTable& mt, MutRomView rom, hipStream_t s);
 

@@ -267,6 +267,17 @@ hipError_t launch_extract_block(const double* G, int32_t p, double* Ahat, hipStr
   return hipGetLastError();
 }
 
+__global__ void round_f32_kernel(const double* __restrict__ src, int64_t n, float* __restrict__ dst) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < n) dst[e] = (float)src[e];
+}
+
+hipError_t launch_round_f32(const double* src, int64_t n, float* dst, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(round_f32_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, src, n, dst);
+  return hipGetLastError();
+}
+
 size_t tsgemm_partial_elems(int64_t N, int32_t p, int32_t q) {
   if (p <= 0 || q <= 0) return 0;
   return (size_t)tsgemm_splits(N, p, q) * (size_t)p * (size_t)q;

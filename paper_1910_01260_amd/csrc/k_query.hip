@@ -6,6 +6,8 @@
 //   * residual: r = b - Ahat_st(mu) x in FP64 evaluated from the ROM pieces
 //     (T, K, Ahat_q), never from a stored matrix;
 //   * small bookkeeping kernels for iterative refinement.
+#include <type_traits>
+
 #include "internal.h"
 #include "wave_ops.h"
 
@@ -182,12 +184,16 @@ __device__ inline void query_setup(const RomView& rom, int32_t q, int32_t i, con
     L.Ah[ic] = v;
   }
   __syncthreads();
-  for (int m = threadIdx.x; m < n_s; m += blockDim.x) {
-    const int32_t b = L.loff[m], e = L.loff[m + 1], g0 = rom.moff[m];
-    for (int32_t c = b; c < e; ++c) {
-      L.gmap[c] = g0 + (c - b);
-      L.mmap[c] = (int16_t)m;
+  // column maps: local column c -> mode (binary search of the offsets) and global index
+  const int32_t wq = L.loff[n_s];
+  for (int c = threadIdx.x; c < wq; c += blockDim.x) {
+    int lo = 0, hi = n_s - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (L.loff[mid] <= c) lo = mid; else hi = mid - 1;
     }
+    L.mmap[c] = (int16_t)lo;
+    L.gmap[c] = rom.moff[lo] + (c - L.loff[lo]);
   }
   __syncthreads();
 }
@@ -196,6 +202,43 @@ __device__ inline void query_setup(const RomView& rom, int32_t q, int32_t i, con
 constexpr int kRowUnroll = 4;
 // Rows of one residual pass (their partial sums live in registers).
 constexpr int kResRows = 8;
+
+// The rows of one mode i for the columns c = cb + 256 k (k < KC) of one query's
+// system outside the mode's own block: -Ahat(mu)[i, mode(c)] T[g0 + j, gmap(c)].
+// T symmetric: column g0 + j holds row g0 + j.
+template <typename OutT, typename TT, int KC>
+__device__ inline void form_columns(const QueryLds& L, int w, int cb, int nti, int g0, int r0, int64_t n,
+                                    const TT* __restrict__ tsrc, OutT* __restrict__ M) {
+  int gc[KC];
+  double ah[KC];
+  bool ok[KC];
+#pragma unroll
+  for (int k = 0; k < KC; ++k) {
+    const int c = cb + k * kFormThreads;
+    ok[k] = c < w && (c < r0 || c >= r0 + nti);
+    gc[k] = c < w ? L.gmap[c] : 0;
+    ah[k] = c < w ? -L.Ah[L.mmap[c]] : 0.0;
+  }
+  constexpr int RU = 8;  // rows whose T loads are in flight together
+  for (int j0 = 0; j0 < nti; j0 += RU) {
+    OutT v[RU][KC];
+#pragma unroll
+    for (int u = 0; u < RU; ++u) {
+      const int j = min(j0 + u, nti - 1);
+      const TT* Trow = tsrc + (int64_t)(g0 + j) * n;
+#pragma unroll
+      for (int k = 0; k < KC; ++k) v[u][k] = (OutT)(ah[k] * (double)Trow[gc[k]]);
+    }
+#pragma unroll
+    for (int u = 0; u < RU; ++u) {
+      if (j0 + u >= nti) break;
+      OutT* Mr = M + (int64_t)(r0 + j0 + u) * w;
+#pragma unroll
+      for (int k = 0; k < KC; ++k)
+        if (ok[k]) Mr[cb + k * kFormThreads] = v[u][k];
+    }
+  }
+}
 
 template <typename OutT>
 __global__ __launch_bounds__(kFormThreads) void form_kernel(RomView rom, int32_t n_q, const double* __restrict__ thA,
@@ -219,39 +262,36 @@ __global__ __launch_bounds__(kFormThreads) void form_kernel(RomView rom, int32_t
   const int ntf = rom.moff[i + 1] - g0;               // full n_t,i (leading dimension of K_i)
   const double* Ki = rom.K + rom.koff[i];            // K_i[j', j] at Ki[j * ntf + j']
   OutT* M = mats + plan.mat_off[q];
-  // Each thread owns the columns c = tid + 256 k; their mode and global index stay
-  // in registers while the rows of the mode stream past, kRowUnroll rows at a time.
-  for (int cb = threadIdx.x; cb < w; cb += kColChunk * kFormThreads) {
-    int ic[kColChunk], gc[kColChunk];
-    double ah[kColChunk];
-#pragma unroll
-    for (int k = 0; k < kColChunk; ++k) {
-      const int c = cb + k * kFormThreads;
-      ic[k] = c < w ? L.mmap[c] : -1;
-      gc[k] = c < w ? L.gmap[c] : 0;
-      ah[k] = c < w ? -L.Ah[ic[k]] : 0.0;
-    }
-    for (int j0 = 0; j0 < nti; j0 += kRowUnroll) {
-      double v[kRowUnroll][kColChunk];
-#pragma unroll
-      for (int u = 0; u < kRowUnroll; ++u) {
-        const int j = min(j0 + u, nti - 1);
-        const double* Trow = rom.T + (int64_t)(g0 + j) * n;  // T symmetric: column g0 + j holds row g0 + j
-#pragma unroll
-        for (int k = 0; k < kColChunk; ++k) {
-          double t = ic[k] >= 0 ? Trow[gc[k]] : 0.0;
-          const double kv = ic[k] == i ? Ki[(int64_t)(gc[k] - g0) * ntf + j] : 0.0;
-          v[u][k] = fma(ah[k], t, kv);
-        }
-      }
-#pragma unroll
-      for (int u = 0; u < kRowUnroll; ++u) {
-        if (j0 + u >= nti) break;
-        OutT* Mr = M + (int64_t)(r0 + j0 + u) * w;
-#pragma unroll
-        for (int k = 0; k < kColChunk; ++k)
-          if (ic[k] >= 0) Mr[cb + k * kFormThreads] = (OutT)v[u][k];
-      }
+  // The FP32 assembly reads the FP32 copy of T: its entries are rounded to FP32
+  // anyway, and the FP64 copy's L2 traffic (twice the bytes written) would bound it.
+  typedef typename std::conditional<std::is_same<OutT, float>::value, float, double>::type TT;
+  const TT* tsrc;
+  if constexpr (std::is_same<OutT, float>::value) tsrc = rom.T32;
+  else tsrc = rom.T;
+  // Columns outside the mode's own block: each thread owns the columns c = tid + 256 k,
+  // k < KC; their global index and -Ahat(mu) factor stay in registers while the rows
+  // of the mode stream past.  KC follows the query's width so that few column slots
+  // are empty; the loop is branch-free per element (empty slots and the mode's own
+  // columns read T[., 0] or their T entry and are not stored).
+  const int kc = (w + kFormThreads - 1) / kFormThreads;
+  switch (kc) {
+    case 1: form_columns<OutT, TT, 1>(L, w, threadIdx.x, nti, g0, r0, n, tsrc, M); break;
+    case 2: form_columns<OutT, TT, 2>(L, w, threadIdx.x, nti, g0, r0, n, tsrc, M); break;
+    case 3: form_columns<OutT, TT, 3>(L, w, threadIdx.x, nti, g0, r0, n, tsrc, M); break;
+    case 4: form_columns<OutT, TT, 4>(L, w, threadIdx.x, nti, g0, r0, n, tsrc, M); break;
+    case 5: form_columns<OutT, TT, 5>(L, w, threadIdx.x, nti, g0, r0, n, tsrc, M); break;
+    default:
+      for (int cb = threadIdx.x; cb < w; cb += 4 * kFormThreads)
+        form_columns<OutT, TT, 4>(L, w, cb, nti, g0, r0, n, tsrc, M);
+  }
+  // The mode's own block (rows and columns r0 .. r0 + nti - 1): K_i plus the T term,
+  // one element per thread.
+  {
+    const double ahi = -L.Ah[i];
+    for (int e = threadIdx.x; e < nti * nti; e += kFormThreads) {
+      const int j = e / nti, jj = e % nti;
+      M[(int64_t)(r0 + j) * w + r0 + jj] =
+          (OutT)fma(ahi, (double)tsrc[(int64_t)(g0 + j) * n + g0 + jj], Ki[(int64_t)jj * ntf + j]);
     }
   }
   // right-hand side of these rows

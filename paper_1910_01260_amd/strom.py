@@ -40,7 +40,7 @@ class st_rom_desc(ctypes.Structure):
 
 class st_rom_layout_t(ctypes.Structure):
     _fields_ = [(k, ctypes.c_size_t) for k in ("Ahat", "bhat", "u0hat", "T", "K", "Wf", "P1", "mode", "moff", "koff", "Phit", "dt",
-                                               "total")]
+                                               "T32", "total")]
 
 
 _lib = None
@@ -262,10 +262,11 @@ def st_assemble(desc: RomDesc, Phi_s: torch.Tensor, Phi_t: torch.Tensor, dt: tor
 def rom_section(desc: RomDesc, rom: torch.Tensor, name: str) -> torch.Tensor:
     """View of one FP64 section of a ROM buffer (flat)."""
     lay = st_rom_layout(desc)
-    order = ["Ahat", "bhat", "u0hat", "T", "K", "Wf", "P1", "mode", "moff", "koff", "Phit", "dt", "total"]
+    order = ["Ahat", "bhat", "u0hat", "T", "K", "Wf", "P1", "mode", "moff", "koff", "Phit", "dt", "T32", "total"]
     i = order.index(name)
     b0, b1 = lay[name], lay[order[i + 1]]
-    dtype = {"mode": torch.int32, "moff": torch.int32, "koff": torch.int64}.get(name, torch.float64)
+    dtype = {"mode": torch.int32, "moff": torch.int32, "koff": torch.int64, "T32": torch.float32}.get(name,
+                                                                                                    torch.float64)
     return rom[b0:b1].view(dtype)
 
 

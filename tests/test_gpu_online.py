@@ -130,9 +130,11 @@ def test_form_c2_small(c2s_rom):
 
 
 def test_form_fp32_rounding(cb_rom):
+    """FP32 systems: each entry is computed from the FP32 copy of T and rounded to
+    FP32, so it carries at most two FP32 roundings (2 * 2^-24 of the scale)."""
     prob = C.problem("cb")
     nt = W.ragged_profiles(4, 40, seed=3)
-    _form_and_compare(cb_rom, "cb", W.sample_params(prob, 4, seed=4), nt, out_prec=strom.ST_F32, tol=6e-8)
+    _form_and_compare(cb_rom, "cb", W.sample_params(prob, 4, seed=4), nt, out_prec=strom.ST_F32, tol=2.0 ** -23)
 
 
 def _solve_and_compare(dr, key, mus, nt=None, lu_prec=strom.ST_F64, ir_tol=0.0, ir_max=0, rtol=RTOL):
