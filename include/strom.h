@@ -167,7 +167,11 @@ st_status st_rom_layout(const st_rom_desc* d, st_rom_layout_t* out);
  * of U (error ~ eps sigma_1 / gap) rather than of its Gram (~ eps sigma_1^2
  * / gap^2), down to modes at round-off.  Each temporal snapshot matrix Y_i
  * (N_t x n_mu, Y_i[k,p] = v_i(p N_t + k)) is decomposed by one-sided Jacobi.
- * If U has exact rank r < n_s the trailing columns are zero (sigma = 0).  Temporal bases keep the left singular
+ * If U has exact rank r < n_s the trailing columns are zero (sigma = 0).
+ * The Jacobi runs in one launch when its matrix fits in LDS (rows x k x 8
+ * bytes <= 144 KB); otherwise it takes one launch per round and the host reads
+ * each sweep's rotation count, so st_build_bases then synchronises the stream
+ * once per sweep (it is an offline call and is not graph-captured).  Temporal bases keep the left singular
  * vectors above tau_t and are completed, when n_t[i] exceeds that rank,
  * with DCT-II vectors cos(pi m (k+1/2)/N_t), m = 0,1,..., each orthogonalised
  * twice against the kept vectors and accepted if >= 1e-2 of its norm

@@ -628,6 +628,78 @@ __global__ __launch_bounds__(kTallThreads) void tall_jacobi_round_kernel(double*
   if (threadIdx.x == 0) atomicAdd(&rot[sweep], 1);
 }
 
+// The same one-sided Jacobi in one workgroup with the whole m x k matrix in LDS
+// (all sweeps in one launch): one wave per column pair of a round, a barrier per
+// round, the sweep loop ends once a sweep rotated nothing.  Records rot[] and
+// offmax[] as the per-round kernel does.
+__global__ __launch_bounds__(kOneWG) void tall_jacobi_lds_kernel(double* __restrict__ Ag, int64_t m, int k,
+                                                                  double* __restrict__ J, int max_sweeps,
+                                                                  int* __restrict__ rot,
+                                                                  double* __restrict__ offmax, double tol) {
+  extern __shared__ __align__(16) double As[];
+  __shared__ int s_rot;
+  __shared__ double s_off;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  constexpr int NWV = kOneWG / 64;
+  for (int64_t e = tid; e < m * k; e += kOneWG) As[e] = Ag[e];
+  const int kk = (k + 1) / 2 * 2;
+  for (int sw = 0; sw < max_sweeps; ++sw) {
+    if (tid == 0) {
+      s_rot = 0;
+      s_off = 0.0;
+    }
+    __syncthreads();
+    for (int r = 0; r < kk - 1; ++r) {
+      for (int pr = wave; pr < kk / 2; pr += NWV) {
+        int a, b;
+        tournament_pair(r, pr, kk, a, b);
+        if (a >= k || b >= k) continue;
+        double* x = As + (int64_t)a * m;
+        double* y = As + (int64_t)b * m;
+        double saa = 0.0, sbb = 0.0, sab = 0.0;
+        for (int64_t i = lane; i < m; i += 64) {
+          const double u = x[i], v = y[i];
+          saa = fma(u, u, saa);
+          sbb = fma(v, v, sbb);
+          sab = fma(u, v, sab);
+        }
+        saa = __ockl_wfred_add_f64(saa);
+        sbb = __ockl_wfred_add_f64(sbb);
+        sab = __ockl_wfred_add_f64(sab);
+        const double scale = sqrt(saa) * sqrt(sbb);
+        const double off = scale > 0.0 ? fabs(sab) / scale : 0.0;
+        if (lane == 0) atomic_max_nonneg(&s_off, off);
+        if (!(off > tol)) continue;
+        const double zeta = (sbb - saa) / (2.0 * sab);
+        const double t = copysign(1.0, zeta) / (fabs(zeta) + hypot(1.0, zeta));
+        const double c = 1.0 / sqrt(fma(t, t, 1.0));
+        const double sn = c * t;
+        for (int64_t i = lane; i < m; i += 64) {
+          const double u = x[i], v = y[i];
+          x[i] = c * u - sn * v;
+          y[i] = sn * u + c * v;
+        }
+        if (J)
+          for (int i = lane; i < k; i += 64) {
+            const double u = J[i + (int64_t)a * k], v = J[i + (int64_t)b * k];
+            J[i + (int64_t)a * k] = c * u - sn * v;
+            J[i + (int64_t)b * k] = sn * u + c * v;
+          }
+        if (lane == 0) atomicAdd(&s_rot, 1);
+      }
+      __syncthreads();
+    }
+    const int nrot = s_rot;
+    if (tid == 0) {
+      rot[sw] = nrot;
+      offmax[sw] = s_off;
+    }
+    __syncthreads();
+    if (nrot == 0) break;
+  }
+  for (int64_t e = tid; e < m * k; e += kOneWG) Ag[e] = As[e];
+}
+
 // After the sweeps: column norms (singular values), descending order (ties by
 // index), sigma and the permutation of the leading n_out; diagnostics
 // (accumulated over calls by maximum) diag[1] = sweeps that rotated, diag[2] =
@@ -997,13 +1069,30 @@ hipError_t launch_tall_jacobi(double* A, int64_t m, int k, double* J, int* rot, 
                      max_sweeps);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || k < 2) return e;
+  const size_t lds = sizeof(double) * (size_t)m * k;
+  if (lds <= kOrthMaxLds) {
+    // the whole matrix in LDS: every sweep in one launch
+    if ((e = hipFuncSetAttribute((const void*)tall_jacobi_lds_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)lds)) != hipSuccess)
+      return e;
+    hipLaunchKernelGGL(tall_jacobi_lds_kernel, dim3(1), dim3(kOneWG), lds, s, A, m, k, J, max_sweeps, rot, offmax,
+                       tol);
+    return hipGetLastError();
+  }
+  // one launch per round; after each sweep the host reads the sweep's rotation count
+  // (a stream synchronisation) and stops once a sweep rotated nothing
   const int kk = (k + 1) / 2 * 2;
-  for (int sw = 0; sw < max_sweeps; ++sw)
+  for (int sw = 0; sw < max_sweeps; ++sw) {
     for (int r = 0; r < kk - 1; ++r) {
       hipLaunchKernelGGL(tall_jacobi_round_kernel, dim3(kk / 2), dim3(kTallThreads), 0, s, A, m, k, kk, J, r, sw, rot,
                          offmax, tol);
       if ((e = hipGetLastError()) != hipSuccess) return e;
     }
+    int nrot = 0;
+    if ((e = hipMemcpyAsync(&nrot, rot + sw, sizeof(int), hipMemcpyDeviceToHost, s)) != hipSuccess) return e;
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
+    if (nrot == 0) break;
+  }
   return hipSuccess;
 }
 
