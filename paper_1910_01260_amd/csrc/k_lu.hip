@@ -581,6 +581,7 @@ template <typename T, int NMAX, int NT>
 __device__ __forceinline__ void block_row_solve(T* __restrict__ A, int w, int r0, int n, int c_lo, int c_hi,
                                                 T* __restrict__ Ls, T* __restrict__ pool) {
   constexpr int CW = (64 * 1024) / (sizeof(T) * NMAX) < NT ? (64 * 1024) / (sizeof(T) * NMAX) : NT;
+  static_assert((size_t)NMAX * CW <= lu_pool_elems<T, NT>(), "block-row staging exceeds the pool");
   const int tid = threadIdx.x;
   for (int e = tid; e < n * n; e += NT) {
     const int i = e / n, k = e % n;
@@ -711,6 +712,21 @@ __global__ __launch_bounds__(NT, 2) void lu_kernel(int32_t n_q, Plan plan, T* __
   constexpr int NBO = C::NBO;
   constexpr int BLOCK = NT, NW = NT / 64;
   static_assert(NBO % NBI == 0 && NBI <= 32, "block shape");
+  // Carve-up of the dynamic LDS pool (lu_pool_elems<T, NT>() elements of T), phase by phase;
+  // phases that reuse it are separated by barriers (each helper ends with one).
+  constexpr size_t kPoolBytes = sizeof(T) * lu_pool_elems<T, NT>();
+  // sub-panel pivot bookkeeping: pos_of and row_at, 2 (w - i0) ints with w <= R NT
+  static_assert(2 * (size_t)R * NT * sizeof(int32_t) <= kPoolBytes, "pos_of / row_at exceed the pool");
+  // permute_rows: up to 2 NBO staged row segments of CHW elements, then a position map of w ints
+  static_assert(sizeof(T) * 2 * NBO * C::CHW + sizeof(int32_t) * (size_t)R * NT <= kPoolBytes,
+                "row staging / position map exceed the pool");
+  // tile_update(_flat): the left factor (RB x (NBO + 4)) and two right-factor buffers (CB x (NBO + 4))
+  static_assert(sizeof(T) * (size_t)(C::RB + 2 * C::CB) * (NBO + 4) <= kPoolBytes, "update tiles exceed the pool");
+  // U12: the unit lower block and its inverse (2 NBO x (NBO + 1)), and the per-wave B strips
+  static_assert(sizeof(T) * 2 * (size_t)NBO * (NBO + 1) <= kPoolBytes, "L11 / Linv exceed the pool");
+  static_assert(NBO <= 64 || (size_t)NW * NBO * 16 <= (size_t)NBO * (NBO + 1) ||
+                    sizeof(T) * ((size_t)2 * NBO * (NBO + 1) + (size_t)NW * NBO * 16) <= kPoolBytes,
+                "U12 strips exceed the pool");
   extern __shared__ __align__(16) unsigned char lds_raw[];
   T* pool = reinterpret_cast<T*>(lds_raw);
   __shared__ T s_cand[2][NW][NBI];
@@ -1188,7 +1204,9 @@ int device_cus() {
 }
 
 template <typename T, int R, int NBI, int NT>
-hipError_t lu_go(int32_t n_q, Plan plan, void* mats, int32_t* piv, hipStream_t s) {
+hipError_t lu_go(int32_t n_q, Plan plan, void* mats, int32_t* piv, int32_t n_max, hipStream_t s) {
+  // the R register slots of the NT threads must cover every row of the widest query
+  if (n_max > R * NT) return hipErrorInvalidValue;
   const size_t lds = sizeof(T) * lu_pool_elems<T, NT>();
   if (!g_capturing) {
     const hipError_t e = hipFuncSetAttribute((const void*)lu_kernel<T, R, NBI, NT>,
@@ -1228,15 +1246,15 @@ hipError_t launch_lu(int32_t n_q, Plan plan, int32_t prec, void* mats, int32_t* 
   const bool f64 = prec == ST_F64;
   if (n_max <= 3 * kLuThreads) {
     if (variant == 2)
-      return f64 ? lu_go<double, 6, 8, 256>(n_q, plan, mats, piv, s) : lu_go<float, 6, 16, 256>(n_q, plan, mats, piv, s);
+      return f64 ? lu_go<double, 6, 8, 256>(n_q, plan, mats, piv, n_max, s) : lu_go<float, 6, 16, 256>(n_q, plan, mats, piv, n_max, s);
     if (variant == 1)
-      return f64 ? lu_go<double, 3, 8, 512>(n_q, plan, mats, piv, s) : lu_go<float, 3, 16, 512>(n_q, plan, mats, piv, s);
-    return f64 ? lu_go<double, 3, 16, 512>(n_q, plan, mats, piv, s) : lu_go<float, 3, 32, 512>(n_q, plan, mats, piv, s);
+      return f64 ? lu_go<double, 3, 8, 512>(n_q, plan, mats, piv, n_max, s) : lu_go<float, 3, 16, 512>(n_q, plan, mats, piv, n_max, s);
+    return f64 ? lu_go<double, 3, 16, 512>(n_q, plan, mats, piv, n_max, s) : lu_go<float, 3, 32, 512>(n_q, plan, mats, piv, n_max, s);
   }
   if (n_max <= 8 * kLuThreads) {
     if (variant == 1)
-      return f64 ? lu_go<double, 8, 4, 512>(n_q, plan, mats, piv, s) : lu_go<float, 8, 8, 512>(n_q, plan, mats, piv, s);
-    return f64 ? lu_go<double, 8, 8, 512>(n_q, plan, mats, piv, s) : lu_go<float, 8, 16, 512>(n_q, plan, mats, piv, s);
+      return f64 ? lu_go<double, 8, 4, 512>(n_q, plan, mats, piv, n_max, s) : lu_go<float, 8, 8, 512>(n_q, plan, mats, piv, n_max, s);
+    return f64 ? lu_go<double, 8, 8, 512>(n_q, plan, mats, piv, n_max, s) : lu_go<float, 8, 16, 512>(n_q, plan, mats, piv, n_max, s);
   }
   return hipErrorInvalidValue;
 }
