@@ -21,6 +21,9 @@ rom      spatial Galerkin operators (Sec. 3.1, Eq. (galerkin)), the explicit
          projection (Eq. (st-galerkin)), the block formulas of Sec. 4.3,
          the reduced solve and the spatial-ROM time march.
 bounds   the a-posteriori error bounds of Sec. 5 (Theorems 1-3).
+cn       the Crank-Nicolson variant (the paper's remark that other time
+         integrators give other block structures): full-order march,
+         explicit space-time system and the reduced block formulas.
 mlp      FP64 reference of the surrogate network (forward, hand-derived
          backward, Adam) used for gradient parity.
 

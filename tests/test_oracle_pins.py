@@ -510,3 +510,100 @@ def test_adam_first_step_closed_form():
     mlp.adam_step(p, g, st, lr=0.01)
     np.testing.assert_allclose(p[0][0], [[1.0 - 0.01 * 0.3 / (0.3 + 1e-8), -2.0 + 0.01 * 4.0 / (4.0 + 1e-8)]], rtol=1e-14)
     np.testing.assert_allclose(p[0][1], [0.5 - 0.01 * 1e-9 / (1e-9 + 1e-8)], rtol=1e-12)
+
+
+# ----------------------------------------------------------------------------
+# Crank-Nicolson variant (the paper's remark on other time integrators, Sec. 2)
+# ----------------------------------------------------------------------------
+
+def test_cn_golden_scalar_two_step():
+    """Hand-derived 2-step scalar Crank-Nicolson ST-ROM (tests/golden/scalar_two_step_cn.json)."""
+    from oracle import cn
+    g = json.load(open(os.path.join(GOLDEN, "scalar_two_step_cn.json")))
+    A = np.array([[g["system"]["A"]]])
+    dt = np.array(g["system"]["dt"])
+    Phi_s = np.array(g["basis"]["Phi_s"])
+    Phi_t = [np.array(g["basis"]["Phi_t"])]
+    u0 = np.array([g["system"]["u0"]])
+    M = cn.block_operator(rom.spatial_operator(Phi_s, A), Phi_t, dt)
+    rhs = cn.initial_vector(Phi_s.T @ u0, Phi_s.T @ (A @ u0), Phi_t, dt)
+    np.testing.assert_allclose(M, g["Ahat_st"], rtol=0, atol=1e-15)
+    np.testing.assert_allclose(rhs, g["rhs"], rtol=0, atol=1e-15)
+    c = rom.solve(M, rhs)
+    np.testing.assert_allclose(c, g["c_hat"], rtol=1e-14)
+    np.testing.assert_allclose(rom.reconstruct(Phi_s, Phi_t, c)[0], g["trajectory"], rtol=1e-14)
+    np.testing.assert_allclose(cn.crank_nicolson(A, np.zeros((1, 2)), u0, dt)[0], g["trajectory"], rtol=1e-15)
+
+
+def test_cn_scalar_closed_form():
+    """Trapezoidal rule on u' = -lam u + b: u^(k) = r u^(k-1) + dt b / (1 + lam dt / 2),
+    r = (1 - lam dt/2) / (1 + lam dt/2); the full-order march and the complete-basis
+    Crank-Nicolson ST-ROM both reproduce it."""
+    from oracle import cn
+    lam, b, u0, dt, Nt = 3.0, 0.7, 2.0, 0.1, 7
+    r = (1 - lam * dt / 2) / (1 + lam * dt / 2)
+    exact, u = [], u0
+    for _ in range(Nt):
+        u = r * u + dt * b / (1 + lam * dt / 2)
+        exact.append(u)
+    A = np.array([[-lam]])
+    F = np.full((1, Nt), b)
+    dts = np.full(Nt, dt)
+    np.testing.assert_allclose(cn.crank_nicolson(A, F, [u0], dts)[0], exact, rtol=1e-14)
+    Phi_t = [np.linalg.qr(np.random.default_rng(1).standard_normal((Nt, Nt)))[0]]
+    Phi_s = np.eye(1)
+    M = cn.block_operator(A, Phi_t, dts)
+    rhs = cn.input_vector(F, Phi_t, dts) + cn.initial_vector(np.array([u0]), A @ np.array([u0]), Phi_t, dts)
+    c = rom.solve(M, rhs)
+    np.testing.assert_allclose(rom.reconstruct(Phi_s, Phi_t, c)[0], exact, rtol=1e-12)
+
+
+@pytest.mark.parametrize("problem", ["advdiff", "transport"])
+def test_cn_block_formulas_equal_bruteforce(problem):
+    """The Crank-Nicolson block operator, input and initial vectors equal the explicit
+    projection Phi_st^T A_st Phi_st, Phi_st^T f_st, Phi_st^T u0_st (ragged, mode-major)."""
+    from oracle import cn
+    prob = _tiny_advdiff() if problem == "advdiff" else _tiny_transport()
+    U, Phi_s, s, V, Phi_t, _ = _bases(prob, 4, [4, 3, 2, 2])
+    mu = W.sample_params(prob, 1, seed=17)[0]
+    A = prob.operator(mu)
+    F = prob.forcing(mu)
+    u0 = prob.initial(mu)
+    A_st, f_st, u0_st = cn.space_time_system(A, F, u0, prob.dt)
+    Phi_st = rom.spacetime_basis(Phi_s, Phi_t, order="mode")
+    Ab, fb, ub = rom.project_space_time(Phi_st, A_st, f_st, u0_st)
+    M = cn.block_operator(rom.spatial_operator(Phi_s, A), Phi_t, prob.dt)
+    np.testing.assert_allclose(M, Ab, atol=1e-12 * np.abs(Ab).max())
+    np.testing.assert_allclose(cn.input_vector(Phi_s.T @ F, Phi_t, prob.dt), fb, atol=1e-14 + 1e-12 * np.abs(fb).max())
+    np.testing.assert_allclose(cn.initial_vector(Phi_s.T @ u0, Phi_s.T @ (A @ u0), Phi_t, prob.dt), ub,
+                               atol=1e-14 + 1e-12 * np.abs(ub).max())
+    # the affine assembly of the same system
+    tA, tf, t0 = prob.thetas(mu)
+    Ahat_q = [rom.spatial_operator(Phi_s, Aq) for Aq in prob.terms]
+    bhat = Phi_s.T @ prob.Bf if prob.Qf else np.zeros((4, 0))
+    u0hat = Phi_s.T @ prob.u0 if prob.Q0 else np.zeros((4, 0))
+    Au0hat = [Phi_s.T @ (Aq @ prob.u0) if prob.Q0 else np.zeros((4, 0)) for Aq in prob.terms]
+    M2, rhs2 = cn.reduced_system(Ahat_q, tA[0], bhat, tf[0], prob.g, u0hat, Au0hat, t0[0], Phi_t, prob.dt)
+    np.testing.assert_allclose(M2, Ab, atol=1e-12 * np.abs(Ab).max())
+    np.testing.assert_allclose(rhs2, fb + ub, atol=1e-14 + 1e-12 * np.abs(fb + ub).max())
+
+
+@pytest.mark.parametrize("problem", ["advdiff", "transport"])
+def test_cn_complete_bases_reproduce_fom(problem):
+    """Complete spatial and temporal bases: the Crank-Nicolson ST-ROM solution is the
+    Crank-Nicolson full-order trajectory."""
+    from oracle import cn
+    prob = _tiny_advdiff(N=12, N_t=6) if problem == "advdiff" else _tiny_transport(nx=2, ndir=4, N_t=5)
+    N = prob.N_s
+    rng = np.random.default_rng(18)
+    Phi_s = np.linalg.qr(rng.standard_normal((N, N)))[0]
+    Phi_t = [np.linalg.qr(rng.standard_normal((prob.N_t, prob.N_t)))[0] for _ in range(N)]
+    mu = W.sample_params(prob, 1, seed=19)[0]
+    A = prob.operator(mu)
+    M = cn.block_operator(rom.spatial_operator(Phi_s, A), Phi_t, prob.dt)
+    u0 = prob.initial(mu)
+    rhs = cn.input_vector(Phi_s.T @ prob.forcing(mu), Phi_t, prob.dt) + \
+        cn.initial_vector(Phi_s.T @ u0, Phi_s.T @ (A @ u0), Phi_t, prob.dt)
+    c = rom.solve(M, rhs)
+    Ut = cn.crank_nicolson(A, prob.forcing(mu), u0, prob.dt)
+    np.testing.assert_allclose(rom.reconstruct(Phi_s, Phi_t, c), Ut, atol=1e-11 * np.abs(Ut).max())
