@@ -577,6 +577,14 @@ def test_cn_block_formulas_equal_bruteforce(problem):
     np.testing.assert_allclose(cn.input_vector(Phi_s.T @ F, Phi_t, prob.dt), fb, atol=1e-14 + 1e-12 * np.abs(fb).max())
     np.testing.assert_allclose(cn.initial_vector(Phi_s.T @ u0, Phi_s.T @ (A @ u0), Phi_t, prob.dt), ub,
                                atol=1e-14 + 1e-12 * np.abs(ub).max())
+    # variable steps: the shifted contraction carries the step of its later time level
+    dtv = prob.dt * (1.0 + np.random.default_rng(20).random(prob.N_t))
+    A_st, f_st, u0_st = cn.space_time_system(A, F, u0, dtv)
+    Ab2, fb2, ub2 = rom.project_space_time(Phi_st, A_st, f_st, u0_st)
+    np.testing.assert_allclose(cn.block_operator(rom.spatial_operator(Phi_s, A), Phi_t, dtv), Ab2,
+                               atol=1e-12 * np.abs(Ab2).max())
+    np.testing.assert_allclose(cn.initial_vector(Phi_s.T @ u0, Phi_s.T @ (A @ u0), Phi_t, dtv), ub2,
+                               atol=1e-14 + 1e-12 * np.abs(ub2).max())
     # the affine assembly of the same system
     tA, tf, t0 = prob.thetas(mu)
     Ahat_q = [rom.spatial_operator(Phi_s, Aq) for Aq in prob.terms]
