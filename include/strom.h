@@ -104,8 +104,18 @@ typedef struct {
  *   Q0     number of initial-state terms u0 = sum_q theta_0[q] u0_q    (>= 0)
  *   n_t    [host] n_s entries: temporal basis size of each mode (1..N_t);
  *          queries may use any prefix of each mode's basis.
+ *   integrator  ST_BACKWARD_EULER (the paper's, Sec. 2 Eq. (fom)) or
+ *          ST_CRANK_NICOLSON: (I - dt_k/2 A) u^(k) = (I + dt_k/2 A) u^(k-1)
+ *          + dt_k B f^(k), the other block structure Sec. 2 mentions.  The
+ *          reduced operator then uses T_cn = (T + S)/2 with
+ *          S[a,b] = sum_{k>1} dt_k phi_a(k) phi_b(k-1) in place of T, and the
+ *          initial vector phi_a(1) (Phi_s^T (I + dt_1/2 A(mu)) u0)_i.  The input
+ *          g[k] is the input of step k (for a time-varying input under
+ *          Crank-Nicolson, the average of its values at the step's two ends).
  * n = sum_i n_t[i] is the full reduced dimension.
  * ---------------------------------------------------------------------- */
+#define ST_BACKWARD_EULER 0
+#define ST_CRANK_NICOLSON 1
 typedef struct {
   int32_t n_s;
   int32_t N_t;
@@ -113,6 +123,7 @@ typedef struct {
   int32_t Qf;
   int32_t Q0;
   const int32_t* n_t;
+  int32_t integrator;
 } st_rom_desc;
 
 /* Byte offsets of the sections of a ROM buffer (filled by st_rom_layout).
@@ -130,11 +141,13 @@ typedef struct {
  *   koff   n_s + 1 (int64)   element offsets of each K_i inside K
  *   Phit   N_t x n           the concatenated temporal bases, column-major (Phit[k + N_t a] = phi_a(k))
  *   dt     N_t               the time steps
- *   T32    n x n (FP32)      T rounded to FP32 (read by the FP32 assembly)
+ *   T32    n x n (FP32)      the assembly's T (T, or T_cn) rounded to FP32, row-major
+ *   Tcn    n x n             Crank-Nicolson only: T_cn = (T + S)/2, row-major
+ *   Au0    Q x Q0 x n_s      Crank-Nicolson only: Phi_s^T A_q u0_q0
  * where phi_a is column a of the concatenated temporal bases (mode-major).
  */
 typedef struct {
-  size_t Ahat, bhat, u0hat, T, K, Wf, P1, mode, moff, koff, Phit, dt, T32, total;
+  size_t Ahat, bhat, u0hat, T, K, Wf, P1, mode, moff, koff, Phit, dt, T32, Tcn, Au0, total;
 } st_rom_layout_t;
 
 st_status st_rom_layout(const st_rom_desc* d, st_rom_layout_t* out);
@@ -434,7 +447,8 @@ st_status st_certify(const st_rom_desc* d, const void* rom, int32_t n_q, const d
  *           1 / st_coercivity_floor(N_t), valid whenever sym(A(mu)) <= 0.
  * Outputs [dev] n_q doubles each: res_inf = ||r_st||_inf, u_inf =
  * ||u~_st||_inf, bound = sqrt(N_t) inv_norm res_inf (NaN for invalid queries).
- * Limits: n_s <= 128 and (33 n_s + 32 (n_s (Q+1) + Qf + Q0)) 8 bytes <= 160 KB.
+ * Limits: n_s <= 128 and (33 n_s + 32 (n_s (Q+1) + Qf + Q0)) 8 bytes <= 160 KB;
+ * backward Euler only (ST_EUNSUPPORTED for a Crank-Nicolson model).
  * ====================================================================== */
 size_t st_fom_bound_workspace(const st_rom_desc* d, int64_t N_s, int32_t n_q);
 st_status st_fom_bound(const st_rom_desc* d, const void* rom, int64_t N_s, const double* Phi_s, const st_csr* A,
@@ -462,7 +476,8 @@ st_status st_fom_bound(const st_rom_desc* d, const void* rom, int64_t N_s, const
  *          I - dt_k Ahat(mu) is singular (its entries are then NaN).
  * Each query factors I - dt Ahat(mu) once per distinct step size (an explicit
  * inverse by Gauss-Jordan elimination with partial pivoting, FP64), then
- * marches.  n_s <= 128 and (n_s^2 + (3 + Qf) n_s) 8 bytes <= 160 KB.
+ * marches.  n_s <= 128 and (n_s^2 + (3 + Qf) n_s) 8 bytes <= 160 KB; backward
+ * Euler only (ST_EUNSUPPORTED for a Crank-Nicolson model).
  *
  * st_project: out (n_s x k, ld n_s) = Phi_s^T X, X N_s x k (ld N_s), FP64,
  * e.g. Chat = Phi_s^T C (Eq. (galerkin)).

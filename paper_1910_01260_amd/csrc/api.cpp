@@ -25,6 +25,7 @@ bool desc_ok(const st_rom_desc* d) {
   if (!d || !d->n_t) return false;
   if (d->n_s < 1 || d->n_s > kMaxModes || d->N_t < 1) return false;
   if (d->Q < 1 || d->Q > kMaxTerms || d->Qf < 0 || d->Qf > kMaxTerms || d->Q0 < 0 || d->Q0 > kMaxTerms) return false;
+  if (d->integrator != ST_BACKWARD_EULER && d->integrator != ST_CRANK_NICOLSON) return false;
   for (int i = 0; i < d->n_s; ++i)
     if (d->n_t[i] < 1 || d->n_t[i] > d->N_t) return false;
   return true;
@@ -48,6 +49,9 @@ void layout_of(const st_rom_desc* d, st_rom_layout_t* L) {
   L->Phit = o;  o = align_up(o + sizeof(double) * d->N_t * n);
   L->dt = o;    o = align_up(o + sizeof(double) * d->N_t);
   L->T32 = o;   o = align_up(o + sizeof(float) * n * n);
+  const bool cn = d->integrator == ST_CRANK_NICOLSON;
+  L->Tcn = o;   o = align_up(o + (cn ? sizeof(double) * n * n : 0));
+  L->Au0 = o;   o = align_up(o + (cn ? sizeof(double) * d->Q * d->Q0 * n_s : 0));
   L->total = o;
 }
 
@@ -69,6 +73,9 @@ RomView view_of(const st_rom_desc* d, const void* rom) {
   v.Phit = reinterpret_cast<const double*>(b + L.Phit);
   v.dt = reinterpret_cast<const double*>(b + L.dt);
   v.T32 = reinterpret_cast<const float*>(b + L.T32);
+  v.integ = d->integrator;
+  v.Teff = d->integrator == ST_CRANK_NICOLSON ? reinterpret_cast<const double*>(b + L.Tcn) : v.T;
+  v.Au0 = reinterpret_cast<const double*>(b + L.Au0);
   v.n_s = d->n_s;
   v.N_t = d->N_t;
   v.n = (int32_t)total_nt(d);
@@ -145,7 +152,13 @@ size_t st_assemble_workspace(const st_rom_desc* d, int64_t N_s) {
   part = part > tsgemm_partial_elems(N_s, d->n_s, d->Q0) ? part : tsgemm_partial_elems(N_s, d->n_s, d->Q0);
   part = part > tsgemm_partial_elems(d->N_t, (int32_t)n, (int32_t)n) ? part
                                                                       : tsgemm_partial_elems(d->N_t, (int32_t)n, (int32_t)n);
-  const size_t fp64 = align_up(sizeof(double) * (size_t)N_s * d->n_s) * 2 + align_up(sizeof(double) * part);
+  if (d->integrator == ST_CRANK_NICOLSON) {
+    // the shifted contraction S (n x n) and its partials share the partial area
+    const size_t cn = (size_t)n * n + tsgemm_partial_elems(d->N_t > 1 ? d->N_t - 1 : 1, (int32_t)n, (int32_t)n);
+    part = part > cn ? part : cn;
+  }
+  const size_t fp64 = align_up(sizeof(double) * (size_t)N_s * d->n_s) * 2 +
+                      align_up(sizeof(double) * (size_t)N_s * d->Q0) * 2 + align_up(sizeof(double) * part);
   // reduced-precision projection: Z (N_s x 2 n_s FP32), its Gram and the Gram's partials
   const int32_t p2 = 2 * d->n_s;
   const size_t red = align_up(sizeof(float) * (size_t)N_s * p2) + align_up(sizeof(double) * (size_t)p2 * p2) +
@@ -188,10 +201,14 @@ st_status st_assemble(const st_rom_desc* d, int64_t N_s, const double* Phi_s, co
   mv.Phit = reinterpret_cast<double*>(rb + L.Phit);
   mv.dt = reinterpret_cast<double*>(rb + L.dt);
   mv.T32 = reinterpret_cast<float*>(rb + L.T32);
+  mv.Tcn = reinterpret_cast<double*>(rb + L.Tcn);
+  mv.Au0 = reinterpret_cast<double*>(rb + L.Au0);
 
   Carver c(ws);
   double* Phir = c.take<double>((size_t)N_s * d->n_s);
   double* Y = c.take<double>((size_t)N_s * d->n_s);
+  double* u0r = c.take<double>((size_t)N_s * d->Q0);  // Crank-Nicolson: u0 terms, row-major
+  double* Yu = c.take<double>((size_t)N_s * d->Q0);   //                 A_q u0 terms
   double* part = reinterpret_cast<double*>(c.base + c.used);
   const size_t part_elems = (ws_bytes - c.used) / sizeof(double);
 
@@ -233,7 +250,32 @@ st_status st_assemble(const st_rom_desc* d, int64_t N_s, const double* Phi_s, co
   ST_TRY(launch_tsgemm_w(d->N_t, (int32_t)n, (int32_t)n, Phi_t, 1, d->N_t, Phi_t, 1, d->N_t, dt, mv.T, (int32_t)n, part,
                          part_elems, s));
   ST_TRY(launch_temporal(Phi_t, d->N_t, (int32_t)n, dt, g, d->Qf, mt, mv, s));
-  ST_TRY(launch_round_f32(mv.T, (int64_t)n * n, mv.T32, s));
+  if (d->integrator == ST_CRANK_NICOLSON) {
+    // S[a,b] = sum_{k>1} dt_k phi_a(k) phi_b(k-1) (column-major, in the workspace),
+    // then T_cn = (T + S)/2, row-major, and its FP32 copy
+    const size_t nn = (size_t)n * n;
+    double* Sc = part;
+    double* part2 = part + nn;
+    const size_t part2_elems = part_elems - nn;
+    if (d->N_t > 1)
+      ST_TRY(launch_tsgemm_w(d->N_t - 1, (int32_t)n, (int32_t)n, Phi_t + 1, 1, d->N_t, Phi_t, 1, d->N_t, dt + 1, Sc,
+                             (int32_t)n, part2, part2_elems, s));
+    else
+      ST_TRY(launch_fill_f64(Sc, (int64_t)nn, 0.0, s));
+    ST_TRY(launch_combine_cn(mv.T, Sc, (int32_t)n, mv.Tcn, s));
+    ST_TRY(launch_round_f32(mv.Tcn, (int64_t)nn, mv.T32, s));
+    // Phi_s^T A_q u0_q0: the initial terms through each operator term
+    if (d->Q0 > 0) {
+      ST_TRY(launch_transpose(u0, N_s, d->Q0, N_s, u0r, s));
+      for (int q = 0; q < d->Q; ++q) {
+        ST_TRY(launch_spmm_rowmajor(A[q], u0r, d->Q0, Yu, s));
+        ST_TRY(launch_tsgemm(N_s, ns, d->Q0, Phir, ns, 1, Yu, d->Q0, 1, mv.Au0 + (size_t)q * d->Q0 * ns, ns, part,
+                             part_elems, s));
+      }
+    }
+  } else {
+    ST_TRY(launch_round_f32(mv.T, (int64_t)n * n, mv.T32, s));
+  }
   // the bases and steps themselves, for the residual evaluated on the time grid
   ST_TRY(launch_copy_cols(Phi_t, d->N_t, mv.Phit, d->N_t, d->N_t, (int)n, s));
   ST_TRY(launch_copy_cols(dt, d->N_t, mv.dt, d->N_t, d->N_t, 1, s));
@@ -486,6 +528,7 @@ std::vector<uint64_t> graph_key(const SolveArgs& a, int device) {
   put((uint64_t)device);
   put((uint64_t)a.d->n_s); put((uint64_t)a.d->N_t); put((uint64_t)a.d->Q); put((uint64_t)a.d->Qf);
   put((uint64_t)a.d->Q0);
+  put((uint64_t)a.d->integrator);
   for (int i = 0; i < a.d->n_s; ++i) put((uint64_t)a.d->n_t[i]);
   ptr(a.rom); put((uint64_t)a.n_q); ptr(a.thA); ptr(a.thf); ptr(a.th0); ptr(a.nt_q); ptr(a.skip);
   put((uint64_t)a.lu_prec);
@@ -1007,7 +1050,7 @@ st_status st_surrogate_check(const st_rom_desc* d, const void* rom, int32_t n_q,
   ST_TRY(launch_plan(n_q, d->n_s, rv.moff, nullptr, nullptr, theta_A, theta_f, theta_0, d->Q, d->Qf, d->Q0,
                      (int64_t)n_q * n, (int64_t)1 << 62, plan, s));
   ST_TRY(launch_destandardize(n_q, (int32_t)n, Y, mean, scale, plan, coeff, s));
-  ST_TRY(launch_rhs(rv, n_q, theta_f, theta_0, nullptr, plan, b, (int32_t)n, s));
+  ST_TRY(launch_rhs(rv, n_q, theta_A, theta_f, theta_0, nullptr, plan, b, (int32_t)n, s));
   ST_TRY(launch_residual(rv, n_q, theta_A, nullptr, plan, b, coeff, r, rnorm, nullptr, (int32_t)n, s));
   ST_TRY(launch_vec_norms(n_q, plan, coeff, cnorm, s));
   ST_TRY(launch_certificate(n_q, plan, rnorm, cnorm, gamma, tol, cert, accept, nullptr, nullptr, s));
@@ -1061,7 +1104,7 @@ st_status st_fom_bound(const st_rom_desc* d, const void* rom, int64_t N_s, const
     if (A[q].n_rows != N_s || A[q].nnz < 0 || !A[q].row_ptr) return ST_EINVAL;
     if (A[q].nnz > 0 && (!A[q].col_idx || !A[q].val)) return ST_EINVAL;
   }
-  if (d->n_s > kMaxFormModes) return ST_EUNSUPPORTED;
+  if (d->n_s > kMaxFormModes || d->integrator != ST_BACKWARD_EULER) return ST_EUNSUPPORTED;
   if (fom_bound_lds_bytes(d->n_s, dict_cols(d)) > 160 * 1024) return ST_EUNSUPPORTED;
   if (n_q == 0) return ST_OK;
   if (!coeff || !res_inf || !u_inf || !bound || !ws) return ST_EINVAL;
@@ -1094,6 +1137,7 @@ st_status st_spatial_march(const st_rom_desc* d, const void* rom, int32_t n_q, c
                            const double* Chat, double* traj, double* outputs, int32_t* info, void* stream) {
   if (!query_args_ok(d, rom, n_q, theta_A, theta_f, theta_0) || n_out < 0) return ST_EINVAL;
   if (d->n_s > kMaxFormModes || spatial_march_lds_bytes(d->n_s, d->Qf) > 160 * 1024) return ST_EUNSUPPORTED;
+  if (d->integrator != ST_BACKWARD_EULER) return ST_EUNSUPPORTED;
   if (n_q == 0) return ST_OK;
   if (!info || (outputs && (n_out < 1 || !Chat))) return ST_EINVAL;
   ST_TRY(launch_spatial_march(view_of(d, rom), n_q, theta_A, theta_f, theta_0, g, outputs ? n_out : 0, Chat, traj,
@@ -1146,7 +1190,7 @@ st_status st_certify(const st_rom_desc* d, const void* rom, int32_t n_q, const d
   double* r = c.take<double>(coeff_cap);
   ST_TRY(launch_plan(n_q, d->n_s, rv.moff, nt_q, nullptr, theta_A, theta_f, theta_0, d->Q, d->Qf, d->Q0, coeff_cap,
                      (int64_t)1 << 62, plan, s));
-  ST_TRY(launch_rhs(rv, n_q, theta_f, theta_0, nt_q, plan, b, (int32_t)n, s));
+  ST_TRY(launch_rhs(rv, n_q, theta_A, theta_f, theta_0, nt_q, plan, b, (int32_t)n, s));
   ST_TRY(launch_residual(rv, n_q, theta_A, nt_q, plan, b, coeff, r, rnorm, nullptr, (int32_t)n, s));
   ST_TRY(launch_vec_norms(n_q, plan, coeff, cnorm, s));
   ST_TRY(launch_vec_norms(n_q, plan, b, bnorm, s));

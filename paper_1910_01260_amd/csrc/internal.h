@@ -34,8 +34,11 @@ struct RomView {
   const int64_t* koff;  // n_s + 1
   const double* Phit;   // N_t x n, column-major (the concatenated temporal bases)
   const double* dt;     // N_t
-  const float* T32;     // n x n, T rounded to FP32 (read by the FP32 assembly)
+  const float* T32;     // n x n, the assembly's T rounded to FP32, row-major
+  const double* Teff;   // n x n read as row-major: T (symmetric) or, Crank-Nicolson, T_cn
+  const double* Au0;    // Q x Q0 x n_s (Crank-Nicolson): Phi_s^T A_q u0_q0
   int32_t n_s, N_t, n, Q, Qf, Q0;
+  int32_t integ;        // ST_BACKWARD_EULER or ST_CRANK_NICOLSON
 };
 
 struct MutRomView {
@@ -44,6 +47,7 @@ struct MutRomView {
   int64_t* koff;
   double *Phit, *dt;
   float* T32;
+  double *Tcn, *Au0;
 };
 
 inline size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
@@ -84,6 +88,8 @@ hipError_t launch_spmm_f32(const st_csr& A, int32_t p, float* Z, hipStream_t s);
 hipError_t launch_extract_block(const double* G, int32_t p, double* Ahat, hipStream_t s);
 hipError_t launch_mode_offsets(const ModeTable& mt, int32_t* moff, hipStream_t s);
 hipError_t launch_round_f32(const double* src, int64_t n, float* dst, hipStream_t s);
+// T_cn (row-major) = (T + S)/2 from column-major T and S (n x n)
+hipError_t launch_combine_cn(const double* T, const double* S, int32_t n, double* Tcn, hipStream_t s);
 hipError_t launch_temporal(const double* Phi_t, int32_t N_t, int32_t n, const double* dt, const double* g, int32_t Qf,
                            const ModeTable& mt, MutRomView rom, hipStream_t s);
 
@@ -116,7 +122,8 @@ hipError_t launch_temporal_svd(const double* V, int64_t ldV, int N_t, int n_mu, 
 hipError_t launch_plan(int32_t n_q, int32_t n_s, const int32_t* full_nt_dev, const int32_t* nt_q, const int32_t* skip,
                        const double* thA, const double* thf, const double* th0, int32_t Q, int32_t Qf, int32_t Q0,
                        int64_t coeff_cap, int64_t mat_cap, Plan plan, hipStream_t s);
-hipError_t launch_rhs(const RomView& rom, int32_t n_q, const double* thf, const double* th0, const int32_t* nt_q,
+hipError_t launch_rhs(const RomView& rom, int32_t n_q, const double* thA, const double* thf, const double* th0,
+                      const int32_t* nt_q,
                       Plan plan, double* rhs, int32_t n_max, hipStream_t s);
 hipError_t launch_destandardize(int32_t n_q, int32_t n, const float* Y, const double* mean, const double* scale,
                                 Plan plan, double* coeff, hipStream_t s);
@@ -168,6 +175,7 @@ hipError_t launch_ir_check(int32_t n_q, Plan plan, const double* rnorm, const do
 hipError_t launch_vec_norms(int32_t n_q, Plan plan, const double* v, double* norms, hipStream_t s);
 hipError_t launch_finalize(int32_t n_q, Plan plan, double* coeff, int32_t* info_out, hipStream_t s);
 hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
+hipError_t launch_fill_f64(double* p, int64_t n, double v, hipStream_t s);
 // FP64 re-solve of queries whose FP32 refinement did not converge (info -1 -> -6)
 hipError_t launch_fallback_plan(int32_t n_q, Plan plan, Plan fb, int32_t* active, int64_t mat_cap, hipStream_t s);
 hipError_t launch_fallback_finish(int32_t n_q, Plan plan, Plan fb, const int32_t* active, hipStream_t s);

@@ -272,6 +272,21 @@ __global__ void round_f32_kernel(const double* __restrict__ src, int64_t n, floa
   if (e < n) dst[e] = (float)src[e];
 }
 
+__global__ void combine_cn_kernel(const double* __restrict__ T, const double* __restrict__ S, int32_t n,
+                                  double* __restrict__ Tcn) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)n * n) return;
+  const int64_t a = e / n, b = e % n;  // row-major destination, column-major sources
+  Tcn[e] = 0.5 * (T[a + b * n] + S[a + b * n]);
+}
+
+hipError_t launch_combine_cn(const double* T, const double* S, int32_t n, double* Tcn, hipStream_t s) {
+  const int64_t e = (int64_t)n * n;
+  if (e == 0) return hipSuccess;
+  hipLaunchKernelGGL(combine_cn_kernel, dim3((unsigned)((e + 255) / 256)), dim3(256), 0, s, T, S, n, Tcn);
+  return hipGetLastError();
+}
+
 hipError_t launch_round_f32(const double* src, int64_t n, float* dst, hipStream_t s) {
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(round_f32_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, src, n, dst);

@@ -20,6 +20,24 @@ constexpr int kColChunk = 4;      // columns per thread in flight in the form ke
 
 __device__ inline bool finite_d(double v) { return v == v && v - v == 0.0; }
 
+// Coefficient of P1[a] in the right-hand side for spatial mode i of query q: the
+// reduced initial state (Phi_s^T u0)_i, and under Crank-Nicolson the first step's
+// explicit half, (Phi_s^T (I + dt_1/2 A(mu)) u0)_i.
+__device__ inline double initial_coef(const RomView& rom, const double* __restrict__ thA,
+                                      const double* __restrict__ th0, int32_t q, int i) {
+  double u0 = 0.0;
+  for (int k = 0; k < rom.Q0; ++k) u0 = fma(th0[(int64_t)q * rom.Q0 + k], rom.u0hat[(int64_t)k * rom.n_s + i], u0);
+  if (rom.integ == ST_CRANK_NICOLSON && rom.Q0 > 0) {
+    double au = 0.0;
+    for (int t = 0; t < rom.Q; ++t)
+      for (int k = 0; k < rom.Q0; ++k)
+        au = fma(thA[(int64_t)q * rom.Q + t] * th0[(int64_t)q * rom.Q0 + k],
+                 rom.Au0[((int64_t)t * rom.Q0 + k) * rom.n_s + i], au);
+    u0 = fma(0.5 * rom.dt[0], au, u0);
+  }
+  return u0;
+}
+
 // wavefront sum of the device library (DPP based, all lanes active)
 extern "C" __device__ double __ockl_wfred_add_f64(double);
 
@@ -267,7 +285,7 @@ __global__ __launch_bounds__(kFormThreads) void form_kernel(RomView rom, int32_t
   typedef typename std::conditional<std::is_same<OutT, float>::value, float, double>::type TT;
   const TT* tsrc;
   if constexpr (std::is_same<OutT, float>::value) tsrc = rom.T32;
-  else tsrc = rom.T;
+  else tsrc = rom.Teff;
   // Columns outside the mode's own block: each thread owns the columns c = tid + 256 k,
   // k < KC; their global index and -Ahat(mu) factor stay in registers while the rows
   // of the mode stream past.  KC follows the query's width so that few column slots
@@ -300,8 +318,7 @@ __global__ __launch_bounds__(kFormThreads) void form_kernel(RomView rom, int32_t
     double b = 0.0;
     for (int k = 0; k < rom.Qf; ++k)
       b = fma(thf[(int64_t)q * rom.Qf + k] * rom.Wf[(int64_t)k * n + g], rom.bhat[(int64_t)k * rom.n_s + i], b);
-    double u0 = 0.0;
-    for (int k = 0; k < rom.Q0; ++k) u0 = fma(th0[(int64_t)q * rom.Q0 + k], rom.u0hat[(int64_t)k * rom.n_s + i], u0);
+    const double u0 = initial_coef(rom, thA, th0, q, i);
     rhs[plan.coeff_off[q] + r0 + j] = fma(rom.P1[g], u0, b);
   }
 }
@@ -354,7 +371,7 @@ __global__ __launch_bounds__(kFormThreads) void residual_kernel(RomView rom, int
 #pragma unroll
       for (int rr = 0; rr < kResRows; ++rr) {
         const int j = jb + min(rr, nrow - 1);
-        const double* Trow = rom.T + (int64_t)(g0 + j) * n;
+        const double* Trow = rom.Teff + (int64_t)(g0 + j) * n;  // row g0 + j of T (or T_cn)
         double sum = 0.0;
 #pragma unroll
         for (int k = 0; k < kColChunk; ++k) {
@@ -486,8 +503,9 @@ __global__ void finalize_kernel(int32_t n_q, Plan plan, double* __restrict__ coe
 }
 
 // right-hand side only (see form_kernel), one thread per reduced index of a query
-__global__ __launch_bounds__(256) void rhs_kernel(RomView rom, int32_t n_q, const double* __restrict__ thf,
-                                                  const double* __restrict__ th0, Plan plan, double* __restrict__ rhs) {
+__global__ __launch_bounds__(256) void rhs_kernel(RomView rom, int32_t n_q, const double* __restrict__ thA,
+                                                  const double* __restrict__ thf, const double* __restrict__ th0,
+                                                  Plan plan, double* __restrict__ rhs) {
   const int32_t q = blockIdx.y;
   if (plan.info[q] != 0) return;
   const int32_t w = plan.width[q];
@@ -497,14 +515,14 @@ __global__ __launch_bounds__(256) void rhs_kernel(RomView rom, int32_t n_q, cons
   double b = 0.0;
   for (int k = 0; k < rom.Qf; ++k)
     b = fma(thf[(int64_t)q * rom.Qf + k] * rom.Wf[(int64_t)k * rom.n + a], rom.bhat[(int64_t)k * rom.n_s + i], b);
-  double u0 = 0.0;
-  for (int k = 0; k < rom.Q0; ++k) u0 = fma(th0[(int64_t)q * rom.Q0 + k], rom.u0hat[(int64_t)k * rom.n_s + i], u0);
+  const double u0 = initial_coef(rom, thA, th0, q, i);
   rhs[plan.coeff_off[q] + a] = fma(rom.P1[a], u0, b);
 }
 
 // right-hand side of queries with per-mode prefixes: one workgroup per (mode,
 // query); mode i's local block starts at the sum of the query's earlier prefixes
-__global__ __launch_bounds__(256) void rhs_prefix_kernel(RomView rom, int32_t n_q, const double* __restrict__ thf,
+__global__ __launch_bounds__(256) void rhs_prefix_kernel(RomView rom, int32_t n_q, const double* __restrict__ thA,
+                                                         const double* __restrict__ thf,
                                                          const double* __restrict__ th0,
                                                          const int32_t* __restrict__ nt_q, Plan plan,
                                                          double* __restrict__ rhs) {
@@ -513,8 +531,7 @@ __global__ __launch_bounds__(256) void rhs_prefix_kernel(RomView rom, int32_t n_
   const int32_t* ntq = nt_q + (int64_t)q * rom.n_s;
   int64_t loff = 0;
   for (int l = 0; l < i; ++l) loff += ntq[l];
-  double u0 = 0.0;
-  for (int k = 0; k < rom.Q0; ++k) u0 = fma(th0[(int64_t)q * rom.Q0 + k], rom.u0hat[(int64_t)k * rom.n_s + i], u0);
+  const double u0 = initial_coef(rom, thA, th0, q, i);
   const int32_t a0 = rom.moff[i];
   for (int j = threadIdx.x; j < ntq[i]; j += 256) {
     const int a = a0 + j;
@@ -553,6 +570,11 @@ __global__ void certificate_kernel(int32_t n_q, Plan plan, const double* __restr
   if (relres)
     relres[q] = plan.info[q] != 0 ? __longlong_as_double(0x7ff8000000000000LL)
                                    : (bnorm[q] > 0.0 ? rnorm[q] / bnorm[q] : rnorm[q]);
+}
+
+__global__ void fill_f64_kernel(double* p, int64_t n, double v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
 }
 
 __global__ void fill_i32_kernel(int32_t* p, int64_t n, int32_t v) {
@@ -632,15 +654,28 @@ __global__ __launch_bounds__(kResMfThreads) void residual_mf_kernel(RomView rom,
     Z[e] = z;
   }
   __syncthreads();
-  // bracket: z_i(k) - z_i(k - 1) - dt_k sum_i' Ahat(mu)[i, i'] z_i'(k)
+  // bracket: z_i(k) - z_i(k - 1) - dt_k sum_i' Ahat(mu)[i, i'] z_i'(k)  (backward Euler), or
+  // z_i(k) - z_i(k - 1) - dt_k/2 sum_i' Ahat(mu)[i, i'] (z_i'(k) + z_i'(k - 1))  (Crank-Nicolson)
+  const bool cn = rom.integ == ST_CRANK_NICOLSON;
   for (int e = tid; e < n_s * N_t; e += kResMfThreads) {
     const int i = e / N_t, k = e % N_t;
     const double* ar = Ah + i * n_s;
     double u = 0.0;
     for (int ip = 0; ip < n_s; ++ip) u = fma(ar[ip], Z[ip * N_t + k], u);
-    V[e] = Z[e] - (k > 0 ? Z[e - 1] : 0.0) - rom.dt[k] * u;
+    V[e] = cn ? u : Z[e] - (k > 0 ? Z[e - 1] : 0.0) - rom.dt[k] * u;
   }
   __syncthreads();
+  if (cn) {
+    // V holds Ahat(mu) z(k); one thread per mode walks its steps backwards (V(k - 1) is
+    // still the product when step k is finished)
+    for (int i = tid; i < n_s; i += kResMfThreads)
+      for (int k = N_t - 1; k >= 0; --k) {
+        const int e = i * N_t + k;
+        const double az = V[e] + (k > 0 ? V[e - 1] : 0.0);
+        V[e] = Z[e] - (k > 0 ? Z[e - 1] : 0.0) - 0.5 * rom.dt[k] * az;
+      }
+    __syncthreads();
+  }
   // (Ahat_st x)_(i,j) = sum_k phi_(i,j)(k) V_i(k): 16 lanes per output (one DPP row), 4
   // outputs per wave per pass; the pass count is uniform per wave
   const int sub = lane >> 4, c16 = lane & 15;
@@ -669,13 +704,15 @@ hipError_t launch_plan(int32_t n_q, int32_t n_s, const int32_t* moff, const int3
   return hipGetLastError();
 }
 
-hipError_t launch_rhs(const RomView& rom, int32_t n_q, const double* thf, const double* th0, const int32_t* nt_q,
-                      Plan plan, double* rhs, int32_t n_max, hipStream_t s) {
+hipError_t launch_rhs(const RomView& rom, int32_t n_q, const double* thA, const double* thf, const double* th0,
+                      const int32_t* nt_q, Plan plan, double* rhs, int32_t n_max, hipStream_t s) {
   if (n_q == 0 || n_max == 0) return hipSuccess;
   if (nt_q)
-    hipLaunchKernelGGL(rhs_prefix_kernel, dim3(rom.n_s, n_q), dim3(256), 0, s, rom, n_q, thf, th0, nt_q, plan, rhs);
+    hipLaunchKernelGGL(rhs_prefix_kernel, dim3(rom.n_s, n_q), dim3(256), 0, s, rom, n_q, thA, thf, th0, nt_q, plan,
+                       rhs);
   else
-    hipLaunchKernelGGL(rhs_kernel, dim3((n_max + 255) / 256, n_q), dim3(256), 0, s, rom, n_q, thf, th0, plan, rhs);
+    hipLaunchKernelGGL(rhs_kernel, dim3((n_max + 255) / 256, n_q), dim3(256), 0, s, rom, n_q, thA, thf, th0, plan,
+                       rhs);
   return hipGetLastError();
 }
 
@@ -781,6 +818,12 @@ hipError_t launch_fallback_plan(int32_t n_q, Plan plan, Plan fb, int32_t* active
 hipError_t launch_fallback_finish(int32_t n_q, Plan plan, Plan fb, const int32_t* active, hipStream_t s) {
   if (n_q == 0) return hipSuccess;
   hipLaunchKernelGGL(fallback_finish_kernel, dim3((n_q + 255) / 256), dim3(256), 0, s, n_q, plan, fb, active);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_f64(double* p, int64_t n, double v, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_f64_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n, v);
   return hipGetLastError();
 }
 

@@ -19,6 +19,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libstrom.so")
 
 ST_F64, ST_F32, ST_BF16X3 = 0, 1, 2
+ST_BACKWARD_EULER, ST_CRANK_NICOLSON = 0, 1
 ST_OK = 0
 
 
@@ -35,12 +36,12 @@ class st_csr(ctypes.Structure):
 
 class st_rom_desc(ctypes.Structure):
     _fields_ = [("n_s", ctypes.c_int32), ("N_t", ctypes.c_int32), ("Q", ctypes.c_int32), ("Qf", ctypes.c_int32),
-                ("Q0", ctypes.c_int32), ("n_t", ctypes.POINTER(ctypes.c_int32))]
+                ("Q0", ctypes.c_int32), ("n_t", ctypes.POINTER(ctypes.c_int32)), ("integrator", ctypes.c_int32)]
 
 
 class st_rom_layout_t(ctypes.Structure):
     _fields_ = [(k, ctypes.c_size_t) for k in ("Ahat", "bhat", "u0hat", "T", "K", "Wf", "P1", "mode", "moff", "koff", "Phit", "dt",
-                                               "T32", "total")]
+                                               "T32", "Tcn", "Au0", "total")]
 
 
 _lib = None
@@ -159,10 +160,10 @@ def _stream():
 class RomDesc:
     """Host description of a reduced model (keeps its n_t array alive)."""
 
-    def __init__(self, n_t: Sequence[int], N_t: int, Q: int, Qf: int, Q0: int):
+    def __init__(self, n_t: Sequence[int], N_t: int, Q: int, Qf: int, Q0: int, integrator: int = 0):
         self.n_t_arr = np.ascontiguousarray(np.asarray(n_t, dtype=np.int32))
         self.n_t_ptr = self.n_t_arr.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
-        self.c = st_rom_desc(len(self.n_t_arr), int(N_t), int(Q), int(Qf), int(Q0), self.n_t_ptr)
+        self.c = st_rom_desc(len(self.n_t_arr), int(N_t), int(Q), int(Qf), int(Q0), self.n_t_ptr, int(integrator))
 
     @property
     def N_t(self):
@@ -262,7 +263,8 @@ def st_assemble(desc: RomDesc, Phi_s: torch.Tensor, Phi_t: torch.Tensor, dt: tor
 def rom_section(desc: RomDesc, rom: torch.Tensor, name: str) -> torch.Tensor:
     """View of one FP64 section of a ROM buffer (flat)."""
     lay = st_rom_layout(desc)
-    order = ["Ahat", "bhat", "u0hat", "T", "K", "Wf", "P1", "mode", "moff", "koff", "Phit", "dt", "T32", "total"]
+    order = ["Ahat", "bhat", "u0hat", "T", "K", "Wf", "P1", "mode", "moff", "koff", "Phit", "dt", "T32", "Tcn", "Au0",
+             "total"]
     i = order.index(name)
     b0, b1 = lay[name], lay[order[i + 1]]
     dtype = {"mode": torch.int32, "moff": torch.int32, "koff": torch.int64, "T32": torch.float32}.get(name,

@@ -18,10 +18,10 @@ def colmajor(a: np.ndarray) -> torch.Tensor:
 class DeviceRom:
     """ROM buffer built on the device from given bases (st_assemble)."""
 
-    def __init__(self, prob, Phi_s: np.ndarray, Phi_t_list, proj_prec=strom.ST_F64):
+    def __init__(self, prob, Phi_s: np.ndarray, Phi_t_list, proj_prec=strom.ST_F64, integrator=strom.ST_BACKWARD_EULER):
         self.prob = prob
         n_t = [P.shape[1] for P in Phi_t_list]
-        self.desc = strom.RomDesc(n_t, prob.N_t, prob.Q, prob.Qf, prob.Q0)
+        self.desc = strom.RomDesc(n_t, prob.N_t, prob.Q, prob.Qf, prob.Q0, integrator)
         self.Phi_s = colmajor(Phi_s)
         self.Phi_t = colmajor(np.concatenate(Phi_t_list, axis=1))
         self.dt = torch.tensor(prob.dt, device="cuda")

@@ -50,13 +50,14 @@ def test_strerror_and_version():
 def test_layout_is_deterministic_and_aligned():
     d = strom.RomDesc([3, 5, 2], 10, 2, 1, 1)
     lay = strom.st_rom_layout(d)
-    keys = ["Ahat", "bhat", "u0hat", "T", "K", "Wf", "P1", "mode", "moff", "koff", "Phit", "dt", "T32", "total"]
+    keys = ["Ahat", "bhat", "u0hat", "T", "K", "Wf", "P1", "mode", "moff", "koff", "Phit", "dt", "T32", "Tcn", "Au0",
+            "total"]
     offs = [lay[k] for k in keys]
     assert offs == sorted(offs) and all(o % 256 == 0 for o in offs)
     n = 10
     assert lay["K"] - lay["T"] >= 8 * n * n
     assert lay["dt"] - lay["Phit"] >= 8 * 10 * n and lay["T32"] - lay["dt"] >= 8 * 10
-    assert lay["total"] - lay["T32"] >= 4 * n * n
+    assert lay["Tcn"] - lay["T32"] >= 4 * n * n and lay["total"] == lay["Tcn"]     # backward Euler: no CN sections
 
 
 def _null():
