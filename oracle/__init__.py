@@ -24,6 +24,8 @@ bounds   the a-posteriori error bounds of Sec. 5 (Theorems 1-3).
 cn       the Crank-Nicolson variant (the paper's remark that other time
          integrators give other block structures): full-order march,
          explicit space-time system and the reduced block formulas.
+isvd     incremental SVD of a snapshot stream (Sec. 4.2, Alg. 1-2) and the
+         spatial and temporal bases taken from it.
 mlp      FP64 reference of the surrogate network (forward, hand-derived
          backward, Adam) used for gradient parity.
 

@@ -615,3 +615,138 @@ def test_cn_complete_bases_reproduce_fom(problem):
     c = rom.solve(M, rhs)
     Ut = cn.crank_nicolson(A, prob.forcing(mu), u0, prob.dt)
     np.testing.assert_allclose(rom.reconstruct(Phi_s, Phi_t, c), Ut, atol=1e-11 * np.abs(Ut).max())
+
+
+# ---------------------------------------------------------------------------
+# Incremental SVD (Sec. 4.2, Alg. 1-2)
+# ---------------------------------------------------------------------------
+from oracle import isvd  # noqa: E402
+
+
+def _principal_cos(A, B):
+    """Cosines of the principal angles between span(A) and span(B)."""
+    return np.linalg.svd(np.linalg.qr(A)[0].T @ np.linalg.qr(B)[0], compute_uv=False)
+
+
+def test_isvd_two_orthogonal_snapshots_by_hand():
+    # u1 = 3 e1, u2 = 4 e2: Q = [[3, 0], [0, 4]] -> sigma = (4, 3),
+    # W = [e2, e1], V = [[0, 1], [1, 0]] up to the signs of a pair
+    e = np.eye(5)
+    W, s, V = isvd.incremental_svd(np.stack([3 * e[0], 4 * e[1]], axis=1), 1e-12, 1e-12)
+    assert np.allclose(s, [4.0, 3.0], rtol=0, atol=1e-15)
+    assert np.allclose(np.abs(W), np.abs(e[:, [1, 0]]), atol=1e-15)
+    assert np.allclose(np.abs(V), [[0, 1], [1, 0]], atol=1e-15)
+    assert np.allclose(W @ np.diag(s) @ V.T, np.stack([3 * e[0], 4 * e[1]], axis=1), atol=1e-15)
+
+
+def test_isvd_dependent_snapshot_by_hand():
+    # u2 = 2 u1 is dependent: rank stays 1, sigma = sqrt(5) |u1|, V = [1, 2] / sqrt(5)
+    u = np.array([1.0, 2.0, 2.0])
+    ev = []
+    W, s, V = isvd.incremental_svd(np.stack([u, 2 * u], axis=1), 1e-10, 1e-12, events=ev)
+    assert ev == ["init", "dependent"]
+    assert W.shape == (3, 1)
+    assert abs(s[0] - 3.0 * math.sqrt(5.0)) < 1e-14
+    assert np.allclose(np.abs(V[:, 0]), np.array([1.0, 2.0]) / math.sqrt(5.0), atol=1e-15)
+    assert np.allclose(np.abs(W[:, 0]), u / 3.0, atol=1e-15)
+
+
+def test_isvd_skipped_first_snapshot_keeps_a_zero_row():
+    u = np.array([0.0, 3.0, 4.0])
+    ev = []
+    W, s, V = isvd.incremental_svd(np.stack([np.zeros(3), u, u], axis=1), 1e-10, 1e-12, events=ev)
+    assert ev == ["skip", "init", "dependent"]
+    assert V.shape == (3, 1) and V[0, 0] == 0.0
+    assert np.allclose(W @ np.diag(s) @ V.T, np.stack([np.zeros(3), u, u], axis=1), atol=1e-14)
+
+
+def test_isvd_rank_cap_keeps_the_larger_triplet():
+    # r_max = 1 on u1 = 3 e1, u2 = 4 e2: the update gives (4, 3), 3 is dropped
+    e = np.eye(4)
+    W, s, V = isvd.incremental_svd(np.stack([3 * e[0], 4 * e[1]], axis=1), 1e-12, 1e-12, r_max=1)
+    assert np.allclose(s, [4.0]) and np.allclose(np.abs(W[:, 0]), e[1]) and np.allclose(np.abs(V[:, 0]), [0, 1])
+
+
+def test_isvd_truncates_a_small_trailing_singular_value():
+    # u2 = u1 + 1e-9 e3 with eps_sv = 1e-6: the new direction's sigma ~ 7e-10 is dropped
+    u = np.array([1.0, 1.0, 0.0])
+    W, s, V = isvd.incremental_svd(np.stack([u, u + np.array([0, 0, 1e-9])], axis=1), 1e-12, 1e-6)
+    assert len(s) == 1 and abs(s[0] - 2.0) < 1e-12
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_isvd_equals_batch_svd_on_a_graded_matrix(seed):
+    # full stream with tiny tolerances: the thin SVD of the whole matrix
+    rng = np.random.default_rng(seed)
+    N, m, r = 70, 45, 12
+    U = rng.standard_normal((N, r)) @ np.diag(10.0 ** -np.linspace(0, 6, r)) @ rng.standard_normal((r, m))
+    ev = []
+    W, s, V = isvd.incremental_svd(U, 1e-11, 1e-13, events=ev)
+    Wb, sb, Vbt = np.linalg.svd(U, full_matrices=False)
+    kinds = [e.split("+")[0] for e in ev]
+    assert len(s) == r and kinds.count("update") == r - 1 and kinds.count("dependent") == m - r
+    assert np.max(np.abs(s - sb[:r]) / sb[0]) < 1e-14
+    for i in range(r):  # singular vectors up to sign (the gaps are large)
+        assert abs(abs(W[:, i] @ Wb[:, i]) - 1) < 1e-9 * sb[0] / sb[i]
+        assert abs(abs(V[:, i] @ Vbt[i]) - 1) < 1e-9 * sb[0] / sb[i]
+    assert np.linalg.norm(W.T @ W - np.eye(r)) < 1e-13
+    assert np.linalg.norm(U - W @ np.diag(s) @ V.T) < 1e-13 * np.linalg.norm(U)
+
+
+def test_isvd_reproduces_every_snapshot_column():
+    # V has one row per snapshot: column c of U is W diag(s) V(c, :)^T
+    prob = _tiny_advdiff(N=24, N_t=10, n_train=3)
+    U = pod.snapshot_matrix([_fom(prob, m) for m in prob.train_mu])
+    W, s, V = isvd.incremental_svd(U, 1e-13, 1e-15)
+    assert V.shape[0] == U.shape[1]
+    cols = np.linalg.norm(U - W @ np.diag(s) @ V.T, axis=0) / np.linalg.norm(U, axis=0)
+    assert cols.max() < 1e-12
+
+
+def test_isvd_reorthogonalisation_restores_orthonormality():
+    # a basis whose first and last columns are 1e-9 apart from orthogonal trips the
+    # test of Alg. 2 and comes back orthonormal with the same span
+    rng = np.random.default_rng(3)
+    W0 = np.linalg.qr(rng.standard_normal((30, 4)))[0]
+    W0[:, 3] += 1e-9 * W0[:, 0]
+    s0 = np.array([4.0, 3.0, 2.0, 1.0])
+    V0 = np.linalg.qr(rng.standard_normal((6, 4)))[0]
+    u = rng.standard_normal(30)
+    W, s, V, ev = isvd.update(W0, s0, V0, u, 1e-12, 1e-14, 10)
+    assert ev == "update+qr"
+    assert np.abs(W.T @ W - np.eye(W.shape[1])).max() < 1e-14
+    assert np.min(_principal_cos(W, np.concatenate([W0, u[:, None]], axis=1))) > 1 - 1e-12
+    # R is dropped, so the factorisation still holds to the size of the perturbation
+    before = np.concatenate([W0 @ np.diag(s0) @ V0.T, u[:, None]], axis=1)
+    assert np.abs(W @ np.diag(s) @ V.T - before).max() < 1e-8
+
+
+def test_isvd_nearly_dependent_snapshot_needs_the_second_pass():
+    # u = 1e3 (w1 + w2 + w3) + 1e-6 w4: one Gram-Schmidt pass leaves W-components of
+    # ~eps |u| in a residual of norm 1e-6, i.e. j off orthogonal by ~1e-7, which trips
+    # the orthogonality test of Alg. 2; with the second pass W stays orthonormal to
+    # round-off and no re-orthonormalisation is needed.
+    rng = np.random.default_rng(4)
+    Wq = np.linalg.qr(rng.standard_normal((40, 4)))[0]
+    U = np.stack([3 * Wq[:, 0], 2 * Wq[:, 1], Wq[:, 2], 1e3 * Wq[:, :3].sum(axis=1) + 1e-6 * Wq[:, 3]], axis=1)
+    ev = []
+    W, s, V = isvd.incremental_svd(U, 1e-12, 1e-15, events=ev)
+    assert ev == ["init", "update", "update", "update"] and len(s) == 4
+    assert np.abs(W.T @ W - np.eye(4)).max() < 1e-13
+    assert np.linalg.norm(U - W @ np.diag(s) @ V.T) < 1e-13 * np.linalg.norm(U)
+
+
+def test_isvd_bases_match_batch_pod_bases():
+    # the spatial and temporal bases from the stream equal those of the batch POD
+    prob = _tiny_advdiff(N=32, N_t=12, n_train=3)
+    U = pod.snapshot_matrix([_fom(prob, m) for m in prob.train_mu])
+    n_s, n_t = 5, np.array([3, 3, 2, 2, 2])
+    Phi_b, s_b, V_b = pod.pod(U, n_s)
+    Pt_b, rk_b = pod.temporal_bases(V_b, prob.N_t, 3, n_t)
+    W, s, V = isvd.incremental_svd(U, 1e-13, 1e-15)
+    Phi, sig, Pt, rk = isvd.bases(W, s, V, prob.N_t, 3, n_s, n_t)
+    assert np.abs(sig - s_b[:n_s]).max() < 1e-13 * s_b[0]
+    assert np.abs(Phi - Phi_b).max() < 1e-9
+    assert list(rk) == list(rk_b)
+    for a, b in zip(Pt, Pt_b):
+        assert np.abs(a - b).max() < 1e-8
