@@ -74,19 +74,23 @@ def update(W, s, V, u, eps_svd, eps_sv, r_max):
     Q[:r, :r] = np.diag(s)
     Q[:r, r] = l
     Q[r, r] = 0.0 if dependent else p
-    Uq, sq, Vqt = np.linalg.svd(Q)
-    Vq = Vqt.T
     Vext = np.zeros((k + 1, r + 1))
     Vext[:k, :r] = V
     Vext[k, r] = 1.0
     if dependent:
-        W = W @ Uq[:r, :r]
-        s = sq[:r]
-        V = Vext @ Vq[:, :r]
+        # Q has a zero last row: its left singular vectors of nonzero singular
+        # value lie in the first r coordinates, so the leading r components are
+        # the SVD of the r x (r+1) block (taken directly, which keeps the r x r
+        # factor orthogonal when some singular values are tiny)
+        Uq, sq, Vqt = np.linalg.svd(Q[:r, :], full_matrices=False)
+        W = W @ Uq
+        s = sq
+        V = Vext @ Vqt.T
     else:
+        Uq, sq, Vqt = np.linalg.svd(Q)
         W = np.concatenate([W, (res / p)[:, None]], axis=1) @ Uq
         s = sq
-        V = Vext @ Vq
+        V = Vext @ Vqt.T
     if len(s) > 0 and s[-1] < eps_sv:
         W, s, V = W[:, :-1], s[:-1], V[:, :-1]
     if len(s) > r_max:
