@@ -18,6 +18,8 @@
  *                   (j-block-vector), and the projection of u0_st).
  *   st_solve        per-query reduced solve Ahat_st c = fhat_st + u0hat_st
  *                   (Sec. 3.2, Eq. (st-galerkin)) for a ragged batch.
+ *   st_isvd_*       incremental SVD of a snapshot stream and the bases taken
+ *                   from it (Sec. 4.2, Alg. 1-2).
  *   st_mlp_*        a surrogate network mu -> c with a residual check
  *                   (not part of the paper; see the st_mlp section).
  *
@@ -488,6 +490,69 @@ st_status st_spatial_march(const st_rom_desc* d, const void* rom, int32_t n_q, c
 size_t st_project_workspace(int64_t N_s, int32_t n_s, int32_t k);
 st_status st_project(int64_t N_s, int32_t n_s, const double* Phi_s, int32_t k, const double* X, double* out, void* ws,
                      size_t ws_bytes, void* stream);
+
+/* ========================================================================
+ * st_isvd_* - incremental SVD of a snapshot stream (Sec. 4.2, Alg. 1 and 2,
+ * Eq. (factorization2), (middleMat), (svdMiddleMat), (rankOneUpdateSVD2)).
+ *
+ * Snapshots are taken one at a time, as a full-order solver produces them,
+ * and U_k = W diag(s) V^T is updated without keeping U.  For a snapshot u:
+ * l = W^T u and p = ||u - W l|| (two Gram-Schmidt passes); the middle matrix
+ * [[diag(s), l], [0, p]] is decomposed (secular equation with deflation and
+ * Loewner-recomputed vectors) and W <- [W, (u - W l)/p] Uq,
+ * V <- [[V, 0], [0, 1]] Vq, s <- the new singular values.  Decisions, in the
+ * paper's order:
+ *   - empty basis (Alg. 1): u starts it if ||u|| > eps_svd, else u is
+ *     skipped (V still gains a zero row, so row c of V belongs to snapshot c);
+ *   - p < eps_svd (or p at the rounding level of the middle matrix, 8 eps
+ *     times its norm): u is dependent, the rank stays, only the leading r
+ *     triplets are kept;
+ *   - the smallest new singular value < eps_sv: its triplet is dropped;
+ *   - the rank never exceeds r_max: the trailing triplet is dropped (the
+ *     basis is kept, not restarted);
+ *   - |W(:,1)^T W(:,end)| > min(eps_svd, eps N_s) (eps the machine epsilon):
+ *     W is replaced by the Q factor of its QR factorisation with a positive
+ *     diagonal of R (classical Gram-Schmidt with re-orthogonalisation in one
+ *     workgroup), R is dropped.
+ *
+ * Buffers [dev], owned by the caller and passed unchanged to every call of
+ * one stream: W N_s x r_max (ld N_s), s r_max, V m_max x r_max (ld m_max),
+ * state ST_ISVD_STATE int32 words (clear it with st_isvd_reset before the
+ * first snapshot), workspace of st_isvd_workspace(N_s, r_max) bytes.
+ * Columns 0..r-1 of W and V and s[0..r-1] hold the factors, r = state[0];
+ * the rest is stale.  Public state words:
+ *   state[0] r, the current rank         state[1] k, snapshots taken
+ *   state[2] re-orthonormalisations      state[3] dependent snapshots
+ *   state[4] truncated triplets          state[5] snapshots skipped by Alg. 1
+ *   state[6] snapshots refused because k had reached m_max (no update made)
+ * Words 7..15 are internal.
+ *
+ * st_isvd_update streams the b columns of U (N_s x b, ld ldU >= N_s) in
+ * order: five kernel launches each, no host synchronisation, no allocation.
+ * Limits: 1 <= r_max <= ST_ISVD_MAX_RANK, N_s >= 1, m_max >= 1.  Calls on one
+ * state must not overlap (use one stream).
+ *
+ * st_isvd_bases: Eq. (spatialincrementalbasis), (incrementaltemporalsnapshotmat),
+ * (temporalincrementalbasis): once the stream holds all n_mu N_t snapshots
+ * (parameter-major, then time, as st_build_bases's U), Phi_s = W(:, 1:n_s),
+ * sigma = s(1:n_s), and the temporal bases of the columns of V with the
+ * same completion, threshold and sign rules as st_build_bases (columns
+ * beyond the rank are zero).  Synchronises the stream to read the state;
+ * ST_EINVAL when state[1] != n_mu N_t.  Same limits as st_build_bases's
+ * temporal part (n_mu <= 64, N_t n_mu 8 bytes <= 120 KB, n_t[i] <= 512).
+ * ====================================================================== */
+#define ST_ISVD_STATE 16
+#define ST_ISVD_MAX_RANK 256
+size_t st_isvd_workspace(int64_t N_s, int32_t r_max);
+st_status st_isvd_reset(int32_t* state, void* stream);
+st_status st_isvd_update(const double* U, int64_t ldU, int64_t N_s, int32_t b, int32_t r_max, int64_t m_max,
+                         double eps_svd, double eps_sv, double* W, double* s, double* V, int32_t* state, void* ws,
+                         size_t ws_bytes, void* stream);
+size_t st_isvd_bases_workspace(int32_t N_t, int32_t n_mu, int32_t n_s);
+st_status st_isvd_bases(const double* W, const double* s, const double* V, const int32_t* state, int64_t N_s,
+                        int64_t m_max, int32_t N_t, int32_t n_mu, int32_t n_s, const int32_t* n_t, double tau_t,
+                        double* Phi_s, double* Phi_t, double* sigma, int32_t* rank_t, void* ws, size_t ws_bytes,
+                        void* stream);
 
 /* ========================================================================
  * Phase timing (measurement tools).  After st_timing_enable(1), every st_solve

@@ -1161,6 +1161,122 @@ st_status st_project(int64_t N_s, int32_t n_s, const double* Phi_s, int32_t k, c
   return ST_OK;
 }
 
+// ---------------------------------------------------------------------------
+// incremental SVD
+// ---------------------------------------------------------------------------
+static_assert(ST_ISVD_STATE == kIsvdStateInts, "state size");
+static_assert(ST_ISVD_MAX_RANK == kIsvdMaxRank, "rank limit");
+
+static size_t isvd_part_elems(int64_t N_s, int32_t r_max) {
+  const int64_t a = (int64_t)isvd_row_blocks(N_s) * (r_max + 1);
+  const int64_t b = (N_s + 63) / 64;  // one partial per 64-row block of the W update
+  return (size_t)(a > b ? a : b);
+}
+
+static IsvdArgs isvd_carve(int64_t N_s, int32_t r_max, void* ws, size_t* total) {
+  Carver c(ws);
+  IsvdArgs a;
+  memset(&a, 0, sizeof(a));
+  const size_t q = (size_t)(r_max + 1) * (r_max + 1) + 16;  // + the tail read by the 8-column passes
+  a.l1 = c.take<double>(r_max + 1);
+  a.l2 = c.take<double>(r_max + 1);
+  a.scal = c.take<double>(8);
+  a.part = c.take<double>(isvd_part_elems(N_s, r_max));
+  a.res = c.take<double>((size_t)N_s);
+  a.UqT = c.take<double>(q);
+  a.VqT = c.take<double>(q);
+  if (total) *total = c.used;
+  return a;
+}
+
+size_t st_isvd_workspace(int64_t N_s, int32_t r_max) {
+  if (N_s < 1 || r_max < 1 || r_max > kIsvdMaxRank) return 0;
+  size_t total = 0;
+  isvd_carve(N_s, r_max, nullptr, &total);
+  return total;
+}
+
+st_status st_isvd_reset(int32_t* state, void* stream) {
+  if (!state) return ST_EINVAL;
+  ST_TRY(launch_isvd_reset(state, static_cast<hipStream_t>(stream)));
+  return ST_OK;
+}
+
+st_status st_isvd_update(const double* U, int64_t ldU, int64_t N_s, int32_t b, int32_t r_max, int64_t m_max,
+                         double eps_svd, double eps_sv, double* W, double* s, double* V, int32_t* state, void* ws,
+                         size_t ws_bytes, void* stream) {
+  if (N_s < 1 || b < 0 || m_max < 1 || ldU < N_s) return ST_EINVAL;
+  if (r_max < 1) return ST_EINVAL;
+  if (r_max > kIsvdMaxRank) return ST_EUNSUPPORTED;
+  if (!(eps_svd >= 0.0) || !(eps_sv >= 0.0) || !std::isfinite(eps_svd) || !std::isfinite(eps_sv)) return ST_EINVAL;
+  if (!W || !s || !V || !state || !ws || (b > 0 && !U)) return ST_EINVAL;
+  if (ws_bytes < st_isvd_workspace(N_s, r_max)) return ST_EWORKSPACE;
+  IsvdArgs a = isvd_carve(N_s, r_max, ws, nullptr);
+  a.N_s = N_s;
+  a.r_max = r_max;
+  a.m_max = m_max;
+  a.eps_svd = eps_svd;
+  a.eps_sv = eps_sv;
+  a.W = W;
+  a.s = s;
+  a.V = V;
+  a.state = state;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  for (int32_t c = 0; c < b; ++c) ST_TRY(launch_isvd_step(a, U + (int64_t)c * ldU, st));
+  return ST_OK;
+}
+
+size_t st_isvd_bases_workspace(int32_t N_t, int32_t n_mu, int32_t n_s) {
+  if (N_t < 1 || n_mu < 1 || n_s < 1) return 0;
+  Carver c(nullptr);
+  c.take<double>((size_t)N_t * n_mu * n_s);
+  c.take<int32_t>(n_s + 1);
+  return c.used;
+}
+
+st_status st_isvd_bases(const double* W, const double* s, const double* V, const int32_t* state, int64_t N_s,
+                        int64_t m_max, int32_t N_t, int32_t n_mu, int32_t n_s, const int32_t* n_t, double tau_t,
+                        double* Phi_s, double* Phi_t, double* sigma, int32_t* rank_t, void* ws, size_t ws_bytes,
+                        void* stream) {
+  if (!W || !s || !V || !state || !n_t || !Phi_s || !Phi_t || !sigma || !ws) return ST_EINVAL;
+  if (N_s < 1 || N_t < 1 || n_mu < 1 || n_s < 1 || !(tau_t >= 0.0)) return ST_EINVAL;
+  const int64_t m = (int64_t)N_t * n_mu;
+  if (m > m_max || n_s > N_s) return ST_EINVAL;
+  for (int i = 0; i < n_s; ++i)
+    if (n_t[i] < 1 || n_t[i] > N_t) return ST_EINVAL;
+  if (n_s > kMaxModes || n_mu > 64 || (size_t)m * sizeof(double) > 120 * 1024) return ST_EUNSUPPORTED;
+  for (int i = 0; i < n_s; ++i)
+    if (n_t[i] > 512) return ST_EUNSUPPORTED;
+  if (ws_bytes < st_isvd_bases_workspace(N_t, n_mu, n_s)) return ST_EWORKSPACE;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  int32_t hs[2];
+  if (hipMemcpyAsync(hs, state, sizeof(hs), hipMemcpyDeviceToHost, st) != hipSuccess) return ST_EDEVICE;
+  if (hipStreamSynchronize(st) != hipSuccess) return ST_EDEVICE;
+  if (hs[1] != m || hs[0] < 0) return ST_EINVAL;
+  const int rc = hs[0] < n_s ? hs[0] : n_s;
+  Carver c(ws);
+  double* Vs = c.take<double>((size_t)m * n_s);
+  int32_t* moff = c.take<int32_t>(n_s + 1);
+  if (rc > 0) {
+    ST_TRY(launch_copy_cols(W, N_s, Phi_s, N_s, N_s, rc, st));
+    ST_TRY(launch_copy_cols(V, m_max, Vs, m, m, rc, st));
+    ST_TRY(launch_copy_cols(s, rc, sigma, rc, rc, 1, st));
+  }
+  if (rc < n_s) {
+    ST_TRY(launch_fill_f64(Phi_s + (int64_t)rc * N_s, (int64_t)(n_s - rc) * N_s, 0.0, st));
+    ST_TRY(launch_fill_f64(Vs + (int64_t)rc * m, (int64_t)(n_s - rc) * m, 0.0, st));
+    ST_TRY(launch_fill_f64(sigma + rc, n_s - rc, 0.0, st));
+  }
+  ST_TRY(launch_sign_fix(Phi_s, N_s, n_s, Vs, m, st));
+  ModeTable mt;
+  memset(&mt, 0, sizeof(mt));
+  mt.n_s = n_s;
+  for (int i = 0; i < n_s; ++i) mt.nt[i] = n_t[i];
+  ST_TRY(launch_mode_offsets(mt, moff, st));
+  ST_TRY(launch_temporal_svd(Vs, m, N_t, n_mu, n_s, moff, tau_t, Phi_t, rank_t, st));
+  return ST_OK;
+}
+
 st_status st_certify(const st_rom_desc* d, const void* rom, int32_t n_q, const double* theta_A, const double* theta_f,
                      const double* theta_0, const int32_t* nt_q, const double* coeff, int64_t coeff_cap, double gamma,
                      double* relres, double* cert, void* ws, size_t ws_bytes, void* stream) {

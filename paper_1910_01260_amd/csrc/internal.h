@@ -165,6 +165,24 @@ hipError_t launch_reconstruct(int64_t N_s, int32_t N_t, int32_t n_s, const doubl
 
 // True while st_solve records its launches into a HIP graph: launchers then skip
 // hipFuncSetAttribute (set on the eager run that precedes every capture).
+// incremental SVD of a snapshot stream (k_isvd.hip)
+constexpr int kIsvdMaxRank = 256;   // r_max limit (the bordered SVD keeps r_max + 1 coordinates in LDS)
+constexpr int kIsvdStateInts = 16;  // device state words
+struct IsvdArgs {
+  int64_t N_s;
+  int32_t r_max;
+  int64_t m_max;
+  double eps_svd, eps_sv;
+  double *W, *s, *V;
+  int32_t* state;
+  double *l1, *l2, *scal, *part, *res, *UqT, *VqT;
+};
+int64_t isvd_rows_per_block(int64_t N_s);
+int isvd_row_blocks(int64_t N_s);
+size_t isvd_apply_lds_bytes(int r_max);
+hipError_t launch_isvd_reset(int32_t* state, hipStream_t s);
+// one snapshot u (N_s) through the five launches of the update
+hipError_t launch_isvd_step(const IsvdArgs& a, const double* u, hipStream_t s);
 extern bool g_capturing;
 // x (or x += solution when accumulate) for every active query: solve LU x = b
 hipError_t launch_lu_solve(int32_t n_q, Plan plan, int32_t prec, const void* mats, const int32_t* piv, const double* b,

@@ -97,6 +97,11 @@ _SIGNATURES = {
     "st_spatial_march": (_I32, [ctypes.POINTER(st_rom_desc), _P, _I32, _P, _P, _P, _P, _I32, _P, _P, _P, _P, _P]),
     "st_project_workspace": (_SZ, [_I64, _I32, _I32]),
     "st_project": (_I32, [_I64, _I32, _P, _I32, _P, _P, _P, _SZ, _P]),
+    "st_isvd_workspace": (_SZ, [_I64, _I32]),
+    "st_isvd_reset": (_I32, [_P, _P]),
+    "st_isvd_update": (_I32, [_P, _I64, _I64, _I32, _I32, _I64, _D, _D, _P, _P, _P, _P, _P, _SZ, _P]),
+    "st_isvd_bases_workspace": (_SZ, [_I32, _I32, _I32]),
+    "st_isvd_bases": (_I32, [_P, _P, _P, _P, _I64, _I64, _I32, _I32, _I32, _P, _D, _P, _P, _P, _P, _P, _SZ, _P]),
     "st_timing_enable": (_I32, [_I32]),
     "st_timing_read": (_I32, [ctypes.POINTER(ctypes.c_double), _I32]),
 }
@@ -574,3 +579,72 @@ def st_spatial_march(desc: RomDesc, rom: torch.Tensor, theta_A: torch.Tensor, th
                                   n_out, colmajor(Chat), _ptr(traj), _ptr(outs), _ptr(info), _stream()),
            "st_spatial_march")
     return traj, outs, info[:n_q]
+
+
+ISVD_STATE = 16
+ISVD_MAX_RANK = 256
+ISVD_STATE_NAMES = ("rank", "snapshots", "reorthonormalisations", "dependent", "truncated", "skipped", "refused")
+
+
+class IncrementalSVD:
+    """Device buffers of one incremental-SVD stream (st_isvd_*): W (N_s x r_max),
+    s (r_max), V (m_max x r_max), the state words and the workspace."""
+
+    def __init__(self, N_s: int, r_max: int, m_max: int, eps_svd: float, eps_sv: float, device="cuda"):
+        self.N_s, self.r_max, self.m_max = int(N_s), int(r_max), int(m_max)
+        self.eps_svd, self.eps_sv = float(eps_svd), float(eps_sv)
+        self.W_store = torch.zeros((self.r_max, self.N_s), dtype=torch.float64, device=device)
+        self.s = torch.zeros(self.r_max, dtype=torch.float64, device=device)
+        self.V_store = torch.zeros((self.r_max, self.m_max), dtype=torch.float64, device=device)
+        self.state = torch.zeros(ISVD_STATE, dtype=torch.int32, device=device)
+        nb = lib().st_isvd_workspace(self.N_s, self.r_max)
+        if nb == 0:
+            raise StromError(-1, "st_isvd_workspace")
+        self.ws = torch.empty(nb, dtype=torch.uint8, device=device)
+        self.reset()
+
+    def reset(self):
+        _check(lib().st_isvd_reset(_ptr(self.state), _stream()), "st_isvd_reset")
+
+    def update(self, U: torch.Tensor):
+        """Stream the columns of U (N_s x b, column-major, or one vector)."""
+        if U.shape[0] != self.N_s or U.dtype != torch.float64 or not U.is_cuda:
+            raise ValueError("U must be a float64 device tensor with N_s rows")
+        if U.dim() == 1:
+            U = U.contiguous()
+            ptr, ld, b = ctypes.c_void_p(U.data_ptr()), self.N_s, 1
+        else:
+            if U.stride(0) != 1:
+                U = U.T.contiguous().T
+            ptr, ld, b = ctypes.c_void_p(U.data_ptr()), max(U.stride(1), self.N_s), U.shape[1]
+        _check(lib().st_isvd_update(ptr, ld, self.N_s, b, self.r_max, self.m_max, self.eps_svd, self.eps_sv,
+                                    _ptr(self.W_store), _ptr(self.s), _ptr(self.V_store), _ptr(self.state),
+                                    _ptr(self.ws), self.ws.numel(), _stream()), "st_isvd_update")
+
+    def counters(self) -> dict:
+        st = self.state.cpu().numpy()
+        return {k: int(st[i]) for i, k in enumerate(ISVD_STATE_NAMES)}
+
+    def factors(self):
+        """(W N_s x r, s r, V k x r) as host arrays."""
+        c = self.counters()
+        r, k = c["rank"], c["snapshots"]
+        W = self.W_store[:r].cpu().numpy().T.copy()
+        V = self.V_store[:r, :k].cpu().numpy().T.copy()
+        return W, self.s[:r].cpu().numpy().copy(), V
+
+    def bases(self, N_t: int, n_mu: int, n_s: int, n_t: Sequence[int], tau_t: float = 1e-7):
+        """st_isvd_bases: (Phi_s N_s x n_s, Phi_t N_t x n, sigma n_s, rank_t n_s), column-major views."""
+        nt = np.ascontiguousarray(np.asarray(n_t, dtype=np.int32))
+        n = int(nt.sum())
+        dev = self.W_store.device
+        nb = lib().st_isvd_bases_workspace(N_t, n_mu, n_s)
+        ws = torch.empty(max(nb, 1), dtype=torch.uint8, device=dev)
+        Phi_s = torch.empty((n_s, self.N_s), dtype=torch.float64, device=dev)
+        Phi_t = torch.empty((n, N_t), dtype=torch.float64, device=dev)
+        sigma = torch.empty(n_s, dtype=torch.float64, device=dev)
+        rank = torch.empty(n_s, dtype=torch.int32, device=dev)
+        _check(lib().st_isvd_bases(_ptr(self.W_store), _ptr(self.s), _ptr(self.V_store), _ptr(self.state), self.N_s,
+                                   self.m_max, N_t, n_mu, n_s, nt.ctypes.data, float(tau_t), _ptr(Phi_s),
+                                   _ptr(Phi_t), _ptr(sigma), _ptr(rank), _ptr(ws), nb, _stream()), "st_isvd_bases")
+        return Phi_s.T, Phi_t.T, sigma, rank
