@@ -528,7 +528,8 @@ st_status st_project(int64_t N_s, int32_t n_s, const double* Phi_s, int32_t k, c
  * Words 7..15 are internal.
  *
  * st_isvd_update streams the b columns of U (N_s x b, ld ldU >= N_s) in
- * order: five kernel launches each, no host synchronisation, no allocation.
+ * order: four kernel launches each for N_s <= 4096, nine beyond, with no host
+ * synchronisation and no allocation.
  * Limits: 1 <= r_max <= ST_ISVD_MAX_RANK, N_s >= 1, m_max >= 1.  Calls on one
  * state must not overlap (use one stream).
  *

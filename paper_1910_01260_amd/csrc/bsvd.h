@@ -52,6 +52,8 @@ struct Problem {
   double* z;       // [n] z_t, rotated and deflated in place
   int* act;        // [n] active coordinates in order (descending d), count na
   int na;
+  double* da;      // [n] d and z of the active coordinates, contiguous (da[k] = d[act[k]])
+  double* za;
   int* rot_i;      // [r] rotation pairs (kept, deflated), count nrot
   int* rot_j;
   double* rot_c;
@@ -93,23 +95,30 @@ BSVD_FN double deflate(Problem& P, bool dependent) {
   }
   P.na = 0;
   for (int t = 0; t <= r; ++t)
-    if (P.z[t] != 0.0) P.act[P.na++] = t;
+    if (P.z[t] != 0.0) {
+      P.da[P.na] = P.d[t];
+      P.za[P.na] = P.z[t];
+      P.act[P.na++] = t;
+    }
   P.p_active = P.z[r] != 0.0;
   return tol;
 }
 
-// f(tau) and f'(tau) for the origin coordinate o (sigma = d_o + tau), over
-// the active coordinates.
-BSVD_FN void secular(const Problem& P, int o, double tau, double& f, double& df, double& fabs_sum) {
-  const double dob = P.d[o];
+// Partial sums of f(tau) - 1, f'(tau) and sum |terms| at sigma = dob + tau over
+// the active coordinates k0, k0 + kstep, ... (a group of threads splits the
+// sum and combines the parts).
+BSVD_FN void secular_part(const Problem& P, double dob, double tau, int k0, int kstep, double& f, double& df,
+                          double& fabs_sum) {
   const double sig = dob + tau;
-  double s = 1.0, ds = 0.0, a = 1.0;
-  for (int k = 0; k < P.na; ++k) {
-    const int t = P.act[k];
-    const double del = (P.d[t] - dob) - tau;  // d_t - sigma
-    const double sum = P.d[t] + sig;          // d_t + sigma
-    const double q = P.z[t] / (del * sum);
-    const double term = P.z[t] * q;
+  double s = 0.0, ds = 0.0, a = 0.0;
+  const double* __restrict__ da = P.da;
+  const double* __restrict__ za = P.za;
+#pragma unroll 4
+  for (int k = k0; k < P.na; k += kstep) {
+    const double del = (da[k] - dob) - tau;  // d_t - sigma
+    const double sum = da[k] + sig;          // d_t + sigma
+    const double q = za[k] / (del * sum);
+    const double term = za[k] * q;
     s += term;
     a += fabs(term);
     ds += 2.0 * sig * q * q;
@@ -119,29 +128,36 @@ BSVD_FN void secular(const Problem& P, int o, double tau, double& f, double& df,
   fabs_sum = a;
 }
 
-// Root number k (0-based, descending) of the active problem.  Writes its
-// origin coordinate and offset: sigma_k = d[o] + tau.
-BSVD_FN void root(const Problem& P, int k, int& o_out, double& tau_out) {
-  const int t = P.act[k];
-  double lo, hi;
-  int o;
+// Combines the partial sums of one group (nothing to do for one thread).
+struct SoloSum {
+  BSVD_FN void operator()(double&, double&, double&) const {}
+};
+
+// Root number k (0-based, descending) of the active problem, found by the
+// group of threads that share k (each passes its k0 = rank in the group and
+// kstep = group size, and `red` combines the group's partial sums).  Writes
+// its origin (the nearer end of its gap) and offset: sigma_k = dorg + tau.
+template <typename Red>
+BSVD_FN void root_group(const Problem& P, int k, int k0, int kstep, Red red, double& dorg_out, double& tau_out) {
+  double lo, hi, dob;
   if (k == 0) {
-    double zz = 0.0;
-    for (int m = 0; m < P.na; ++m) zz += P.z[P.act[m]] * P.z[P.act[m]];
-    o = t;
+    double zz = 0.0, u = 0.0, w = 0.0;
+    for (int m = k0; m < P.na; m += kstep) zz += P.za[m] * P.za[m];
+    red(zz, u, w);
+    dob = P.da[0];
     lo = 0.0;
-    hi = zz / (P.d[t] + sqrt(P.d[t] * P.d[t] + zz));
+    hi = zz / (dob + sqrt(dob * dob + zz));
   } else {
-    const int tp = P.act[k - 1];
-    const double gap = P.d[tp] - P.d[t];
+    const double gap = P.da[k - 1] - P.da[k];
     double f, df, a;
-    secular(P, t, 0.5 * gap, f, df, a);
-    if (f >= 0.0) {
-      o = t;
+    secular_part(P, P.da[k], 0.5 * gap, k0, kstep, f, df, a);
+    red(f, df, a);
+    if (1.0 + f >= 0.0) {
+      dob = P.da[k];
       lo = 0.0;
       hi = 0.5 * gap;
     } else {
-      o = tp;
+      dob = P.da[k - 1];
       lo = -0.5 * gap;
       hi = 0.0;
     }
@@ -150,7 +166,10 @@ BSVD_FN void root(const Problem& P, int k, int& o_out, double& tau_out) {
   double tau = 0.5 * (lo + hi);
   for (int it = 0; it < kMaxNewton; ++it) {
     double f, df, a;
-    secular(P, o, tau, f, df, a);
+    secular_part(P, dob, tau, k0, kstep, f, df, a);
+    red(f, df, a);
+    f += 1.0;
+    a += 1.0;
     if (f == 0.0 || fabs(f) <= kEps * a) break;
     if (f < 0.0)
       lo = tau;
@@ -175,40 +194,47 @@ BSVD_FN void root(const Problem& P, int k, int& o_out, double& tau_out) {
     if (nt == tau) break;
     tau = nt;
   }
-  o_out = o;
+  dorg_out = dob;
   tau_out = tau;
 }
 
-// sigma_k - d_t and sigma_k + d_t from the stored (origin, tau).
-BSVD_FN double minus_d(const Problem& P, int o, double tau, int t) { return (P.d[o] - P.d[t]) + tau; }
-BSVD_FN double plus_d(const Problem& P, int o, double tau, int t) { return P.d[o] + tau + P.d[t]; }
+// One thread per root.
+BSVD_FN void root(const Problem& P, int k, double& dorg_out, double& tau_out) {
+  root_group(P, k, 0, 1, SoloSum{}, dorg_out, tau_out);
+}
+
+// sigma_k - d and sigma_k + d from the stored (origin, tau).
+BSVD_FN double minus_d(double dorg, double tau, double d) { return (dorg - d) + tau; }
+BSVD_FN double plus_d(double dorg, double tau, double d) { return dorg + tau + d; }
 
 // Loewner's formula for the active coordinate at position m: the z for which
 // the computed roots are exact.
-BSVD_FN double zhat(const Problem& P, int m, const int* org, const double* tau) {
-  const int t = P.act[m];
-  double prod = minus_d(P, org[m], tau[m], t) * plus_d(P, org[m], tau[m], t);
+BSVD_FN double zhat(const Problem& P, int m, const double* dorg, const double* tau) {
+  const double dt = P.da[m];
+  double prod = minus_d(dorg[m], tau[m], dt) * plus_d(dorg[m], tau[m], dt);
   for (int k = 0; k < P.na; ++k) {
     if (k == m) continue;
-    const int u = P.act[k];
-    const double num = minus_d(P, org[k], tau[k], t) * plus_d(P, org[k], tau[k], t);
-    const double den = (P.d[u] - P.d[t]) * (P.d[u] + P.d[t]);
+    const double du = P.da[k];
+    const double num = minus_d(dorg[k], tau[k], dt) * plus_d(dorg[k], tau[k], dt);
+    const double den = (du - dt) * (du + dt);
     prod *= num / den;
   }
-  return copysign(sqrt(fabs(prod)), P.z[t]);
+  return copysign(sqrt(fabs(prod)), P.za[m]);
 }
 
-// Entry t of the unnormalised left and right vectors of root k, with zh the
-// recomputed z of every coordinate (zero where deflated).
-BSVD_FN void vec_entry(const Problem& P, const double* zh, int o, double tau, int t, double& ul, double& vr) {
+// Entry t of the unnormalised left and right vectors of the root
+// (dorg, tau), with zh the recomputed z of every coordinate (zero where
+// deflated).
+BSVD_FN void vec_entry(const Problem& P, const double* zh, double dorg, double tau, int t, double& ul, double& vr) {
   if (zh[t] == 0.0) {
     ul = 0.0;
     vr = (t == P.r) ? -1.0 : 0.0;
     return;
   }
-  const double den = -(minus_d(P, o, tau, t) * plus_d(P, o, tau, t));  // d_t^2 - sigma^2
-  ul = zh[t] / den;
-  vr = (t == P.r) ? -1.0 : P.d[t] * zh[t] / den;
+  const double dt = P.d[t];
+  const double q = zh[t] / -(minus_d(dorg, tau, dt) * plus_d(dorg, tau, dt));  // z_t / (d_t^2 - sigma^2)
+  ul = q;
+  vr = (t == P.r) ? -1.0 : dt * q;
 }
 
 // Undo the deflation rotations on one column (coordinates < r), last first.
@@ -229,8 +255,8 @@ namespace bsvd {
 // Singular value of the candidate carried by coordinate t: the root whose gap
 // starts at t when t is active (pos[t] = its index among the active
 // coordinates), d_t when t is deflated.
-BSVD_FN double cand_sigma(const Problem& P, const int* pos, const int* org, const double* tau, int t) {
-  return pos[t] >= 0 ? P.d[org[pos[t]]] + tau[pos[t]] : P.d[t];
+BSVD_FN double cand_sigma(const Problem& P, const int* pos, const double* dorg, const double* tau, int t) {
+  return pos[t] >= 0 ? dorg[pos[t]] + tau[pos[t]] : P.d[t];
 }
 
 // Position of candidate t in the descending order of the n_cand candidates
@@ -243,7 +269,7 @@ BSVD_FN int cand_rank(const double* sig, int n_cand, int t) {
 
 // Left and right singular vectors of candidate t, normalised and rotated back
 // to the coordinates of Q, written with the given element stride.
-BSVD_FN void fill_column(const Problem& P, const double* zh, const int* pos, const int* org, const double* tau,
+BSVD_FN void fill_column(const Problem& P, const double* zh, const int* pos, const double* dorg, const double* tau,
                          int t, double* ucol, double* vcol, int stride) {
   const int n = P.r + 1;
   if (pos[t] < 0) {
@@ -256,16 +282,16 @@ BSVD_FN void fill_column(const Problem& P, const double* zh, const int* pos, con
     double nu = 0.0, nv = 0.0;
     for (int q = 0; q < n; ++q) {
       double a, b;
-      vec_entry(P, zh, org[k], tau[k], q, a, b);
+      vec_entry(P, zh, dorg[k], tau[k], q, a, b);
+      ucol[(int64_t)q * stride] = a;
+      vcol[(int64_t)q * stride] = b;
       nu += a * a;
       nv += b * b;
     }
     const double iu = 1.0 / sqrt(nu), iv = 1.0 / sqrt(nv);
     for (int q = 0; q < n; ++q) {
-      double a, b;
-      vec_entry(P, zh, org[k], tau[k], q, a, b);
-      ucol[(int64_t)q * stride] = a * iu;
-      vcol[(int64_t)q * stride] = b * iv;
+      ucol[(int64_t)q * stride] *= iu;
+      vcol[(int64_t)q * stride] *= iv;
     }
   }
   unrotate(P, ucol, stride);

@@ -1,22 +1,23 @@
 // Incremental SVD of a snapshot stream (Sec. 4.2, Alg. 1 and 2).
 //
 // The factors W (N_s x r), s (r) and V (k x r) live in device memory and are
-// updated in place for each snapshot u by five launches, none of which waits
-// on the host:
-//   dots   l1 = W^T u                                   (row blocks)
-//   sub1   res = u - W l1,  l2 = W^T res                (row blocks)
-//   sub2   res -= W l2,  p = ||res||; the last workgroup solves the bordered
-//          middle matrix [[diag(s), l1 + l2], [0, p]] (bsvd.h) and writes
-//          Uq^T, Vq^T, the new s and the step's decisions (Alg. 1 when the
-//          basis is empty; dependence, truncation, rank cap)
-//   applyW W <- [W, res/p] Uq  in place by rows; the last workgroup applies
-//          the orthogonality test of Alg. 2 to the new first and last columns
-//   applyV V <- [[V, 0], [0, 1]] Vq  in place by rows; the last workgroup
-//          commits the step and, when the test failed, re-orthonormalises W
-//          by classical Gram-Schmidt with re-orthogonalisation (the Q factor
-//          with a positive diagonal of R, which is dropped).
-// Each reduction across workgroups ends in the last workgroup to arrive (an
-// atomic ticket), so no workgroup ever waits for another.
+// updated in place for each snapshot u, with no host synchronisation:
+//   front   l1 = W^T u, res = u - W l1, l2 = W^T res, res -= W l2 (two
+//           Gram-Schmidt passes), p = ||res||; then, in one workgroup, the
+//           step's decisions (Alg. 1 when the basis is empty; dependence,
+//           truncation, rank cap) and the SVD of the bordered middle matrix
+//           [[diag(s), l1 + l2], [0, p]] (bsvd.h), which writes Uq^T, Vq^T
+//           and the new s.  Snapshots up to kFrontRows long take one
+//           workgroup for all of it; longer ones take row-block launches
+//           whose partials are summed by launches of their own.
+//   applyW  W <- [W, res/p] Uq in place by rows, with the partials of the
+//           orthogonality test of Alg. 2 (new first column against new last)
+//   applyV  V <- [[V, 0], [0, 1]] Vq in place by rows
+//   commit  the test; when it fails W is re-orthonormalised by classical
+//           Gram-Schmidt with re-orthogonalisation (the Q factor with a
+//           positive diagonal of R, which is dropped); the new rank and count.
+// Workgroups never wait for one another: every cross-workgroup sum ends a
+// launch and is read by the next.
 #include "bsvd.h"
 #include "internal.h"
 
@@ -30,17 +31,38 @@ constexpr int kNW = kIT / 64;      // waves per workgroup
 constexpr int kApplyRows = 64;     // rows per workgroup of the factor updates
 constexpr int kColPass = 8;        // output columns per lane and pass
 constexpr int kMaxN = kIsvdMaxRank + 1;
+constexpr int kGrp = 8;  // lanes per column in the norms of the bordered SVD's vectors
+constexpr int64_t kFrontRows = 4096;  // snapshots up to this length take the one-workgroup front
 
 // state slots (the first seven are documented in the public header)
 enum : int {
   S_R = 0, S_K = 1, S_QR = 2, S_DEP = 3, S_TRUNC = 4, S_SKIP = 5, S_REFUSED = 6,
-  S_RNEW = 8, S_MODE = 9, S_CTR_A = 10, S_CTR_B = 11, S_CTR_C = 12, S_CTR_E = 13, S_CTR_F = 14, S_ORTH = 15
+  S_RNEW = 8, S_MODE = 9
 };
 enum : int { M_UPDATE = 0, M_NOOP = 1 };
 // scalar slots of the workspace
 enum : int { C_P2 = 0, C_INVP = 1, C_PART0 = 2 };
 
 __device__ inline double wave_sum(double v) { return __ockl_wfred_add_f64(v); }
+
+// Sums three values over a group of L lanes; every lane of the group gets
+// lane 0's result, so the group takes identical decisions.
+template <int L>
+struct GroupSum {
+  __device__ void operator()(double& a, double& b, double& c) const {
+    if constexpr (L > 1) {
+#pragma unroll
+      for (int m = L / 2; m >= 1; m >>= 1) {
+        a += __shfl_xor(a, m, L);
+        b += __shfl_xor(b, m, L);
+        c += __shfl_xor(c, m, L);
+      }
+      a = __shfl(a, 0, L);
+      b = __shfl(b, 0, L);
+      c = __shfl(c, 0, L);
+    }
+  }
+};
 
 __device__ double block_sum(double v) {
   __shared__ double red[kNW];
@@ -59,43 +81,51 @@ __device__ double block_sum(double v) {
   return r;
 }
 
-// True (in every thread) in the last workgroup to arrive at `ctr`; that
-// workgroup then sees the writes of all the others.  The counter is reset for
-// the next launch.
-__device__ bool last_to_arrive(int32_t* ctr, int nblocks) {
-  __shared__ int s_last;
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const int t = atomicAdd(ctr, 1);
-    s_last = (t == nblocks - 1);
-    if (s_last) atomicExch(ctr, 0);
-  }
-  __syncthreads();
-  const bool last = s_last != 0;
-  if (last) __threadfence();
-  return last;
-}
-
-// out[c] = sum over rows [row0, row1) of W[row, c] x[row], c < r (one wave per column)
+// out[c * ostride] = sum over rows [row0, row1) of W[row, c] x[row], c < r
+// (one wave per column)
 __device__ void block_dots(const double* __restrict__ W, int64_t ldw, int r, const double* x, int64_t row0,
-                           int64_t row1, double* out) {
+                           int64_t row1, double* out, int64_t ostride) {
+  constexpr int CB = 4;  // columns per wave and pass: their loads are in flight together
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  for (int c = wave; c < r; c += kNW) {
-    const double* wc = W + (int64_t)c * ldw;
-    double acc = 0.0;
-    for (int64_t i = row0 + lane; i < row1; i += 64) acc = fma(wc[i], x[i], acc);
-    acc = wave_sum(acc);
-    if (lane == 0) out[c] = acc;
+  for (int c0 = wave * CB; c0 < r; c0 += kNW * CB) {
+    double acc[CB];
+#pragma unroll
+    for (int q = 0; q < CB; ++q) acc[q] = 0.0;
+    for (int64_t i = row0 + lane; i < row1; i += 64) {
+      const double xi = x[i];
+#pragma unroll
+      for (int q = 0; q < CB; ++q)
+        if (c0 + q < r) acc[q] = fma(W[i + (int64_t)(c0 + q) * ldw], xi, acc[q]);
+    }
+#pragma unroll
+    for (int q = 0; q < CB; ++q) {
+      const double v = wave_sum(acc[q]);
+      if (lane == 0 && c0 + q < r) out[(c0 + q) * ostride] = v;
+    }
   }
 }
 
-// out[c] = sum_b part[b * width + c], c < cols
-__device__ void reduce_parts(const double* part, int nb, int width, int cols, double* out) {
-  for (int c = threadIdx.x; c < cols; c += kIT) {
-    double s = 0.0;
-    for (int b = 0; b < nb; ++b) s += part[(int64_t)b * width + c];
-    out[c] = s;
+// out[c] = sum_b part[c * nb + b], c < cols (one wave per column, lanes over
+// the workgroups' partials, always summed in the same order; several loads
+// in flight per lane)
+template <int NT>
+__device__ void reduce_parts(const double* part, int nb, int cols, double* out) {
+  constexpr int U = 4;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int c = wave; c < cols; c += NT / 64) {
+    const double* pc = part + (int64_t)c * nb;
+    double s[U];
+#pragma unroll
+    for (int q = 0; q < U; ++q) s[q] = 0.0;
+    for (int b0 = 0; b0 < nb; b0 += 64 * U) {
+#pragma unroll
+      for (int q = 0; q < U; ++q) {
+        const int b = b0 + q * 64 + lane;
+        if (b < nb) s[q] += pc[b];
+      }
+    }
+    const double v = wave_sum((s[0] + s[1]) + (s[2] + s[3]));
+    if (lane == 0) out[c] = v;
   }
 }
 
@@ -113,19 +143,26 @@ __device__ double subtract_block(const double* __restrict__ W, int64_t ldw, int 
   return nn;
 }
 
+// Partials of l1 = W^T u over the workgroup's rows: part[c * G + b].
 __global__ __launch_bounds__(kIT) void isvd_dots_kernel(const double* __restrict__ W, int64_t N_s, int64_t rows_pb,
-                                                        const double* __restrict__ u, int32_t* state, double* part,
-                                                        int width, double* l1) {
+                                                        const double* __restrict__ u, const int32_t* state,
+                                                        double* part) {
   const int r = state[S_R];
   const int64_t row0 = (int64_t)blockIdx.x * rows_pb, row1 = min(row0 + rows_pb, N_s);
-  block_dots(W, N_s, r, u, row0, row1, part + (int64_t)blockIdx.x * width);
-  if (last_to_arrive(state + S_CTR_A, gridDim.x)) reduce_parts(part, gridDim.x, width, r, l1);
+  block_dots(W, N_s, r, u, row0, row1, part + blockIdx.x, gridDim.x);
 }
 
+// out[c] = sum of the G partials of column c, c < r (one workgroup)
+constexpr int kRT = 1024;
+__global__ __launch_bounds__(kRT) void isvd_reduce_kernel(const double* part, int G, const int32_t* state,
+                                                          double* out) {
+  reduce_parts<kRT>(part, G, state[S_R], out);
+}
+
+// res = u - W l1 over the workgroup's rows, and the partials of l2 = W^T res.
 __global__ __launch_bounds__(kIT) void isvd_sub1_kernel(const double* __restrict__ W, int64_t N_s, int64_t rows_pb,
-                                                        const double* __restrict__ u, int32_t* state,
-                                                        const double* l1, double* res, double* part, int width,
-                                                        double* l2) {
+                                                        const double* __restrict__ u, const int32_t* state,
+                                                        const double* l1, double* res, double* part) {
   __shared__ double sl[kIsvdMaxRank];
   const int r = state[S_R];
   for (int c = threadIdx.x; c < r; c += kIT) sl[c] = l1[c];
@@ -133,17 +170,103 @@ __global__ __launch_bounds__(kIT) void isvd_sub1_kernel(const double* __restrict
   const int64_t row0 = (int64_t)blockIdx.x * rows_pb, row1 = min(row0 + rows_pb, N_s);
   subtract_block(W, N_s, r, sl, u, res, row0, row1);
   __syncthreads();
-  block_dots(W, N_s, r, res, row0, row1, part + (int64_t)blockIdx.x * width);
-  if (last_to_arrive(state + S_CTR_B, gridDim.x)) reduce_parts(part, gridDim.x, width, r, l2);
+  block_dots(W, N_s, r, res, row0, row1, part + blockIdx.x, gridDim.x);
+}
+
+// bsvd::deflate spread over the workgroup (same result): the small-z test is
+// independent per coordinate, the serial rotation loop runs only when two
+// consecutive active coordinates are within tol, and wave 0 compacts the
+// active set with ballots.
+__device__ void deflate_block(bsvd::Problem& P, bool dependent, int* s_na, int* s_nrot, int* s_pact) {
+  __shared__ int s_close;
+  __shared__ double s_tol;
+  const int tid = threadIdx.x, r = P.r;
+  double zz = 0.0;
+  for (int t = tid; t <= r; t += kIT) zz += P.z[t] * P.z[t];
+  zz = block_sum(zz);
+  if (tid == 0) {
+    const double dmax = r > 0 ? P.d[0] : 0.0;
+    s_tol = 8.0 * bsvd::kEps * fmax(dmax, sqrt(zz));
+    s_close = 0;
+  }
+  __syncthreads();
+  const double tol = s_tol;
+  for (int t = tid; t <= r; t += kIT)
+    if ((t == r && dependent) || fabs(P.z[t]) <= tol) P.z[t] = 0.0;
+  __syncthreads();
+  for (int t = tid; t < r; t += kIT) {
+    if (P.z[t] == 0.0) continue;
+    int u = t - 1;
+    while (u >= 0 && P.z[u] == 0.0) --u;
+    if (u >= 0 && P.d[u] - P.d[t] <= tol) s_close = 1;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    P.nrot = 0;
+    if (s_close) {
+      int k0 = -1;
+      for (int t = 0; t < r; ++t) {
+        if (P.z[t] == 0.0) continue;
+        if (k0 >= 0 && P.d[k0] - P.d[t] <= tol) {
+          const double rho = hypot(P.z[k0], P.z[t]);
+          P.rot_i[P.nrot] = k0;
+          P.rot_j[P.nrot] = t;
+          P.rot_c[P.nrot] = P.z[k0] / rho;
+          P.rot_s[P.nrot] = P.z[t] / rho;
+          ++P.nrot;
+          P.z[k0] = rho;
+          P.z[t] = 0.0;
+          P.d[t] = P.d[k0];
+        } else {
+          k0 = t;
+        }
+      }
+    }
+    *s_nrot = P.nrot;
+    *s_pact = P.z[r] != 0.0 ? 1 : 0;
+  }
+  __syncthreads();
+  if (tid < 64) {
+    int base = 0;
+    for (int c0 = 0; c0 <= r; c0 += 64) {
+      const int t = c0 + tid;
+      const bool on = t <= r && P.z[t] != 0.0;
+      const uint64_t m = __ballot(on);
+      if (on) {
+        const int k = base + __popcll(m & ((1ull << tid) - 1ull));
+        P.act[k] = t;
+        P.da[k] = P.d[t];
+        P.za[k] = P.z[t];
+      }
+      base += __popcll(m);
+    }
+    if (tid == 0) *s_na = base;
+  }
+  __syncthreads();
+}
+
+// Every root of the active problem, a group of L lanes per root.
+template <int L>
+__device__ void roots_phase(const bsvd::Problem& P, double* org, double* tau, int* pos) {
+  const int grp = threadIdx.x / L, gl = threadIdx.x % L;
+  for (int q = grp; q < P.na; q += kIT / L) {
+    double o, tv;
+    bsvd::root_group(P, q, gl, L, GroupSum<L>{}, o, tv);
+    if (gl == 0) {
+      org[q] = o;
+      tau[q] = tv;
+      pos[P.act[q]] = q;
+    }
+  }
 }
 
 // The step's decisions and the SVD of the middle matrix, in one workgroup.
 __device__ void bordered_step(int r, int r_max, int64_t m_max, double eps_svd, double eps_sv, double p2,
                               const double* l1, const double* l2, double* s, double* UqT, double* VqT, int ldq,
                               double* scal, int32_t* state) {
-  __shared__ double d[kMaxN], z[kMaxN], zh[kMaxN], tau[kMaxN], sg[kMaxN];
-  __shared__ double rc[kIsvdMaxRank], rs[kIsvdMaxRank];
-  __shared__ int act[kMaxN], org[kMaxN], pos[kMaxN], ri[kIsvdMaxRank], rj[kIsvdMaxRank];
+  __shared__ double d[kMaxN], z[kMaxN], zh[kMaxN], tau[kMaxN], org[kMaxN], sg[kMaxN], da[kMaxN], za[kMaxN];
+  __shared__ double rc[kIsvdMaxRank], rs[kIsvdMaxRank], inu[kMaxN], inv[kMaxN];
+  __shared__ int act[kMaxN], pos[kMaxN], ri[kIsvdMaxRank], rj[kIsvdMaxRank], colsrc[kMaxN];
   __shared__ int s_na, s_nrot, s_pact, s_go, s_keep;
   const int tid = threadIdx.x;
   const double p = sqrt(p2);
@@ -154,7 +277,7 @@ __device__ void bordered_step(int r, int r_max, int64_t m_max, double eps_svd, d
   }
   for (int t = tid; t <= r; t += kIT) pos[t] = -1;
   __syncthreads();
-  bsvd::Problem P{r, d, z, act, 0, ri, rj, rc, rs, 0, false};
+  bsvd::Problem P{r, d, z, act, 0, da, za, ri, rj, rc, rs, 0, false};
   if (tid == 0) {
     s_go = 0;
     if (k >= m_max) {
@@ -178,31 +301,41 @@ __device__ void bordered_step(int r, int r_max, int64_t m_max, double eps_svd, d
       state[S_MODE] = M_UPDATE;
       d[r] = 0.0;
       z[r] = p;
-      bsvd::deflate(P, !(p >= eps_svd));
-      s_na = P.na;
-      s_nrot = P.nrot;
-      s_pact = P.p_active ? 1 : 0;
       s_go = 1;
     }
   }
   __syncthreads();
   if (!s_go) return;
+  deflate_block(P, !(p >= eps_svd), &s_na, &s_nrot, &s_pact);
   P.na = s_na;
   P.nrot = s_nrot;
   P.p_active = s_pact != 0;
-  for (int q = tid; q < P.na; q += kIT) {
-    bsvd::root(P, q, org[q], tau[q]);
-    pos[act[q]] = q;
-  }
+  const int n = r + 1;
+  // roots: a group of lanes per root splits the secular sums; the group is
+  // as wide as the workgroup allows with every root in one pass
+  if (P.na * 32 <= kIT)
+    roots_phase<32>(P, org, tau, pos);
+  else if (P.na * 16 <= kIT)
+    roots_phase<16>(P, org, tau, pos);
+  else if (P.na * 8 <= kIT)
+    roots_phase<8>(P, org, tau, pos);
+  else if (P.na * 4 <= kIT)
+    roots_phase<4>(P, org, tau, pos);
+  else if (P.na * 2 <= kIT)
+    roots_phase<2>(P, org, tau, pos);
+  else
+    roots_phase<1>(P, org, tau, pos);
   for (int t = tid; t <= r; t += kIT) zh[t] = 0.0;
   __syncthreads();
   for (int q = tid; q < P.na; q += kIT) zh[act[q]] = bsvd::zhat(P, q, org, tau);
   const int ncand = P.p_active ? r + 1 : r;
   for (int t = tid; t < ncand; t += kIT) sg[t] = bsvd::cand_sigma(P, pos, org, tau, t);
   __syncthreads();
+  // output column c (descending singular values) comes from candidate colsrc[c]
+  for (int t = tid; t < ncand; t += kIT) colsrc[bsvd::cand_rank(sg, ncand, t)] = t;
+  __syncthreads();
   if (tid == 0) {
-    double mn = sg[0];
-    for (int t = 1; t < ncand; ++t) mn = fmin(mn, sg[t]);
+    const double mn = ncand > 0 ? sg[colsrc[ncand - 1]] : 0.0;
     int keep = ncand;
     if (keep > 0 && mn < eps_sv) --keep;
     if (keep > r_max) keep = r_max;
@@ -214,30 +347,98 @@ __device__ void bordered_step(int r, int r_max, int64_t m_max, double eps_svd, d
   }
   __syncthreads();
   const int keep = s_keep;
-  for (int t = tid; t < ncand; t += kIT) {
-    const int c = bsvd::cand_rank(sg, ncand, t);
-    if (c >= keep) continue;
-    bsvd::fill_column(P, zh, pos, org, tau, t, UqT + c, VqT + c, ldq);
-    s[c] = sg[t];
+  for (int c = tid; c < keep; c += kIT) s[c] = sg[colsrc[c]];
+  // norms of the unnormalised vectors, a group of kGrp lanes per column
+  const int grp = tid / kGrp, gl = tid % kGrp;
+  for (int c = grp; c < keep; c += kIT / kGrp) {
+    const int t = colsrc[c];
+    double nu = 1.0, nv = 1.0, w = 0.0;
+    if (pos[t] >= 0) {
+      const int k = pos[t];
+      nu = 0.0;
+      nv = 0.0;
+      for (int q = gl; q < n; q += kGrp) {
+        double a, b;
+        bsvd::vec_entry(P, zh, org[k], tau[k], q, a, b);
+        nu += a * a;
+        nv += b * b;
+      }
+      GroupSum<kGrp>{}(nu, nv, w);
+    }
+    if (gl == 0) {
+      inu[c] = 1.0 / sqrt(nu);
+      inv[c] = 1.0 / sqrt(nv);
+    }
+  }
+  __syncthreads();
+  // the entries, consecutive threads on consecutive columns of a row of U_q^T / V_q^T
+  for (int e = tid; e < keep * n; e += kIT) {
+    const int q = e / keep, c = e - q * keep;
+    const int t = colsrc[c];
+    double a, b;
+    if (pos[t] < 0) {
+      a = b = (q == t) ? 1.0 : 0.0;
+    } else {
+      const int k = pos[t];
+      bsvd::vec_entry(P, zh, org[k], tau[k], q, a, b);
+      a *= inu[c];
+      b *= inv[c];
+    }
+    UqT[(int64_t)q * ldq + c] = a;
+    VqT[(int64_t)q * ldq + c] = b;
+  }
+  if (P.nrot > 0) {
+    // undo the deflation rotations, one thread per column
+    __threadfence_block();
+    __syncthreads();
+    for (int c = tid; c < keep; c += kIT) {
+      bsvd::unrotate(P, UqT + c, ldq);
+      bsvd::unrotate(P, VqT + c, ldq);
+    }
   }
 }
 
+// res -= W l2 over the workgroup's rows; partial of ||res||^2 in part[b].
 __global__ __launch_bounds__(kIT) void isvd_sub2_kernel(const double* __restrict__ W, int64_t N_s, int64_t rows_pb,
-                                                        int32_t* state, const double* l1, const double* l2,
-                                                        double* res, double* part, int width, double* scal,
-                                                        double* s, double* UqT, double* VqT, int r_max,
-                                                        int64_t m_max, double eps_svd, double eps_sv) {
+                                                        const int32_t* state, const double* l2, double* res,
+                                                        double* part) {
   __shared__ double sl[kIsvdMaxRank];
   const int r = state[S_R];
   for (int c = threadIdx.x; c < r; c += kIT) sl[c] = l2[c];
   __syncthreads();
   const int64_t row0 = (int64_t)blockIdx.x * rows_pb, row1 = min(row0 + rows_pb, N_s);
   const double nn = block_sum(subtract_block(W, N_s, r, sl, res, res, row0, row1));
-  if (threadIdx.x == 0) part[(int64_t)blockIdx.x * width] = nn;
-  if (!last_to_arrive(state + S_CTR_C, gridDim.x)) return;
+  if (threadIdx.x == 0) part[blockIdx.x] = nn;
+}
+
+// p = ||res|| from the partials, then the step's decisions and the bordered SVD (one workgroup).
+__global__ __launch_bounds__(kIT) void isvd_svd_kernel(const double* part, int G, int32_t* state, const double* l1,
+                                                       const double* l2, double* scal, double* s, double* UqT,
+                                                       double* VqT, int r_max, int64_t m_max, double eps_svd,
+                                                       double eps_sv) {
   double p2 = 0.0;
-  for (int b = threadIdx.x; b < (int)gridDim.x; b += kIT) p2 += part[(int64_t)b * width];
+  for (int b = threadIdx.x; b < G; b += kIT) p2 += part[b];
   p2 = block_sum(p2);
+  if (threadIdx.x == 0) scal[C_P2] = p2;
+  bordered_step(state[S_R], r_max, m_max, eps_svd, eps_sv, p2, l1, l2, s, UqT, VqT, r_max + 1, scal, state);
+}
+
+// The whole front of a step for a short snapshot (N_s up to kFrontRows), in
+// one workgroup: l1 = W^T u, res = u - W l1, l2 = W^T res, res -= W l2,
+// p = ||res||, then the bordered SVD.
+__global__ __launch_bounds__(kIT) void isvd_front_kernel(const double* __restrict__ W, int64_t N_s,
+                                                         const double* __restrict__ u, int32_t* state, double* res,
+                                                         double* scal, double* s, double* UqT, double* VqT, int r_max,
+                                                         int64_t m_max, double eps_svd, double eps_sv) {
+  __shared__ double l1[kIsvdMaxRank], l2[kIsvdMaxRank];
+  const int r = state[S_R];
+  block_dots(W, N_s, r, u, 0, N_s, l1, 1);
+  __syncthreads();
+  subtract_block(W, N_s, r, l1, u, res, 0, N_s);
+  __syncthreads();
+  block_dots(W, N_s, r, res, 0, N_s, l2, 1);
+  __syncthreads();
+  const double p2 = block_sum(subtract_block(W, N_s, r, l2, res, res, 0, N_s));
   if (threadIdx.x == 0) scal[C_P2] = p2;
   bordered_step(r, r_max, m_max, eps_svd, eps_sv, p2, l1, l2, s, UqT, VqT, r_max + 1, scal, state);
 }
@@ -250,16 +451,17 @@ __device__ void apply_rows(double* __restrict__ X, int64_t ldx, int64_t row0, in
                            const double* __restrict__ MT, int ldq, Extra extra, double* tile) {
   const int tid = threadIdx.x;
   const int n_in = r + 1;
-  for (int e = tid; e < n_in * kApplyRows; e += kIT) {
-    const int j = e / kApplyRows, i = e % kApplyRows;
-    const int64_t row = row0 + i;
-    double v = 0.0;
-    if (row < row1) v = j < r ? X[row + (int64_t)j * ldx] : extra(row);
-    tile[e] = v;
-  }
-  __syncthreads();
   const int lane = tid & 63, wave = tid >> 6;
   const int64_t row = row0 + lane;
+  // one row per lane, the waves over the columns (independent loads in flight)
+  if (row < row1) {
+#pragma unroll 4
+    for (int j = wave; j < r; j += kNW) tile[j * kApplyRows + lane] = X[row + (int64_t)j * ldx];
+    if (wave == 0) tile[r * kApplyRows + lane] = extra(row);
+  } else {
+    for (int j = wave; j < n_in; j += kNW) tile[j * kApplyRows + lane] = 0.0;
+  }
+  __syncthreads();
   for (int cb = wave * kColPass; cb < rnew; cb += kNW * kColPass) {
     const int cbu = __builtin_amdgcn_readfirstlane(cb);
     double acc[kColPass];
@@ -279,11 +481,10 @@ __device__ void apply_rows(double* __restrict__ X, int64_t ldx, int64_t row0, in
   }
 }
 
-__global__ __launch_bounds__(kIT) void isvd_apply_w_kernel(double* __restrict__ W, int64_t N_s, int32_t* state,
-                                                           const double* __restrict__ res,
+__global__ __launch_bounds__(kIT) void isvd_apply_w_kernel(double* __restrict__ W, int64_t N_s,
+                                                           const int32_t* state, const double* __restrict__ res,
                                                            const double* __restrict__ scal,
-                                                           const double* __restrict__ UqT, int ldq, double* part,
-                                                           double orth_tol) {
+                                                           const double* __restrict__ UqT, int ldq, double* part) {
   extern __shared__ __align__(16) double tile[];
   const int r = state[S_R], rnew = state[S_RNEW];
   const bool noop = state[S_MODE] == M_NOOP;
@@ -301,11 +502,6 @@ __global__ __launch_bounds__(kIT) void isvd_apply_w_kernel(double* __restrict__ 
   }
   v = block_sum(v);
   if (threadIdx.x == 0) part[blockIdx.x] = v;
-  if (!last_to_arrive(state + S_CTR_E, gridDim.x)) return;
-  double t = 0.0;
-  for (int b = threadIdx.x; b < (int)gridDim.x; b += kIT) t += part[b];
-  t = block_sum(t);
-  if (threadIdx.x == 0) state[S_ORTH] = (!noop && rnew > 1 && fabs(t) > orth_tol) ? 1 : 0;
 }
 
 // Q factor of W (N_s x n) with a positive diagonal of R, in place: classical
@@ -343,9 +539,9 @@ __device__ void orthonormalise(double* __restrict__ W, int64_t N_s, int n) {
   }
 }
 
-__global__ __launch_bounds__(kIT) void isvd_apply_v_kernel(double* __restrict__ V, int64_t m_max, int32_t* state,
-                                                           const double* __restrict__ VqT, int ldq,
-                                                           double* __restrict__ W, int64_t N_s) {
+__global__ __launch_bounds__(kIT) void isvd_apply_v_kernel(double* __restrict__ V, int64_t m_max,
+                                                           const int32_t* state, const double* __restrict__ VqT,
+                                                           int ldq) {
   extern __shared__ __align__(16) double tile[];
   const int r = state[S_R], rnew = state[S_RNEW];
   const bool noop = state[S_MODE] == M_NOOP;
@@ -353,17 +549,29 @@ __global__ __launch_bounds__(kIT) void isvd_apply_v_kernel(double* __restrict__ 
   const int64_t row0 = (int64_t)blockIdx.x * kApplyRows, row1 = min(row0 + kApplyRows, k + 1);
   if (!noop && rnew > 0 && row0 < row1)
     apply_rows(V, m_max, row0, row1, r, rnew, VqT, ldq, [&](int64_t row) { return row == k ? 1.0 : 0.0; }, tile);
-  if (!last_to_arrive(state + S_CTR_F, gridDim.x)) return;
-  if (noop) {
-    if (threadIdx.x == 0) state[S_REFUSED] += 1;
-    return;
-  }
-  if (state[S_ORTH]) orthonormalise(W, N_s, rnew);
+}
+
+// End of a step (one workgroup): the orthogonality test from the W update's
+// partials, the re-orthonormalisation when it fails, and the new state.
+__global__ __launch_bounds__(kIT) void isvd_commit_kernel(double* __restrict__ W, int64_t N_s, int32_t* state,
+                                                          const double* part, int GW, double orth_tol) {
+  __shared__ int s_orth;
+  const int rnew = state[S_RNEW];
+  const bool noop = state[S_MODE] == M_NOOP;
+  double t = 0.0;
+  for (int b = threadIdx.x; b < GW; b += kIT) t += part[b];
+  t = block_sum(t);
+  if (threadIdx.x == 0) s_orth = (!noop && rnew > 1 && fabs(t) > orth_tol) ? 1 : 0;
+  __syncthreads();
+  if (s_orth) orthonormalise(W, N_s, rnew);
   if (threadIdx.x == 0) {
-    if (state[S_ORTH]) state[S_QR] += 1;
-    state[S_ORTH] = 0;
-    state[S_R] = rnew;
-    state[S_K] = (int32_t)(k + 1);
+    if (noop) {
+      state[S_REFUSED] += 1;
+    } else {
+      if (s_orth) state[S_QR] += 1;
+      state[S_R] = rnew;
+      state[S_K] += 1;
+    }
   }
 }
 
@@ -374,9 +582,9 @@ __global__ void isvd_reset_kernel(int32_t* state) {
 }  // namespace
 
 int64_t isvd_rows_per_block(int64_t N_s) {
-  // row blocks of 512 rows, fewer and longer past 1024 blocks so the final
-  // reductions stay short
-  int64_t rpb = 512;
+  // row blocks of 128 rows (two per lane and column), longer past 1024 blocks
+  // so the final reductions stay short
+  int64_t rpb = 128;
   const int64_t nb = (N_s + rpb - 1) / rpb;
   if (nb > 1024) rpb = ((N_s + 1023) / 1024 + 63) / 64 * 64;
   return rpb;
@@ -395,9 +603,7 @@ hipError_t launch_isvd_reset(int32_t* state, hipStream_t s) {
 }
 
 hipError_t launch_isvd_step(const IsvdArgs& a, const double* u, hipStream_t s) {
-  const int64_t rpb = isvd_rows_per_block(a.N_s);
-  const int G = isvd_row_blocks(a.N_s);
-  const int width = a.r_max + 1, ldq = a.r_max + 1;
+  const int ldq = a.r_max + 1;
   const size_t lds = isvd_apply_lds_bytes(a.r_max);
   if (lds > 64 * 1024 && !g_capturing) {
     hipError_t e = hipFuncSetAttribute((const void*)isvd_apply_w_kernel,
@@ -407,18 +613,29 @@ hipError_t launch_isvd_step(const IsvdArgs& a, const double* u, hipStream_t s) {
                               (int)lds);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(isvd_dots_kernel, dim3(G), dim3(kIT), 0, s, a.W, a.N_s, rpb, u, a.state, a.part, width, a.l1);
-  hipLaunchKernelGGL(isvd_sub1_kernel, dim3(G), dim3(kIT), 0, s, a.W, a.N_s, rpb, u, a.state, a.l1, a.res, a.part,
-                     width, a.l2);
-  hipLaunchKernelGGL(isvd_sub2_kernel, dim3(G), dim3(kIT), 0, s, a.W, a.N_s, rpb, a.state, a.l1, a.l2, a.res,
-                     a.part, width, a.scal, a.s, a.UqT, a.VqT, a.r_max, a.m_max, a.eps_svd, a.eps_sv);
+  if (a.N_s <= kFrontRows) {
+    hipLaunchKernelGGL(isvd_front_kernel, dim3(1), dim3(kIT), 0, s, a.W, a.N_s, u, a.state, a.res, a.scal, a.s,
+                       a.UqT, a.VqT, a.r_max, a.m_max, a.eps_svd, a.eps_sv);
+  } else {
+    // row blocks with their partials, each reduction a launch of its own (a
+    // kernel boundary orders the workgroups' writes without device-wide fences)
+    const int64_t rpb = isvd_rows_per_block(a.N_s);
+    const int G = isvd_row_blocks(a.N_s);
+    hipLaunchKernelGGL(isvd_dots_kernel, dim3(G), dim3(kIT), 0, s, a.W, a.N_s, rpb, u, a.state, a.part);
+    hipLaunchKernelGGL(isvd_reduce_kernel, dim3(1), dim3(kRT), 0, s, a.part, G, a.state, a.l1);
+    hipLaunchKernelGGL(isvd_sub1_kernel, dim3(G), dim3(kIT), 0, s, a.W, a.N_s, rpb, u, a.state, a.l1, a.res, a.part);
+    hipLaunchKernelGGL(isvd_reduce_kernel, dim3(1), dim3(kRT), 0, s, a.part, G, a.state, a.l2);
+    hipLaunchKernelGGL(isvd_sub2_kernel, dim3(G), dim3(kIT), 0, s, a.W, a.N_s, rpb, a.state, a.l2, a.res, a.part);
+    hipLaunchKernelGGL(isvd_svd_kernel, dim3(1), dim3(kIT), 0, s, a.part, G, a.state, a.l1, a.l2, a.scal, a.s,
+                       a.UqT, a.VqT, a.r_max, a.m_max, a.eps_svd, a.eps_sv);
+  }
   const int GW = (int)((a.N_s + kApplyRows - 1) / kApplyRows);
   const double orth_tol = fmin(a.eps_svd, bsvd::kEps * (double)a.N_s);
   hipLaunchKernelGGL(isvd_apply_w_kernel, dim3(GW), dim3(kIT), lds, s, a.W, a.N_s, a.state, a.res, a.scal, a.UqT,
-                     ldq, a.part, orth_tol);
+                     ldq, a.part);
   const int GV = (int)((a.m_max + kApplyRows - 1) / kApplyRows);
-  hipLaunchKernelGGL(isvd_apply_v_kernel, dim3(GV), dim3(kIT), lds, s, a.V, a.m_max, a.state, a.VqT, ldq, a.W,
-                     a.N_s);
+  hipLaunchKernelGGL(isvd_apply_v_kernel, dim3(GV), dim3(kIT), lds, s, a.V, a.m_max, a.state, a.VqT, ldq);
+  hipLaunchKernelGGL(isvd_commit_kernel, dim3(1), dim3(kIT), 0, s, a.W, a.N_s, a.state, a.part, GW, orth_tol);
   return hipGetLastError();
 }
 
