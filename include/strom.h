@@ -163,7 +163,7 @@ st_status st_rom_layout(const st_rom_desc* d, st_rom_layout_t* out);
  *          (U = [U_1 ... U_nmu], U_p = [u^(1) ... u^(N_t)] at mu_p).
  *          U_prec = ST_F64 (double) or ST_F32 (float storage).
  * gram_prec  arithmetic of the snapshot Gram: ST_F64 (FP64 MFMA), ST_F32
- *          (FP32 MFMA) or ST_BF16X3 (split-BF16 MFMA, FP32 accumulate).
+ *          (FP32 MFMA) or ST_BF16X3 (split-BF16 MFMA), as st_gram.
  *          The eigen-decomposition and re-orthonormalisation are FP64.
  * n_s      spatial modes, 1 <= n_s <= min(N_s, n_mu N_t).
  * n_t      [host] n_s temporal basis sizes, 1 <= n_t[i] <= N_t.
@@ -219,6 +219,25 @@ st_status st_build_bases(const void* U, int32_t U_prec, int64_t ldU, int64_t N_s
                          int32_t n_s, const int32_t* n_t, int32_t gram_prec, double tau_t,
                          double* Phi_s, double* Phi_t, double* sigma, int32_t* rank_t, double* diag,
                          void* ws, size_t ws_bytes, void* stream);
+
+/* ========================================================================
+ * st_gram - the snapshot Gram of the method of snapshots (Sec. 4.1, the SVD
+ * of Eq. (SVD) through the eigenpairs of U^T U), the first step of
+ * st_build_bases, on its own so that its precision can be examined.
+ *
+ * X        [dev] K x p, column-major with leading dimension ld >= K;
+ *          X_prec ST_F64 (double) or ST_F32 (float storage).
+ * gram_prec ST_F64 (FP64 MFMA), ST_F32 (FP32 MFMA) or ST_BF16X3 (x = hi + lo
+ *          in BF16, hi*hi + hi*lo + lo*hi on BF16 MFMA); both reduced
+ *          precisions accumulate in FP32 over 1024-term stretches of K and
+ *          sum the stretches in FP64.
+ * G        [dev] p x p output, column-major (ld p), full symmetric matrix.
+ * Workspace st_gram_workspace(K, p) bytes (split-K partial sums).
+ * Limits: 1 <= p <= 65535, K >= 1.
+ * ====================================================================== */
+size_t st_gram_workspace(int64_t K, int32_t p);
+st_status st_gram(const void* X, int32_t X_prec, int64_t ld, int64_t K, int32_t p, int32_t gram_prec, double* G,
+                  void* ws, size_t ws_bytes, void* stream);
 
 /* ========================================================================
  * st_assemble - offline reduced operators.

@@ -1189,6 +1189,23 @@ static IsvdArgs isvd_carve(int64_t N_s, int32_t r_max, void* ws, size_t* total) 
   return a;
 }
 
+size_t st_gram_workspace(int64_t K, int32_t p) {
+  if (K < 1 || p < 1 || p > 65535) return 0;
+  return align_up(sizeof(double) * gram_partial_elems(K, p));
+}
+
+st_status st_gram(const void* X, int32_t X_prec, int64_t ld, int64_t K, int32_t p, int32_t gram_prec, double* G,
+                  void* ws, size_t ws_bytes, void* stream) {
+  if (!X || !G || !ws || K < 1 || p < 1 || ld < K) return ST_EINVAL;
+  if (X_prec != ST_F64 && X_prec != ST_F32) return ST_EINVAL;
+  if (gram_prec != ST_F64 && gram_prec != ST_F32 && gram_prec != ST_BF16X3) return ST_EINVAL;
+  if (p > 65535) return ST_EUNSUPPORTED;
+  if (ws_bytes < st_gram_workspace(K, p)) return ST_EWORKSPACE;
+  ST_TRY(launch_gram(K, p, X, X_prec, 1, ld, gram_prec, G, static_cast<double*>(ws), ws_bytes / sizeof(double),
+                     static_cast<hipStream_t>(stream)));
+  return ST_OK;
+}
+
 size_t st_isvd_workspace(int64_t N_s, int32_t r_max) {
   if (N_s < 1 || r_max < 1 || r_max > kIsvdMaxRank) return 0;
   size_t total = 0;

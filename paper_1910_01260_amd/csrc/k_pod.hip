@@ -85,6 +85,7 @@ typedef short s4 __attribute__((ext_vector_type(4)));
 
 constexpr int kGT = 64;   // output tile
 constexpr int kGK = 32;   // K chunk
+constexpr int kFlushChunks = 32;  // FP32 Gram accumulators move to FP64 every 32 chunks (1024 terms)
 
 __device__ inline void tile_of(int t, int& ti, int& tj) {
   int i = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
@@ -156,7 +157,8 @@ __global__ __launch_bounds__(256) void gram_f64_kernel(int64_t K, int p, const I
       }
 }
 
-// FP32 MFMA (ST_F32) or split-BF16 (ST_BF16X3): inputs rounded to FP32, products accumulated in FP32.
+// FP32 MFMA (ST_F32) or split-BF16 (ST_BF16X3): inputs rounded to FP32, products accumulated in FP32 over
+// 1024-term stretches of K, which are summed in FP64.
 __device__ inline short bf16_rne(float f) {
   uint32_t u = __float_as_uint(f);
   u += 0x7FFFu + ((u >> 16) & 1u);
@@ -178,9 +180,27 @@ __global__ __launch_bounds__(256) void gram_f32_kernel(int64_t K, int p, const I
   const int wi = wave >> 1, wj = wave & 1;
   const int li = lane & 15, lk = lane >> 4;
   f4 acc[2][2];
+  double acc64[2][2][4];
   for (int x = 0; x < 2; ++x)
-    for (int y = 0; y < 2; ++y) acc[x][y] = f4{0.f, 0.f, 0.f, 0.f};
+    for (int y = 0; y < 2; ++y) {
+      acc[x][y] = f4{0.f, 0.f, 0.f, 0.f};
+      for (int r = 0; r < 4; ++r) acc64[x][y][r] = 0.0;
+    }
+  int chunk = 0;
   for (int64_t k0 = kbeg; k0 < kend; k0 += kGK) {
+    if (++chunk == kFlushChunks) {
+      // FP32 accumulation only within kFlushChunks * kGK terms; the chunks add up in FP64
+      chunk = 0;
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            acc64[x][y][r] += (double)acc[x][y][r];
+            acc[x][y][r] = 0.f;
+          }
+    }
     gram_stage<InT>(X, K, p, ks, ms, k0, kend, a0, Xa, nullptr);
     if (ti != tj) gram_stage<InT>(X, K, p, ks, ms, k0, kend, b0, Xb, nullptr);
     __syncthreads();
@@ -242,7 +262,7 @@ __global__ __launch_bounds__(256) void gram_f32_kernel(int64_t K, int p, const I
       for (int r = 0; r < 4; ++r) {
         const int a = a0 + wi * 32 + x * 16 + 4 * lk + r;  // FP32 accumulator row = 4(lane/16) + r
         const int b = b0 + wj * 32 + y * 16 + li;
-        if (a < p && b < p) out[a + (int64_t)b * p] = (double)acc[x][y][r];
+        if (a < p && b < p) out[a + (int64_t)b * p] = acc64[x][y][r] + (double)acc[x][y][r];
       }
 }
 

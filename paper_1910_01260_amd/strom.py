@@ -97,6 +97,8 @@ _SIGNATURES = {
     "st_spatial_march": (_I32, [ctypes.POINTER(st_rom_desc), _P, _I32, _P, _P, _P, _P, _I32, _P, _P, _P, _P, _P]),
     "st_project_workspace": (_SZ, [_I64, _I32, _I32]),
     "st_project": (_I32, [_I64, _I32, _P, _I32, _P, _P, _P, _SZ, _P]),
+    "st_gram_workspace": (_SZ, [_I64, _I32]),
+    "st_gram": (_I32, [_P, _I32, _I64, _I64, _I32, _I32, _P, _P, _SZ, _P]),
     "st_isvd_workspace": (_SZ, [_I64, _I32]),
     "st_isvd_reset": (_I32, [_P, _P]),
     "st_isvd_update": (_I32, [_P, _I64, _I64, _I32, _I32, _I64, _D, _D, _P, _P, _P, _P, _P, _SZ, _P]),
@@ -648,3 +650,20 @@ class IncrementalSVD:
                                    self.m_max, N_t, n_mu, n_s, nt.ctypes.data, float(tau_t), _ptr(Phi_s),
                                    _ptr(Phi_t), _ptr(sigma), _ptr(rank), _ptr(ws), nb, _stream()), "st_isvd_bases")
         return Phi_s.T, Phi_t.T, sigma, rank
+
+
+def st_gram(X: torch.Tensor, gram_prec: int = ST_F64) -> torch.Tensor:
+    """G = X^T X (p x p, FP64) of a column-major K x p device matrix (float32 or
+    float64), in the given arithmetic."""
+    if X.dim() != 2 or X.stride(0) != 1:
+        raise ValueError("X must be column-major (X.T contiguous)")
+    K, p = X.shape
+    prec = ST_F64 if X.dtype == torch.float64 else ST_F32
+    nb = lib().st_gram_workspace(K, p)
+    if nb == 0:
+        raise StromError(-1, "st_gram_workspace")
+    ws = torch.empty(nb, dtype=torch.uint8, device=X.device)
+    G = torch.empty((p, p), dtype=torch.float64, device=X.device)
+    _check(lib().st_gram(ctypes.c_void_p(X.data_ptr()), prec, max(X.stride(1), K), K, p, gram_prec, _ptr(G), _ptr(ws),
+                         nb, _stream()), "st_gram")
+    return G

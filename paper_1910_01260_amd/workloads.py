@@ -302,6 +302,47 @@ def advdiff3d(n: int = 128, N_t: int = 500, n_train: int = 16,
     )
 
 
+def periodic_snapshots_device(prob: Problem, n: int, mus: Optional[Sequence] = None, dtype=None,
+                              device: str = "cuda"):
+    """Snapshot matrix of a periodic, constant-coefficient stencil problem on an
+    n^3 grid (``advdiff3d``), computed on the GPU: N_s x (n_mu N_t), column-major
+    (a transposed contiguous tensor), parameter-major, time inside, u^(0) excluded.
+
+    Each backward-Euler step (I - dt_k A(mu)) u^(k) = u^(k-1) is solved exactly
+    in Fourier space: a translation-invariant operator is diagonal in the
+    discrete Fourier basis, with symbol lambda(k) = sum_j A[0, j]
+    exp(2 pi i k . x_j / n) read off the first CSR row of each affine term, so
+    u^(k) = IFFT(FFT(u^(k-1)) / (1 - dt_k lambda_mu)).  The march runs in FP64
+    (torch.fft) and the snapshots are stored in ``dtype`` (float32 by default).
+    This is the user's full-order simulator, as ``march`` is; it needs the
+    operators to be periodic stencils (it is checked against ``march``)."""
+    import torch
+
+    dtype = torch.float32 if dtype is None else dtype
+    mus = prob.train_mu if mus is None else np.atleast_2d(mus)
+    N = n ** 3
+    assert prob.N_s == N and prob.Qf == 0
+    kk = torch.arange(n, device=device, dtype=torch.float64)
+    kz, ky, kx = torch.meshgrid(kk, kk, kk, indexing="ij")
+    symbols = []
+    for A in prob.terms:
+        A = sp.csr_matrix(A)
+        lam = torch.zeros((n, n, n), dtype=torch.complex128, device=device)
+        for j, a in zip(A.indices[A.indptr[0]:A.indptr[1]], A.data[A.indptr[0]:A.indptr[1]]):
+            dx, dy, dz = j % n, (j // n) % n, j // (n * n)
+            lam += float(a) * torch.exp(1j * (2.0 * np.pi / n) * (kx * dx + ky * dy + kz * dz))
+        symbols.append(lam)
+    U = torch.empty((len(mus) * prob.N_t, N), dtype=dtype, device=device)
+    for p, mu in enumerate(mus):
+        th = prob.theta_A(np.asarray(mu, dtype=np.float64))
+        lam = sum(float(th[q]) * symbols[q] for q in range(prob.Q))
+        u_hat = torch.fft.fftn(torch.tensor(prob.initial(mu).reshape(n, n, n), device=device))
+        for k in range(prob.N_t):
+            u_hat = u_hat / (1.0 - float(prob.dt[k]) * lam)
+            U[p * prob.N_t + k] = torch.fft.ifftn(u_hat).real.reshape(N).to(dtype)
+    return U.T
+
+
 # ----------------------------------------------------------------------------
 # parameters, profiles, snapshots
 # ----------------------------------------------------------------------------
