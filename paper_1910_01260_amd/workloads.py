@@ -20,7 +20,9 @@ Model problems (all synthetic, seeded, shaped like the paper's workloads):
   whose code and data are not public.
 * ``transport2d_absorber`` the same with a third parameter: extra
   absorption in a central box.
-* ``advdiff3d``   3-D periodic advection-diffusion on a 7-point stencil.
+* ``advdiff3d``   3-D periodic advection-diffusion on a 7-point stencil; its
+  snapshots at 128^3 come from ``periodic_snapshots_device`` (the same
+  backward-Euler march, solved exactly in Fourier space on the GPU).
 """
 from __future__ import annotations
 
