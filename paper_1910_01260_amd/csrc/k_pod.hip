@@ -95,17 +95,32 @@ __device__ inline void tile_of(int t, int& ti, int& tj) {
   tj = t - i * (i + 1) / 2;
 }
 
+// A K-chunk of one 64-column panel: each of the 256 threads holds kStagePer
+// entries in registers (fetched for the next chunk while the matrix cores work
+// on the current one), then writes them to LDS as [k][column].
+constexpr int kStagePer = kGK * kGT / 256;
+
 template <typename InT>
-__device__ inline void gram_stage(const InT* __restrict__ X, int64_t K, int p, int64_t ks, int64_t ms, int64_t k0,
-                                  int64_t kend, int a0, float (*dst32)[kGT + 4], double (*dst64)[kGT + 1]) {
-  for (int e = threadIdx.x; e < kGK * kGT; e += blockDim.x) {
+__device__ inline void gram_fetch(const InT* __restrict__ X, int p, int64_t ks, int64_t ms, int64_t k0, int64_t kend,
+                                  int a0, InT (&v)[kStagePer]) {
+#pragma unroll
+  for (int i = 0; i < kStagePer; ++i) {
+    const int e = threadIdx.x + i * 256;
     int kk, a;
     if (ks == 1) { kk = e % kGK; a = e / kGK; } else { a = e % kGT; kk = e / kGT; }
     const int64_t k = k0 + kk;
-    double v = 0.0;
-    if (k < kend && a0 + a < p) v = (double)X[k * ks + (int64_t)(a0 + a) * ms];
-    if (dst64) dst64[kk][a] = v;
-    else dst32[kk][a] = (float)v;
+    v[i] = (k < kend && a0 + a < p) ? X[k * ks + (int64_t)(a0 + a) * ms] : InT(0);
+  }
+}
+
+template <typename InT, typename DstT, int LD>
+__device__ inline void gram_put(const InT (&v)[kStagePer], int64_t ks, DstT (*dst)[LD]) {
+#pragma unroll
+  for (int i = 0; i < kStagePer; ++i) {
+    const int e = threadIdx.x + i * 256;
+    int kk, a;
+    if (ks == 1) { kk = e % kGK; a = e / kGK; } else { a = e % kGT; kk = e / kGT; }
+    dst[kk][a] = (DstT)v[i];
   }
 }
 
@@ -125,11 +140,19 @@ __global__ __launch_bounds__(256) void gram_f64_kernel(int64_t K, int p, const I
   d4 acc[2][2];
   for (int x = 0; x < 2; ++x)
     for (int y = 0; y < 2; ++y) acc[x][y] = d4{0.0, 0.0, 0.0, 0.0};
+  const bool two = ti != tj;
+  InT va[kStagePer], vb[kStagePer];
+  gram_fetch<InT>(X, p, ks, ms, kbeg, kend, a0, va);
+  if (two) gram_fetch<InT>(X, p, ks, ms, kbeg, kend, b0, vb);
   for (int64_t k0 = kbeg; k0 < kend; k0 += kGK) {
-    gram_stage<InT>(X, K, p, ks, ms, k0, kend, a0, nullptr, Xa);
-    if (ti != tj) gram_stage<InT>(X, K, p, ks, ms, k0, kend, b0, nullptr, Xb);
+    gram_put<InT, double, kGT + 1>(va, ks, Xa);
+    if (two) gram_put<InT, double, kGT + 1>(vb, ks, Xb);
     __syncthreads();
-    double(*B)[kGT + 1] = (ti != tj) ? Xb : Xa;
+    if (k0 + kGK < kend) {  // the next chunk is in flight while this one is multiplied
+      gram_fetch<InT>(X, p, ks, ms, k0 + kGK, kend, a0, va);
+      if (two) gram_fetch<InT>(X, p, ks, ms, k0 + kGK, kend, b0, vb);
+    }
+    double(*B)[kGT + 1] = two ? Xb : Xa;
 #pragma unroll
     for (int kk = 0; kk < kGK; kk += 4) {
       double av[2], bv[2];
@@ -187,6 +210,10 @@ __global__ __launch_bounds__(256) void gram_f32_kernel(int64_t K, int p, const I
       for (int r = 0; r < 4; ++r) acc64[x][y][r] = 0.0;
     }
   int chunk = 0;
+  const bool two = ti != tj;
+  InT va[kStagePer], vb[kStagePer];
+  gram_fetch<InT>(X, p, ks, ms, kbeg, kend, a0, va);
+  if (two) gram_fetch<InT>(X, p, ks, ms, kbeg, kend, b0, vb);
   for (int64_t k0 = kbeg; k0 < kend; k0 += kGK) {
     if (++chunk == kFlushChunks) {
       // FP32 accumulation only within kFlushChunks * kGK terms; the chunks add up in FP64
@@ -201,10 +228,14 @@ __global__ __launch_bounds__(256) void gram_f32_kernel(int64_t K, int p, const I
             acc[x][y][r] = 0.f;
           }
     }
-    gram_stage<InT>(X, K, p, ks, ms, k0, kend, a0, Xa, nullptr);
-    if (ti != tj) gram_stage<InT>(X, K, p, ks, ms, k0, kend, b0, Xb, nullptr);
+    gram_put<InT, float, kGT + 4>(va, ks, Xa);
+    if (two) gram_put<InT, float, kGT + 4>(vb, ks, Xb);
     __syncthreads();
-    float(*B)[kGT + 4] = (ti != tj) ? Xb : Xa;
+    if (k0 + kGK < kend) {  // the next chunk is in flight while this one is multiplied
+      gram_fetch<InT>(X, p, ks, ms, k0 + kGK, kend, a0, va);
+      if (two) gram_fetch<InT>(X, p, ks, ms, k0 + kGK, kend, b0, vb);
+    }
+    float(*B)[kGT + 4] = two ? Xb : Xa;
     if (!SPLIT) {
 #pragma unroll
       for (int kk = 0; kk < kGK; kk += 4) {
