@@ -405,6 +405,16 @@ st_status st_mlp_grad(const st_mlp_shape* s, const float* params, int32_t batch,
 st_status st_mlp_adam(int64_t n, float* params, const float* grads, float* m, float* v, int32_t step, float lr,
                       float beta1, float beta2, float eps, void* stream);
 
+/* Output standardisation of the training targets: C [dev] n x d row-major
+ * FP64 coefficients (one training solve per row).  st_mlp_colstats writes
+ * mean [dev, d] and scale [dev, d], the per-column mean and population
+ * standard deviation (1 where it is zero); st_mlp_standardize writes
+ * T [dev] n x d FP32 = (C - mean) / scale, the network's training targets
+ * (the certificate maps outputs y back to c = mean + scale * y). */
+st_status st_mlp_colstats(int32_t n, int32_t d, const double* C, double* mean, double* scale, void* stream);
+st_status st_mlp_standardize(int32_t n, int32_t d, const double* C, const double* mean, const double* scale, float* T,
+                             void* stream);
+
 /* Residual certificate of surrogate coefficients for full-width queries:
  * c = mean + scale * y (FP64; y = row q of Y, n outputs), r = b(mu) -
  * Ahat_st(mu) c in FP64 from the ROM pieces (Sec. 5.2, Eq. (stresidual) in

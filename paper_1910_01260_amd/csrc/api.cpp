@@ -1007,6 +1007,19 @@ st_status st_mlp_adam(int64_t n, float* params, const float* grads, float* m, fl
   return ST_OK;
 }
 
+st_status st_mlp_colstats(int32_t n, int32_t d, const double* C, double* mean, double* scale, void* stream) {
+  if (n < 1 || d < 1 || !C || !mean || !scale) return ST_EINVAL;
+  ST_TRY(mlp_colstats(n, d, C, mean, scale, static_cast<hipStream_t>(stream)));
+  return ST_OK;
+}
+
+st_status st_mlp_standardize(int32_t n, int32_t d, const double* C, const double* mean, const double* scale, float* T,
+                             void* stream) {
+  if (n < 0 || d < 1 || (n > 0 && (!C || !mean || !scale || !T))) return ST_EINVAL;
+  ST_TRY(mlp_standardize(n, d, C, mean, scale, T, static_cast<hipStream_t>(stream)));
+  return ST_OK;
+}
+
 size_t st_surrogate_check_workspace(const st_rom_desc* d, int32_t n_q) {
   if (!desc_ok(d) || n_q < 0) return 0;
   const size_t n = (size_t)total_nt(d);

@@ -210,6 +210,9 @@ hipError_t mlp_forward(const st_mlp_shape& s, const float* params, int32_t batch
 hipError_t mlp_backward(const st_mlp_shape& s, const float* params, int32_t batch, const float* X, const float* acts,
                         float* dY, float* grads, float* tmp0, float* tmp1, hipStream_t st);
 hipError_t mlp_mse(int64_t n, const float* Y, const float* T, float* dY, float* partial, float* loss, hipStream_t st);
+hipError_t mlp_colstats(int n, int d, const double* C, double* mean, double* scale, hipStream_t st);
+hipError_t mlp_standardize(int n, int d, const double* C, const double* mean, const double* scale, float* T,
+                           hipStream_t st);
 hipError_t adam(int64_t n, float* p, const float* g, float* m, float* v, int32_t t, float lr, float b1, float b2,
                 float eps, hipStream_t st);
 

@@ -150,6 +150,35 @@ __global__ void adam_kernel(int64_t n, float* __restrict__ p, const float* __res
   p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
 }
 
+// Per-column mean and population standard deviation of an n x d row-major FP64
+// matrix, two passes per column (one thread per column: consecutive threads
+// read consecutive entries of a row); a zero deviation becomes 1.
+__global__ void colstats_kernel(int n, int d, const double* __restrict__ C, double* __restrict__ mean,
+                                double* __restrict__ scale) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= d) return;
+  double s = 0.0;
+  for (int i = 0; i < n; ++i) s += C[(int64_t)i * d + j];
+  const double mu = s / (double)n;
+  double v = 0.0;
+  for (int i = 0; i < n; ++i) {
+    const double e = C[(int64_t)i * d + j] - mu;
+    v = fma(e, e, v);
+  }
+  const double sd = sqrt(v / (double)n);
+  mean[j] = mu;
+  scale[j] = sd > 0.0 ? sd : 1.0;
+}
+
+// T = FP32((C - mean) / scale), elementwise over n x d row-major
+__global__ void standardize_kernel(int64_t nd, int d, const double* __restrict__ C, const double* __restrict__ mean,
+                                   const double* __restrict__ scale, float* __restrict__ T) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nd) return;
+  const int j = (int)(e % d);
+  T[e] = (float)((C[e] - mean[j]) / scale[j]);
+}
+
 template <int EPI>
 hipError_t gemm(int M, int N, int K, const float* A, int64_t sam, int64_t sak, const float* B, int64_t sbk,
                 int64_t sbn, float* C, int64_t ldc, const float* bias, float* aux, int64_t ldaux, hipStream_t s) {
@@ -254,6 +283,20 @@ hipError_t mlp_mse(int64_t n, const float* Y, const float* T, float* dY, float* 
 }
 
 size_t mlp_mse_partials(int64_t n) { return (size_t)((n + 255) / 256); }
+
+hipError_t mlp_colstats(int n, int d, const double* C, double* mean, double* scale, hipStream_t st) {
+  hipLaunchKernelGGL(colstats_kernel, dim3((d + 255) / 256), dim3(256), 0, st, n, d, C, mean, scale);
+  return hipGetLastError();
+}
+
+hipError_t mlp_standardize(int n, int d, const double* C, const double* mean, const double* scale, float* T,
+                           hipStream_t st) {
+  const int64_t nd = (int64_t)n * d;
+  if (nd == 0) return hipSuccess;
+  hipLaunchKernelGGL(standardize_kernel, dim3((unsigned)((nd + 255) / 256)), dim3(256), 0, st, nd, d, C, mean, scale,
+                     T);
+  return hipGetLastError();
+}
 
 hipError_t adam(int64_t n, float* p, const float* g, float* m, float* v, int32_t t, float lr, float b1, float b2,
                 float eps, hipStream_t st) {

@@ -85,6 +85,8 @@ _SIGNATURES = {
     "st_mlp_grad": (_I32, [_P, _P, _I32, _P, _P, _P, _P, _P, _SZ, _P]),
     "st_mlp_adam": (_I32, [_I64, _P, _P, _P, _P, _I32, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                            _P]),
+    "st_mlp_colstats": (_I32, [_I32, _I32, _P, _P, _P, _P]),
+    "st_mlp_standardize": (_I32, [_I32, _I32, _P, _P, _P, _P, _P]),
     "st_surrogate_check_workspace": (_SZ, [ctypes.POINTER(st_rom_desc), _I32]),
     "st_surrogate_check": (_I32, [ctypes.POINTER(st_rom_desc), _P, _I32, _P, _P, _P, _P, _P, _P, _D, _D, _P, _P, _P,
                                   _P, _SZ, _P]),
@@ -667,3 +669,22 @@ def st_gram(X: torch.Tensor, gram_prec: int = ST_F64) -> torch.Tensor:
     _check(lib().st_gram(ctypes.c_void_p(X.data_ptr()), prec, max(X.stride(1), K), K, p, gram_prec, _ptr(G), _ptr(ws),
                          nb, _stream()), "st_gram")
     return G
+
+
+def st_mlp_colstats(C: torch.Tensor):
+    """(mean, scale) per column of the n x d row-major FP64 device matrix C."""
+    C = C.contiguous()
+    n, d = C.shape
+    mean = torch.empty(d, dtype=torch.float64, device=C.device)
+    scale = torch.empty(d, dtype=torch.float64, device=C.device)
+    _check(lib().st_mlp_colstats(n, d, _ptr(C), _ptr(mean), _ptr(scale), _stream()), "st_mlp_colstats")
+    return mean, scale
+
+
+def st_mlp_standardize(C: torch.Tensor, mean: torch.Tensor, scale: torch.Tensor) -> torch.Tensor:
+    """FP32 (C - mean) / scale of the n x d row-major FP64 device matrix C."""
+    C = C.contiguous()
+    n, d = C.shape
+    T = torch.empty((n, d), dtype=torch.float32, device=C.device)
+    _check(lib().st_mlp_standardize(n, d, _ptr(C), _ptr(mean), _ptr(scale), _ptr(T), _stream()), "st_mlp_standardize")
+    return T

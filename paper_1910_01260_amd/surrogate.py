@@ -28,8 +28,8 @@ from . import strom
 
 def coercivity_floor(N_t: int) -> float:
     """Smallest eigenvalue of tridiag(-1/2, 1, -1/2) of order N_t: a lower bound
-    of lambda_min(sym Ahat_st) when sym(A) <= 0."""
-    return 1.0 - math.cos(math.pi / (N_t + 1))
+    of lambda_min(sym Ahat_st) when sym(A) <= 0 (st_coercivity_floor)."""
+    return strom.st_coercivity_floor(N_t)
 
 
 def scaled_inputs(box_lo, box_hi, mus) -> np.ndarray:
@@ -77,17 +77,16 @@ class Surrogate:
         return self._ws[batch]
 
     # -- standardisation ----------------------------------------------------------
-    def set_standardization(self, C: np.ndarray):
-        """Per-coefficient mean and standard deviation of the training targets (host FP64)."""
-        mean = C.mean(axis=0)
-        scale = C.std(axis=0)
-        scale[scale == 0.0] = 1.0
-        self.mean = torch.tensor(mean, dtype=torch.float64, device=self.device)
-        self.scale = torch.tensor(scale, dtype=torch.float64, device=self.device)
-        self._mean_h, self._scale_h = mean, scale
+    def set_standardization(self, C):
+        """Per-coefficient mean and standard deviation of the training targets
+        (n x d FP64, host or device; st_mlp_colstats)."""
+        C = torch.as_tensor(C, dtype=torch.float64, device=self.device)
+        self.mean, self.scale = strom.st_mlp_colstats(C)
 
-    def standardize(self, C: np.ndarray) -> np.ndarray:
-        return ((C - self._mean_h) / self._scale_h).astype(np.float32)
+    def standardize(self, C) -> torch.Tensor:
+        """FP32 training targets (C - mean) / scale on the device (st_mlp_standardize)."""
+        C = torch.as_tensor(C, dtype=torch.float64, device=self.device)
+        return strom.st_mlp_standardize(C, self.mean, self.scale)
 
     # -- training ------------------------------------------------------------------
     def train_step(self, X: torch.Tensor, T: torch.Tensor, lr: float):
@@ -111,7 +110,7 @@ class Surrogate:
         self.set_standardization(C[tr])
         T_all = self.standardize(C)
         Xv = torch.tensor(X[val], device=self.device)
-        Tv = torch.tensor(T_all[val], device=self.device)
+        Tv = T_all[torch.as_tensor(val, device=self.device)].contiguous()
         batch = min(batch, len(tr))
         n_b = len(tr) // batch
         # one epoch of minibatches lives on the device; reshuffled on the host per epoch
@@ -122,7 +121,7 @@ class Surrogate:
         while step < steps:
             order = tr[rng.permutation(len(tr))[:n_b * batch]]
             Xe.copy_(torch.from_numpy(np.ascontiguousarray(X[order])))
-            Te.copy_(torch.from_numpy(np.ascontiguousarray(T_all[order])))
+            Te.copy_(T_all[torch.as_tensor(order, device=self.device)])
             for b in range(n_b):
                 if step >= steps:
                     break

@@ -294,3 +294,22 @@ def test_surrogate_train_certify_and_fall_back():
     rel = np.linalg.norm(pred - ref, axis=1) / np.linalg.norm(ref, axis=1)
     print(f"  prediction rel err p50 {np.median(rel):.2e} max {rel.max():.2e}")
     assert np.median(rel) < 0.05
+
+
+def test_standardisation_matches_numpy():
+    # st_mlp_colstats / st_mlp_standardize against NumPy's mean, population std and
+    # the FP64 -> FP32 map; a constant column gets scale 1
+    rng = np.random.default_rng(21)
+    C = rng.standard_normal((3001, 37)) * rng.uniform(1e-3, 1e3, 37) + rng.uniform(-5, 5, 37)
+    C[:, 5] = 2.5
+    Cd = torch.tensor(C, device="cuda")
+    mean, scale = strom.st_mlp_colstats(Cd)
+    T = strom.st_mlp_standardize(Cd, mean, scale)
+    torch.cuda.synchronize()
+    m_np, s_np = C.mean(axis=0), C.std(axis=0)
+    s_np[s_np == 0.0] = 1.0
+    assert np.abs(mean.cpu().numpy() - m_np).max() <= 1e-13 * np.abs(C).max()
+    assert np.all(np.abs(scale.cpu().numpy() - s_np) <= 1e-12 * s_np)
+    T_np = ((C - mean.cpu().numpy()) / scale.cpu().numpy()).astype(np.float32)
+    assert np.array_equal(T.cpu().numpy(), T_np)
+    assert scale.cpu().numpy()[5] == 1.0 and np.all(T.cpu().numpy()[:, 5] == 0.0)
