@@ -46,13 +46,14 @@ def parse():
     ap.add_argument("--queries", type=int, default=4096)
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the oracle baseline leg")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", choices=["batch", "surrogate", "isvd", "c4"], default="batch",
+    ap.add_argument("--workload", choices=["batch", "surrogate", "isvd", "c4", "c2"], default="batch",
                     help="batch: the 4096-query batched solve (default); surrogate: train the learned "
                          "surrogate on batched solves of the transport-with-absorber ROM and measure "
                          "surrogate + certificate + fallback against the batched solve; isvd: stream the "
                          "2-D transport snapshots (49152 x 1600) through the incremental SVD; c4: precision at "
                          "scale on the 3-D 128^3 advection-diffusion problem (8000 FP32 snapshots, 8000^2 Gram "
-                         "in three arithmetics, n_s = 100 x 30, 3000-wide reduced solves)")
+                         "in three arithmetics, n_s = 100 x 30, 3000-wide reduced solves); c2: the plain FP64 "
+                         "ST-ROM of the 2-D transport problem (64^2 x 12, N_t = 200, n_s = 40, n_t = 20)")
     ap.add_argument("--surrogate-train", type=int, default=20000)
     ap.add_argument("--surrogate-steps", type=int, default=6000)
     ap.add_argument("--copy-calibration-gib", type=float, default=0.0,
@@ -81,6 +82,8 @@ def main():
         return bench_isvd(args)
     if args.workload == "c4":
         return bench_c4(args)
+    if args.workload == "c2":
+        return bench_c2(args)
 
     import numpy as np
     import torch
@@ -713,6 +716,136 @@ def bench_c4(args):
                                          f"formulas and solved by LAPACK ({dt_q:.2f} s; the projection of the "
                                          f"operators, {t_off:.1f} s, not counted); its solution agrees with the "
                                          f"device's FP32+IR to {err:.1e}"}
+    print(json.dumps(out))
+
+
+def bench_c2(args):
+    """Plain FP64 ST-ROM of the 2-D discrete-ordinates transport problem at its stated size:
+    64^2 cells x 12 directions (N_s = 49152), N_t = 200, 8 training parameters (4 total cross
+    sections x 2 scattering ratios), n_s = 40 spatial modes x n_t = 20 temporal vectors (n = 800).
+    Offline: st_build_bases + st_assemble.  Online: `--queries` parameters drawn in the box,
+    solved with the FP64 LU (the configuration's arithmetic; `value` = its certified <= 1e-6
+    queries/s) and, beside it, with the FP32 LU + FP64 refinement."""
+    import numpy as np
+    import torch
+
+    from paper_1910_01260_amd import strom
+    from paper_1910_01260_amd import workloads as W
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    strom.lib()
+    log = lambda m: print(f"[c2] {m}", file=sys.stderr, flush=True)
+    t0 = time.time()
+    prob = W.transport2d()
+    n_s, n_t = 40, 20
+    U = W.snapshots(prob)
+    log(f"snapshots {U.shape} in {time.time() - t0:.1f}s")
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def timed(fn):
+        ev0.record()
+        r = fn()
+        ev1.record()
+        torch.cuda.synchronize()
+        return r, ev0.elapsed_time(ev1)
+
+    Ud = torch.tensor(np.ascontiguousarray(U.T), device="cuda").T
+    desc = strom.RomDesc([n_t] * n_s, prob.N_t, prob.Q, prob.Qf, prob.Q0)
+    csr = [strom.csr_to_device(*W.csr_arrays(A)) for A in prob.terms]
+    dt = torch.tensor(prob.dt, device="cuda")
+    Bf = torch.tensor(np.ascontiguousarray(prob.Bf.T), device="cuda").T if prob.Qf else None
+    g = torch.tensor(np.ascontiguousarray(prob.g.T), device="cuda").T if prob.Qf else None
+    u0 = torch.tensor(np.ascontiguousarray(prob.u0.T), device="cuda").T if prob.Q0 else None
+
+    def offline():
+        Phi_s, Phi_t, sigma, rank = strom.st_build_bases(Ud, prob.N_t, len(prob.train_mu), n_s, [n_t] * n_s)
+        return Phi_s, Phi_t, strom.st_assemble(desc, Phi_s, Phi_t, dt, [c[0] for c in csr], Bf, g, u0)
+
+    offline()
+    (Phi_s, Phi_t, romb), off_ms = timed(offline)
+    nq = args.queries
+    mus = W.sample_params(prob, nq)
+    tA, tf, t0_ = prob.thetas(mus)
+    dev = lambda a: torch.tensor(np.ascontiguousarray(a), device="cuda") if a.shape[1] else None
+    dA, dF, d0 = dev(tA), dev(tf), dev(t0_)
+    nt = np.full((nq, n_s), n_t, dtype=np.int32)
+    ntd = torch.tensor(nt, device="cuda")
+    widths = nt.astype(np.int64).sum(axis=1)
+    b64 = strom.SolveBuffers(desc, nq, widths, strom.ST_F64, "cuda")
+    b32 = strom.SolveBuffers(desc, nq, widths, strom.ST_F32, "cuda")
+    solve = lambda prec, bufs: strom.st_solve(desc, romb, dA, dF, d0, ntd, lu_prec=prec,
+                                              ir_tol=IR_TOL if prec == strom.ST_F32 else 0.0,
+                                              ir_max=IR_MAX if prec == strom.ST_F32 else 0, bufs=bufs)
+    strom.st_graph_enable(True)
+    for _ in range(max(1, args.warmup)):
+        solve(strom.ST_F64, b64)
+        solve(strom.ST_F32, b32)
+    torch.cuda.synchronize()
+    K = args.steps
+    ms64 = float(np.median([timed(lambda: solve(strom.ST_F64, b64))[1] for _ in range(K)]))
+    ms32 = float(np.median([timed(lambda: solve(strom.ST_F32, b32))[1] for _ in range(K)]))
+    strom.st_graph_enable(False)
+    strom.st_graph_reset()
+    strom.st_timing_enable(True)
+    solve(strom.ST_F64, b64)
+    torch.cuda.synchronize()
+    ph64 = strom.st_timing_read()
+    strom.st_timing_enable(False)
+    gamma = strom.st_coercivity_floor(prob.N_t)
+    _, cert64 = strom.st_certify(desc, romb, dA, dF, d0, b64.coeff, ntd, gamma=gamma)
+    _, cert32 = strom.st_certify(desc, romb, dA, dF, d0, b32.coeff, ntd, gamma=gamma)
+    torch.cuda.synchronize()
+    info64, info32 = b64.info.cpu().numpy()[:nq], b32.info.cpu().numpy()[:nq]
+    ok64 = int(np.sum((info64 == 0) & (cert64.cpu().numpy() <= CERT_TOL)))
+    ok32 = int(np.sum(np.isin(info32, (0, -6)) & (cert32.cpu().numpy() <= CERT_TOL)))
+    lu_flops = float(np.sum(2.0 / 3.0 * widths.astype(np.float64) ** 3))
+    lu_tf = lu_flops / (ph64["lu"] * 1e-3) / 1e12
+    out = {
+        "metric": "ST-ROM queries/sec, plain FP64 (2-D transport, n = 800) at rel err<=1e-6",
+        "value": ok64 / (ms64 * 1e-3),
+        "unit": "queries/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": ms64,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (seeded 2-D transport snapshots and parameters)",
+        "config": {"workload": "plain ST-ROM, FP64: 2-D discrete-ordinates transport 64x64 x 12 directions "
+                               "(N_s=49152), N_t=200, 8 training mu, n_s=40, n_t=20 (n=800), "
+                               f"{nq} queries", "step": "one HIP-graph replay of st_solve (FP64 LU)"},
+        "roofline": {"bound": "mfma", "kernel": "lu_kernel<double> (batched FP64 LU)", "achieved": lu_tf,
+                     "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": lu_tf / FP64_PEAK_TFLOPS, "traffic": None,
+                     "algorithmic_flops_per_launch": lu_flops, "avg_launch_ms": ph64["lu"]},
+        "offline_ms": off_ms,
+        "fp64_phases_ms": ph64,
+        "fp32_ir": {"ms": ms32, "certified": ok32, "queries_per_s": ok32 / (ms32 * 1e-3)},
+        "certified_fp64": ok64,
+        "cpu_baseline": None,
+    }
+    if not args.no_cpu_baseline:
+        from oracle import rom as orom
+        P, Pt_all = Phi_s.cpu().numpy(), Phi_t.cpu().numpy()
+        Pt = [Pt_all[:, i * n_t:(i + 1) * n_t] for i in range(n_s)]
+        Ahat = [orom.spatial_operator(P, A) for A in prob.terms]
+        bhat = orom.reduced_vector(P, prob.Bf) if prob.Qf else np.zeros((n_s, 0))
+        u0hat = orom.reduced_vector(P, prob.u0) if prob.Q0 else np.zeros((n_s, 0))
+        c64, off = b64.coeff.cpu().numpy(), b64.coeff_off.cpu().numpy()
+        n_cpu, worst = 8, 0.0
+        t1 = time.perf_counter()
+        for q in range(n_cpu):
+            M, b = orom.reduced_system(Ahat, tA[q], bhat, tf[q], prob.g, u0hat, t0_[q], Pt, prob.dt)
+            c = np.linalg.solve(M, b)
+            worst = max(worst, float(np.linalg.norm(c64[off[q]:off[q + 1]] - c) / np.linalg.norm(c)))
+        dt_q = (time.perf_counter() - t1) / n_cpu
+        out["cpu_baseline"] = {"value": 1.0 / dt_q, "unit": "queries/s", "cores": os.cpu_count(), "kind": "oracle",
+                               "sample": f"{n_cpu} queries assembled by the oracle's block formulas and solved by "
+                                         f"LAPACK in one process (the projection of the operators not counted); "
+                                         f"their solutions agree with the device's FP64 path to {worst:.1e}"}
     print(json.dumps(out))
 
 
