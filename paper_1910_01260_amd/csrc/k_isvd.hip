@@ -64,15 +64,17 @@ struct GroupSum {
   }
 };
 
+template <int NT = kIT>
 __device__ double block_sum(double v) {
-  __shared__ double red[kNW];
+  constexpr int NW = NT / 64;
+  __shared__ double red[NW];
   __shared__ double tot;
   v = wave_sum(v);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
   __syncthreads();
   if (threadIdx.x == 0) {
     double t = 0.0;
-    for (int w = 0; w < kNW; ++w) t += red[w];
+    for (int w = 0; w < NW; ++w) t += red[w];
     tot = t;
   }
   __syncthreads();
@@ -177,13 +179,14 @@ __global__ __launch_bounds__(kIT) void isvd_sub1_kernel(const double* __restrict
 // independent per coordinate, the serial rotation loop runs only when two
 // consecutive active coordinates are within tol, and wave 0 compacts the
 // active set with ballots.
+template <int NT>
 __device__ void deflate_block(bsvd::Problem& P, bool dependent, int* s_na, int* s_nrot, int* s_pact) {
   __shared__ int s_close;
   __shared__ double s_tol;
   const int tid = threadIdx.x, r = P.r;
   double zz = 0.0;
-  for (int t = tid; t <= r; t += kIT) zz += P.z[t] * P.z[t];
-  zz = block_sum(zz);
+  for (int t = tid; t <= r; t += NT) zz += P.z[t] * P.z[t];
+  zz = block_sum<NT>(zz);
   if (tid == 0) {
     const double dmax = r > 0 ? P.d[0] : 0.0;
     s_tol = 8.0 * bsvd::kEps * fmax(dmax, sqrt(zz));
@@ -191,10 +194,10 @@ __device__ void deflate_block(bsvd::Problem& P, bool dependent, int* s_na, int* 
   }
   __syncthreads();
   const double tol = s_tol;
-  for (int t = tid; t <= r; t += kIT)
+  for (int t = tid; t <= r; t += NT)
     if ((t == r && dependent) || fabs(P.z[t]) <= tol) P.z[t] = 0.0;
   __syncthreads();
-  for (int t = tid; t < r; t += kIT) {
+  for (int t = tid; t < r; t += NT) {
     if (P.z[t] == 0.0) continue;
     int u = t - 1;
     while (u >= 0 && P.z[u] == 0.0) --u;
@@ -246,10 +249,10 @@ __device__ void deflate_block(bsvd::Problem& P, bool dependent, int* s_na, int* 
 }
 
 // Every root of the active problem, a group of L lanes per root.
-template <int L>
+template <int L, int NT>
 __device__ void roots_phase(const bsvd::Problem& P, double* org, double* tau, int* pos) {
   const int grp = threadIdx.x / L, gl = threadIdx.x % L;
-  for (int q = grp; q < P.na; q += kIT / L) {
+  for (int q = grp; q < P.na; q += NT / L) {
     double o, tv;
     bsvd::root_group(P, q, gl, L, GroupSum<L>{}, o, tv);
     if (gl == 0) {
@@ -260,7 +263,8 @@ __device__ void roots_phase(const bsvd::Problem& P, double* org, double* tau, in
   }
 }
 
-// The step's decisions and the SVD of the middle matrix, in one workgroup.
+// The step's decisions and the SVD of the middle matrix, in one workgroup of NT threads.
+template <int NT>
 __device__ void bordered_step(int r, int r_max, int64_t m_max, double eps_svd, double eps_sv, double p2,
                               const double* l1, const double* l2, double* s, double* UqT, double* VqT, int ldq,
                               double* scal, int32_t* state) {
@@ -271,11 +275,11 @@ __device__ void bordered_step(int r, int r_max, int64_t m_max, double eps_svd, d
   const int tid = threadIdx.x;
   const double p = sqrt(p2);
   const int64_t k = state[S_K];
-  for (int t = tid; t < r; t += kIT) {
+  for (int t = tid; t < r; t += NT) {
     d[t] = s[t];
     z[t] = l1[t] + l2[t];
   }
-  for (int t = tid; t <= r; t += kIT) pos[t] = -1;
+  for (int t = tid; t <= r; t += NT) pos[t] = -1;
   __syncthreads();
   bsvd::Problem P{r, d, z, act, 0, da, za, ri, rj, rc, rs, 0, false};
   if (tid == 0) {
@@ -306,33 +310,33 @@ __device__ void bordered_step(int r, int r_max, int64_t m_max, double eps_svd, d
   }
   __syncthreads();
   if (!s_go) return;
-  deflate_block(P, !(p >= eps_svd), &s_na, &s_nrot, &s_pact);
+  deflate_block<NT>(P, !(p >= eps_svd), &s_na, &s_nrot, &s_pact);
   P.na = s_na;
   P.nrot = s_nrot;
   P.p_active = s_pact != 0;
   const int n = r + 1;
   // roots: a group of lanes per root splits the secular sums; the group is
   // as wide as the workgroup allows with every root in one pass
-  if (P.na * 32 <= kIT)
-    roots_phase<32>(P, org, tau, pos);
-  else if (P.na * 16 <= kIT)
-    roots_phase<16>(P, org, tau, pos);
-  else if (P.na * 8 <= kIT)
-    roots_phase<8>(P, org, tau, pos);
-  else if (P.na * 4 <= kIT)
-    roots_phase<4>(P, org, tau, pos);
-  else if (P.na * 2 <= kIT)
-    roots_phase<2>(P, org, tau, pos);
+  if (P.na * 32 <= NT)
+    roots_phase<32, NT>(P, org, tau, pos);
+  else if (P.na * 16 <= NT)
+    roots_phase<16, NT>(P, org, tau, pos);
+  else if (P.na * 8 <= NT)
+    roots_phase<8, NT>(P, org, tau, pos);
+  else if (P.na * 4 <= NT)
+    roots_phase<4, NT>(P, org, tau, pos);
+  else if (P.na * 2 <= NT)
+    roots_phase<2, NT>(P, org, tau, pos);
   else
-    roots_phase<1>(P, org, tau, pos);
-  for (int t = tid; t <= r; t += kIT) zh[t] = 0.0;
+    roots_phase<1, NT>(P, org, tau, pos);
+  for (int t = tid; t <= r; t += NT) zh[t] = 0.0;
   __syncthreads();
-  for (int q = tid; q < P.na; q += kIT) zh[act[q]] = bsvd::zhat(P, q, org, tau);
+  for (int q = tid; q < P.na; q += NT) zh[act[q]] = bsvd::zhat(P, q, org, tau);
   const int ncand = P.p_active ? r + 1 : r;
-  for (int t = tid; t < ncand; t += kIT) sg[t] = bsvd::cand_sigma(P, pos, org, tau, t);
+  for (int t = tid; t < ncand; t += NT) sg[t] = bsvd::cand_sigma(P, pos, org, tau, t);
   __syncthreads();
   // output column c (descending singular values) comes from candidate colsrc[c]
-  for (int t = tid; t < ncand; t += kIT) colsrc[bsvd::cand_rank(sg, ncand, t)] = t;
+  for (int t = tid; t < ncand; t += NT) colsrc[bsvd::cand_rank(sg, ncand, t)] = t;
   __syncthreads();
   if (tid == 0) {
     const double mn = ncand > 0 ? sg[colsrc[ncand - 1]] : 0.0;
@@ -347,10 +351,10 @@ __device__ void bordered_step(int r, int r_max, int64_t m_max, double eps_svd, d
   }
   __syncthreads();
   const int keep = s_keep;
-  for (int c = tid; c < keep; c += kIT) s[c] = sg[colsrc[c]];
+  for (int c = tid; c < keep; c += NT) s[c] = sg[colsrc[c]];
   // norms of the unnormalised vectors, a group of kGrp lanes per column
   const int grp = tid / kGrp, gl = tid % kGrp;
-  for (int c = grp; c < keep; c += kIT / kGrp) {
+  for (int c = grp; c < keep; c += NT / kGrp) {
     const int t = colsrc[c];
     double nu = 1.0, nv = 1.0, w = 0.0;
     if (pos[t] >= 0) {
@@ -372,7 +376,7 @@ __device__ void bordered_step(int r, int r_max, int64_t m_max, double eps_svd, d
   }
   __syncthreads();
   // the entries, consecutive threads on consecutive columns of a row of U_q^T / V_q^T
-  for (int e = tid; e < keep * n; e += kIT) {
+  for (int e = tid; e < keep * n; e += NT) {
     const int q = e / keep, c = e - q * keep;
     const int t = colsrc[c];
     double a, b;
@@ -391,7 +395,7 @@ __device__ void bordered_step(int r, int r_max, int64_t m_max, double eps_svd, d
     // undo the deflation rotations, one thread per column
     __threadfence_block();
     __syncthreads();
-    for (int c = tid; c < keep; c += kIT) {
+    for (int c = tid; c < keep; c += NT) {
       bsvd::unrotate(P, UqT + c, ldq);
       bsvd::unrotate(P, VqT + c, ldq);
     }
@@ -412,15 +416,17 @@ __global__ __launch_bounds__(kIT) void isvd_sub2_kernel(const double* __restrict
 }
 
 // p = ||res|| from the partials, then the step's decisions and the bordered SVD (one workgroup).
-__global__ __launch_bounds__(kIT) void isvd_svd_kernel(const double* part, int G, int32_t* state, const double* l1,
+constexpr int kSvdThreads = 1024;  // the bordered SVD alone: more lanes per root and per vector
+__global__ __launch_bounds__(kSvdThreads) void isvd_svd_kernel(const double* part, int G, int32_t* state, const double* l1,
                                                        const double* l2, double* scal, double* s, double* UqT,
                                                        double* VqT, int r_max, int64_t m_max, double eps_svd,
                                                        double eps_sv) {
   double p2 = 0.0;
-  for (int b = threadIdx.x; b < G; b += kIT) p2 += part[b];
-  p2 = block_sum(p2);
+  for (int b = threadIdx.x; b < G; b += kSvdThreads) p2 += part[b];
+  p2 = block_sum<kSvdThreads>(p2);
   if (threadIdx.x == 0) scal[C_P2] = p2;
-  bordered_step(state[S_R], r_max, m_max, eps_svd, eps_sv, p2, l1, l2, s, UqT, VqT, r_max + 1, scal, state);
+  bordered_step<kSvdThreads>(state[S_R], r_max, m_max, eps_svd, eps_sv, p2, l1, l2, s, UqT, VqT, r_max + 1, scal,
+                             state);
 }
 
 // The whole front of a step for a short snapshot (N_s up to kFrontRows), in
@@ -440,7 +446,7 @@ __global__ __launch_bounds__(kIT) void isvd_front_kernel(const double* __restric
   __syncthreads();
   const double p2 = block_sum(subtract_block(W, N_s, r, l2, res, res, 0, N_s));
   if (threadIdx.x == 0) scal[C_P2] = p2;
-  bordered_step(r, r_max, m_max, eps_svd, eps_sv, p2, l1, l2, s, UqT, VqT, r_max + 1, scal, state);
+  bordered_step<kIT>(r, r_max, m_max, eps_svd, eps_sv, p2, l1, l2, s, UqT, VqT, r_max + 1, scal, state);
 }
 
 // X[row, 0:rnew] <- [X[row, 0:r], extra(row)] M over rows [row0, row1), in
@@ -626,7 +632,7 @@ hipError_t launch_isvd_step(const IsvdArgs& a, const double* u, hipStream_t s) {
     hipLaunchKernelGGL(isvd_sub1_kernel, dim3(G), dim3(kIT), 0, s, a.W, a.N_s, rpb, u, a.state, a.l1, a.res, a.part);
     hipLaunchKernelGGL(isvd_reduce_kernel, dim3(1), dim3(kRT), 0, s, a.part, G, a.state, a.l2);
     hipLaunchKernelGGL(isvd_sub2_kernel, dim3(G), dim3(kIT), 0, s, a.W, a.N_s, rpb, a.state, a.l2, a.res, a.part);
-    hipLaunchKernelGGL(isvd_svd_kernel, dim3(1), dim3(kIT), 0, s, a.part, G, a.state, a.l1, a.l2, a.scal, a.s,
+    hipLaunchKernelGGL(isvd_svd_kernel, dim3(1), dim3(kSvdThreads), 0, s, a.part, G, a.state, a.l1, a.l2, a.scal, a.s,
                        a.UqT, a.VqT, a.r_max, a.m_max, a.eps_svd, a.eps_sv);
   }
   const int GW = (int)((a.N_s + kApplyRows - 1) / kApplyRows);
