@@ -262,7 +262,7 @@ def main():
 
     # the streaming alternative to the offline POD: the same snapshots through the
     # incremental SVD, then its bases against the batch POD's
-    isvd = isvd_stream(strom, Ud, U, prob.N_t, n_mu, n_s, [n_t_max] * n_s, r_max=256, rel_eps=2.5e-11)
+    isvd = isvd_stream(strom, Ud, U, prob.N_t, n_mu, n_s, [n_t_max] * n_s, r_max=128, rel_eps=2.5e-11)
     # (the stream keeps only the triplets above its thresholds: its rank can be below n_s, and
     # the vectors near the truncation level are ill-conditioned, so the leading 20 are compared)
     isvd["max_abs_diff_phi_s_1_to_20_vs_batch_pod"] = float((isvd.pop("Phi_s")[:, :20]

@@ -57,15 +57,17 @@ def _compare(dev, Wo, so, Vo, s_tol=1e-12, vec_tol=1e-12, orth_tol=1e-13):
     return W, s, V
 
 
-def test_isvd_advection_diffusion_stream_matches_oracle():
+@pytest.mark.parametrize("r_max", [256, 128])
+def test_isvd_advection_diffusion_stream_matches_oracle(r_max):
     # 1-D advection-diffusion, N_s = 256, 4 x 128 snapshots; thresholds in a gap
-    # of the spectrum (between sigma_35 and sigma_36)
+    # of the spectrum (between sigma_35 and sigma_36), at two rank limits (the
+    # factor updates stage (r_max + 1)-column tiles).
     U = C.snapshots("c1")
     sc = np.linalg.norm(U, axis=0).max()
     eps = 2.5e-11 * sc
     ev = []
-    Wo, so, Vo = oisvd.incremental_svd(U, eps, eps, r_max=256, events=ev)
-    dev = _stream(U, 256, eps, eps)
+    Wo, so, Vo = oisvd.incremental_svd(U, eps, eps, r_max=r_max, events=ev)
+    dev = _stream(U, r_max, eps, eps)
     cnt = dev.counters()
     assert cnt["snapshots"] == U.shape[1] and cnt["refused"] == 0
     assert cnt["dependent"] == sum(e.startswith("dependent") for e in ev)
