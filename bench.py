@@ -56,6 +56,9 @@ def parse():
                          "ST-ROM of the 2-D transport problem (64^2 x 12, N_t = 200, n_s = 40, n_t = 20)")
     ap.add_argument("--surrogate-train", type=int, default=20000)
     ap.add_argument("--surrogate-steps", type=int, default=6000)
+    ap.add_argument("--no-isvd", action="store_true",
+                    help="skip the incremental-SVD stream of the batch snapshots (e.g. for hardware-counter runs "
+                         "that only need the assembly and LU kernels)")
     ap.add_argument("--copy-calibration-gib", type=float, default=0.0,
                     help="before the steps, copy a buffer of this size once (device to device) so that a "
                          "hardware-counter run can scale byte counters against a kernel of known traffic")
@@ -262,17 +265,19 @@ def main():
 
     # the streaming alternative to the offline POD: the same snapshots through the
     # incremental SVD, then its bases against the batch POD's
-    isvd = isvd_stream(strom, Ud, U, prob.N_t, n_mu, n_s, [n_t_max] * n_s, r_max=128, rel_eps=2.5e-11)
-    # (the stream keeps only the triplets above its thresholds: its rank can be below n_s, and
-    # the vectors near the truncation level are ill-conditioned, so the leading 20 are compared)
-    isvd["max_abs_diff_phi_s_1_to_20_vs_batch_pod"] = float((isvd.pop("Phi_s")[:, :20]
-                                                             - state["Phi_s"][:, :20]).abs().max())
-    kk = min(isvd["counters"]["rank"], n_s)
-    isvd["max_rel_diff_sigma_vs_batch_pod"] = float(((isvd.pop("sigma")[:kk] - state["sigma"][:kk]).abs().max()
-                                                     / state["sigma"][0]))
-    print(f"[bench] incremental SVD of the {U.shape[1]} snapshots: {isvd['stream_ms']:.1f} ms "
-          f"({isvd['us_per_snapshot']:.1f} us/snapshot), rank {isvd['counters']['rank']}", file=sys.stderr,
-          flush=True)
+    isvd = None
+    if not args.no_isvd:
+        isvd = isvd_stream(strom, Ud, U, prob.N_t, n_mu, n_s, [n_t_max] * n_s, r_max=128, rel_eps=2.5e-11)
+        # (the stream keeps only the triplets above its thresholds: its rank can be below n_s, and
+        # the vectors near the truncation level are ill-conditioned, so the leading 20 are compared)
+        isvd["max_abs_diff_phi_s_1_to_20_vs_batch_pod"] = float((isvd.pop("Phi_s")[:, :20]
+                                                                 - state["Phi_s"][:, :20]).abs().max())
+        kk = min(isvd["counters"]["rank"], n_s)
+        isvd["max_rel_diff_sigma_vs_batch_pod"] = float(((isvd.pop("sigma")[:kk] - state["sigma"][:kk]).abs().max()
+                                                         / state["sigma"][0]))
+        print(f"[bench] incremental SVD of the {U.shape[1]} snapshots: {isvd['stream_ms']:.1f} ms "
+              f"({isvd['us_per_snapshot']:.1f} us/snapshot), rank {isvd['counters']['rank']}", file=sys.stderr,
+              flush=True)
 
     # ------------------------------------------------------------- roofline of the dominant kernel
     lu_ms = ph32["lu"]
@@ -651,6 +656,10 @@ def bench_c4(args):
     solve = lambda prec, bufs: strom.st_solve(desc, romb, dA, None, d0, ntd, lu_prec=prec,
                                               ir_tol=IR_TOL if prec == strom.ST_F32 else 0.0,
                                               ir_max=IR_MAX if prec == strom.ST_F32 else 0, bufs=bufs)
+    tune = {}
+    for name, prec, bufs in (("fp32", strom.ST_F32, b32), ("fp64", strom.ST_F64, b64)):
+        choice, ms = strom.st_autotune(desc, romb, dA, None, d0, ntd, prec, bufs=bufs)
+        tune[name] = {"choice": choice, "lu_ms_per_variant": ms}
     for _ in range(max(1, args.warmup)):
         solve(strom.ST_F32, b32)
         solve(strom.ST_F64, b64)
@@ -692,6 +701,7 @@ def bench_c4(args):
         "gram": grams,
         "pod": pods,
         "assemble_ms": asm_ms,
+        "lu_autotune": tune,
         "solve": {"fp32_ir_ms": ms32, "fp64_ms": ms64, "certified_fp32_ir": ok32, "queries": nq,
                   "lu_tflops_fp32_ir": lu_flops / (ms32 * 1e-3) / 1e12,
                   "fp32ir_vs_fp64_max_rel_diff": d3264},
@@ -778,6 +788,11 @@ def bench_c2(args):
     solve = lambda prec, bufs: strom.st_solve(desc, romb, dA, dF, d0, ntd, lu_prec=prec,
                                               ir_tol=IR_TOL if prec == strom.ST_F32 else 0.0,
                                               ir_max=IR_MAX if prec == strom.ST_F32 else 0, bufs=bufs)
+    tune = {}
+    for name, prec, bufs in (("fp64", strom.ST_F64, b64), ("fp32", strom.ST_F32, b32)):
+        choice, ms = strom.st_autotune(desc, romb, dA, dF, d0, ntd, prec, bufs=bufs)
+        tune[name] = {"choice": choice, "lu_ms_per_variant": ms}
+    log(f"LU autotune: {json.dumps(tune)}")
     strom.st_graph_enable(True)
     for _ in range(max(1, args.warmup)):
         solve(strom.ST_F64, b64)
@@ -822,6 +837,7 @@ def bench_c2(args):
                      "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": lu_tf / FP64_PEAK_TFLOPS, "traffic": None,
                      "algorithmic_flops_per_launch": lu_flops, "avg_launch_ms": ph64["lu"]},
         "offline_ms": off_ms,
+        "lu_autotune": tune,
         "fp64_phases_ms": ph64,
         "fp32_ir": {"ms": ms32, "certified": ok32, "queries_per_s": ok32 / (ms32 * 1e-3)},
         "certified_fp64": ok64,
