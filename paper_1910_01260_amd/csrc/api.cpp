@@ -787,7 +787,8 @@ PodWs pod_ws(const PodDims& d, void* base) {
   const size_t cands[] = {tsgemm_partial_elems(d.p, (int)d.p, d.k), tsgemm_partial_elems(d.p, d.k, d.k),
                           tsgemm_partial_elems(d.k, (int)d.p, d.k), tsgemm_partial_elems(d.N_s, (int)d.m, d.kr),
                           tsgemm_partial_elems(d.m, (int)d.N_s, d.kr), tsgemm_partial_elems(d.kr, (int)d.N_s, d.n_s),
-                          tsgemm_partial_elems(d.kr, (int)d.m, d.n_s)};
+                          tsgemm_partial_elems(d.kr, (int)d.m, d.n_s), tsgemm_partial_elems(d.N_s, d.kr, d.kr),
+                          tsgemm_partial_elems(d.m, d.kr, d.kr)};
   for (size_t v : cands) pe = v > pe ? v : pe;
   w.part = c.take<double>(pe);
   w.part_elems = pe;
@@ -869,6 +870,10 @@ st_status st_build_bases(const void* U, int32_t U_prec, int64_t ldU, int64_t N_s
   // columns where the rounding of the inner products themselves approaches it
   const double tol_s = 1e-14 * fmax(1.0, sqrt((double)N_s / 65536.0));
   const double tol_m = 1e-14 * fmax(1.0, sqrt((double)d.m / 65536.0));
+  // scratch of the blocked Jacobi passes: the buffer that receives the run's normalised
+  // columns afterwards (Y1 for C1, Y2 for C2) and the k x k areas of the eigen-step
+  const TallJacobiWork wk1{w.Y1, w.H, w.Z, w.Zs, w.part, w.part_elems};
+  const TallJacobiWork wk2{w.Y2, w.H, w.Z, w.Zs, w.part, w.part_elems};
   if (!d.transposed) {
     // C1 = U X0 (N_s x kr), X0 = Y[:, :kr] in R^m
     if (f32in)
@@ -877,7 +882,7 @@ st_status st_build_bases(const void* U, int32_t U_prec, int64_t ldU, int64_t N_s
     else
       ST_TRY(launch_tsgemm(d.m, (int)N_s, kr, (const double*)U, ldU, 1, w.Y, 1, p, w.C1, (int)N_s, w.part,
                            w.part_elems, s));
-    ST_TRY(launch_tall_jacobi(w.C1, N_s, kr, nullptr, w.rot, w.offmax, kRefineSweeps, tol_s, s));
+    ST_TRY(launch_tall_jacobi(w.C1, N_s, kr, nullptr, w.rot, w.offmax, kRefineSweeps, tol_s, wk1, s));
     ST_TRY(launch_tall_jacobi_finish(w.C1, N_s, kr, nullptr, kr, w.rot, w.offmax, kRefineSweeps, w.sigk, w.perm, w.Y1,
                                      nullptr, w.diag, s));
     // C2 = U^T Y1 (m x kr)
@@ -887,7 +892,7 @@ st_status st_build_bases(const void* U, int32_t U_prec, int64_t ldU, int64_t N_s
     else
       ST_TRY(launch_tsgemm(N_s, (int)d.m, kr, (const double*)U, 1, ldU, w.Y1, 1, N_s, w.C2, (int)d.m, w.part,
                            w.part_elems, s));
-    ST_TRY(launch_tall_jacobi(w.C2, d.m, kr, w.J, w.rot, w.offmax, kRefineSweeps, tol_m, s));
+    ST_TRY(launch_tall_jacobi(w.C2, d.m, kr, w.J, w.rot, w.offmax, kRefineSweeps, tol_m, wk2, s));
     ST_TRY(launch_tall_jacobi_finish(w.C2, d.m, kr, w.J, ns, w.rot, w.offmax, kRefineSweeps, w.sig, w.perm, w.V,
                                      w.Jp, w.diag, s));
     // Phi_s = Y1 Jp (N_s x n_s)
@@ -900,7 +905,7 @@ st_status st_build_bases(const void* U, int32_t U_prec, int64_t ldU, int64_t N_s
     else
       ST_TRY(launch_tsgemm(N_s, (int)d.m, kr, (const double*)U, 1, ldU, w.Y, 1, p, w.C2, (int)d.m, w.part,
                            w.part_elems, s));
-    ST_TRY(launch_tall_jacobi(w.C2, d.m, kr, nullptr, w.rot, w.offmax, kRefineSweeps, tol_m, s));
+    ST_TRY(launch_tall_jacobi(w.C2, d.m, kr, nullptr, w.rot, w.offmax, kRefineSweeps, tol_m, wk2, s));
     ST_TRY(launch_tall_jacobi_finish(w.C2, d.m, kr, nullptr, kr, w.rot, w.offmax, kRefineSweeps, w.sigk, w.perm,
                                      w.Y2, nullptr, w.diag, s));
     // C2 = U Y1 (N_s x kr), Y1 in R^m
@@ -910,7 +915,7 @@ st_status st_build_bases(const void* U, int32_t U_prec, int64_t ldU, int64_t N_s
     else
       ST_TRY(launch_tsgemm(d.m, (int)N_s, kr, (const double*)U, ldU, 1, w.Y2, 1, d.m, w.C1, (int)N_s, w.part,
                            w.part_elems, s));
-    ST_TRY(launch_tall_jacobi(w.C1, N_s, kr, w.J, w.rot, w.offmax, kRefineSweeps, tol_s, s));
+    ST_TRY(launch_tall_jacobi(w.C1, N_s, kr, w.J, w.rot, w.offmax, kRefineSweeps, tol_s, wk1, s));
     ST_TRY(launch_tall_jacobi_finish(w.C1, N_s, kr, w.J, ns, w.rot, w.offmax, kRefineSweeps, w.sig, w.perm, Phi_s,
                                      w.Jp, w.diag, s));
     // V = Y1 Jp (m x n_s)

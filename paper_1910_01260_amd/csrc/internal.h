@@ -81,6 +81,8 @@ hipError_t launch_tsgemm_xf(int64_t N, int32_t p, int32_t q, const float* X, int
                             const double* Y, int64_t yrs, int64_t ycs, double* C, int32_t ldc, double* partial,
                             size_t partial_elems, hipStream_t s);
 size_t tsgemm_partial_elems(int64_t N, int32_t p, int32_t q);
+// out = A V (A, out m x k and V k x k, column-major; k <= 256; no overlap)
+hipError_t launch_mul_small(const double* A, int64_t m, int32_t k, const double* V, double* out, hipStream_t s);
 // reduced-precision projection: Z = [Phi_s, A Phi_s] in FP32 (row-major N x 2p), then the
 // Phi_s^T (A Phi_s) block of its Gram
 hipError_t launch_pack_basis_f32(const double* Phi, int64_t N, int32_t p, float* Z, hipStream_t s);
@@ -107,9 +109,16 @@ hipError_t launch_sqrt_clamp(const double* lam, double* sigma, int n, hipStream_
 hipError_t launch_sign_fix(double* X, int64_t p, int k, double* Y, int64_t py, hipStream_t s);
 hipError_t launch_copy_cols(const double* src, int64_t ld_src, double* dst, int64_t ld_dst, int64_t p, int n,
                             hipStream_t s);
+// Work areas of the blocked passes of launch_tall_jacobi: A2 (m x k), G, V and J2
+// (k x k each; J2 only with J), part (the split partials of A^T A, part_elems
+// doubles).  A2 == nullptr keeps the pair-by-pair sweeps throughout.
+struct TallJacobiWork {
+  double *A2, *G, *V, *J2, *part;
+  size_t part_elems;
+};
 // one-sided Jacobi SVD of the tall m x k matrix A (in place), rotations accumulated in J
 hipError_t launch_tall_jacobi(double* A, int64_t m, int k, double* J, int* rot, double* offmax, int max_sweeps,
-                              double tol, hipStream_t s);
+                              double tol, const TallJacobiWork& wk, hipStream_t s);
 hipError_t launch_tall_jacobi_finish(const double* A, int64_t m, int k, const double* J, int n_out, const int* rot,
                                      const double* offmax, int max_sweeps, double* sigma, int* perm, double* V,
                                      double* Jp, double* diag, hipStream_t s);

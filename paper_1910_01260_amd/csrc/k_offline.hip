@@ -330,6 +330,19 @@ hipError_t launch_tsgemm(int64_t N, int32_t p, int32_t q, const double* X, int64
   return tsgemm_go<double>(N, p, q, X, xrs, xcs, Y, yrs, ycs, nullptr, C, ldc, partial, partial_elems, s);
 }
 
+// out = A V with A m x k and out m x k column-major (leading dimension m), V k x k
+// column-major, k <= 256: the reduction runs over k only, so one split, and the
+// tiles write out directly (out must not overlap A or V).
+hipError_t launch_mul_small(const double* A, int64_t m, int32_t k, const double* V, double* out, hipStream_t s) {
+  if (m <= 0 || k <= 0) return hipSuccess;
+  if (k > 256 || m > 0x7fffffff) return hipErrorInvalidValue;
+  const int64_t rps = (int64_t)(k + kTile - 1) / kTile * kTile;
+  dim3 grid((unsigned)((m + kTile - 1) / kTile), (k + kTile - 1) / kTile, 1);
+  hipLaunchKernelGGL(tsgemm_partial_kernel<double>, grid, dim3(256), 0, s, (int64_t)k, (int32_t)m, k, A, m, 1, V,
+                     1, k, nullptr, rps, out);
+  return hipGetLastError();
+}
+
 hipError_t launch_tsgemm_xf(int64_t N, int32_t p, int32_t q, const float* X, int64_t xrs, int64_t xcs, const double* Y,
                             int64_t yrs, int64_t ycs, double* C, int32_t ldc, double* partial, size_t partial_elems,
                             hipStream_t s) {

@@ -604,6 +604,9 @@ __global__ void copy_cols_kernel(const double* src, int64_t ld_src, double* dst,
 // per column pair; rounds of a sweep touch disjoint pairs.
 // ---------------------------------------------------------------------------
 constexpr int kTallThreads = 256;
+// inner two-sided Jacobi of a blocked pass: relative skip threshold and sweep limit
+constexpr double kGramInnerEps = 1e-16;
+constexpr int kGramInnerSweeps = 30;
 
 // Pair `pr` of round `round` over kk (even) players: player 0 stays, the others rotate.
 __device__ inline void tournament_pair(int round, int pr, int kk, int& a, int& b) {
@@ -749,6 +752,111 @@ __global__ __launch_bounds__(kOneWG) void tall_jacobi_lds_kernel(double* __restr
     if (nrot == 0) break;
   }
   for (int64_t e = tid; e < m * k; e += kOneWG) Ag[e] = As[e];
+}
+
+// One pass of the blocked form of the same one-sided Jacobi, for columns too long
+// to sweep pair by pair: the caller forms G = A^T A of the current columns; this
+// measures its largest |cos| between two columns (offmax[sweep]) and, when that
+// exceeds tol, diagonalises G by cyclic two-sided Jacobi (the rotation of each
+// pair is the one the one-sided method would take from the same three inner
+// products; pairs with |g_ab| <= eps_in sqrt(g_aa g_bb) are skipped) with the
+// rotations accumulated in V (k x k, column-major), which the caller applies to
+// A and J.  rot[sweep] = 0 when converged, else the inner sweeps that ran (>= 1).
+// With IN_LDS, G is copied into LDS; otherwise it is worked on in place.
+template <bool IN_LDS>
+__global__ __launch_bounds__(kOneWG) void gram_jacobi_kernel(int k, double* __restrict__ Gg, double* __restrict__ V,
+                                                             int sweep, int* __restrict__ rot,
+                                                             double* __restrict__ offmax, double tol, double eps_in,
+                                                             int max_inner) {
+  extern __shared__ __align__(16) double gj_lds[];
+  __shared__ int sp[kMaxSubspaceDev / 2], sq[kMaxSubspaceDev / 2];
+  __shared__ double sc[kMaxSubspaceDev / 2], ss[kMaxSubspaceDev / 2];
+  __shared__ double red[kOneWG / 64];
+  __shared__ int s_rot;
+  const int tid = threadIdx.x;
+  double* G = IN_LDS ? gj_lds : Gg;
+  if (IN_LDS)
+    for (int e = tid; e < k * k; e += kOneWG) G[e] = Gg[e];
+  __syncthreads();
+  double off = 0.0;
+  for (int e = tid; e < k * k; e += kOneWG) {
+    const int a = e % k, b = e / k;
+    if (a < b) {
+      const double d = sqrt(fabs(G[a + (int64_t)a * k])) * sqrt(fabs(G[b + (int64_t)b * k]));
+      if (d > 0.0) off = fmax(off, fabs(G[e]) / d);
+    }
+  }
+  off = block_max(off, red);
+  if (tid == 0) offmax[sweep] = off;
+  if (!(off > tol)) {  // uniform: every thread holds the same maximum
+    if (tid == 0) rot[sweep] = 0;
+    return;
+  }
+  for (int e = tid; e < k * k; e += kOneWG) V[e] = (e % k == e / k) ? 1.0 : 0.0;
+  const int kk = (k + 1) / 2 * 2, np = kk / 2;
+  int used = 0;
+  for (int inner = 0; inner < max_inner; ++inner) {
+    if (tid == 0) s_rot = 0;
+    __syncthreads();
+    for (int rnd = 0; rnd < kk - 1; ++rnd) {
+      if (tid < np) {
+        int a, b;
+        tournament_pair(rnd, tid, kk, a, b);
+        if (a > b) {
+          const int t = a;
+          a = b;
+          b = t;
+        }
+        double c = 1.0, sn = 0.0;
+        if (b < k) {
+          const double gab = G[a + (int64_t)b * k];
+          const double gaa = fabs(G[a + (int64_t)a * k]), gbb = fabs(G[b + (int64_t)b * k]);
+          if (fabs(gab) > eps_in * sqrt(gaa) * sqrt(gbb)) {
+            const double zeta = (gbb - gaa) / (2.0 * gab);
+            const double t = copysign(1.0, zeta) / (fabs(zeta) + hypot(1.0, zeta));
+            c = 1.0 / sqrt(fma(t, t, 1.0));
+            sn = c * t;
+            s_rot = 1;
+          }
+        }
+        sp[tid] = a;
+        sq[tid] = b;
+        sc[tid] = c;
+        ss[tid] = sn;
+      }
+      __syncthreads();
+      // rows a and b: G <- R^T G (R: column a -> c a - s b, column b -> s a + c b)
+      for (int e = tid; e < np * k; e += kOneWG) {
+        const int t = e / k, j = e % k;
+        const int a = sp[t], b = sq[t];
+        if (b >= k || ss[t] == 0.0) continue;
+        const double c = sc[t], sn = ss[t];
+        const double x = G[a + (int64_t)j * k], y = G[b + (int64_t)j * k];
+        G[a + (int64_t)j * k] = c * x - sn * y;
+        G[b + (int64_t)j * k] = sn * x + c * y;
+      }
+      __syncthreads();
+      // columns a and b of G (the pair's own entries become exact zeros) and of V
+      for (int e = tid; e < np * k; e += kOneWG) {
+        const int t = e / k, i = e % k;
+        const int a = sp[t], b = sq[t];
+        if (b >= k || ss[t] == 0.0) continue;
+        const double c = sc[t], sn = ss[t];
+        const double x = G[i + (int64_t)a * k], y = G[i + (int64_t)b * k];
+        G[i + (int64_t)a * k] = (i == b) ? 0.0 : c * x - sn * y;
+        G[i + (int64_t)b * k] = (i == a) ? 0.0 : sn * x + c * y;
+        const double u = V[i + (int64_t)a * k], v = V[i + (int64_t)b * k];
+        V[i + (int64_t)a * k] = c * u - sn * v;
+        V[i + (int64_t)b * k] = sn * u + c * v;
+      }
+      __syncthreads();
+    }
+    const int nrot = s_rot;
+    __syncthreads();  // every thread has read s_rot before it is reset
+    if (nrot == 0) break;
+    ++used;
+  }
+  if (tid == 0) rot[sweep] = used > 0 ? used : 1;
 }
 
 // After the sweeps: column norms (singular values), descending order (ties by
@@ -1113,7 +1221,7 @@ hipError_t launch_copy_cols(const double* src, int64_t ld_src, double* dst, int6
 }
 
 hipError_t launch_tall_jacobi(double* A, int64_t m, int k, double* J, int* rot, double* offmax, int max_sweeps,
-                              double tol, hipStream_t s) {
+                              double tol, const TallJacobiWork& wk, hipStream_t s) {
   if (k < 1 || k > kMaxSubspaceDev || m < 1) return hipErrorInvalidValue;
   const int64_t init = (int64_t)k * k > max_sweeps ? (int64_t)k * k : max_sweeps;
   hipLaunchKernelGGL(tall_jacobi_init_kernel, dim3((unsigned)((init + 255) / 256)), dim3(256), 0, s, J, k, rot, offmax,
@@ -1130,16 +1238,54 @@ hipError_t launch_tall_jacobi(double* A, int64_t m, int k, double* J, int* rot, 
                        tol);
     return hipGetLastError();
   }
-  // one launch per round; after each sweep the host reads the sweep's rotation count
-  // (a stream synchronisation) and stops once a sweep rotated nothing
+  // Longer columns: blocked passes while they converge fast -- G = A^T A (one read of
+  // A), its two-sided Jacobi in one workgroup, then A <- A V and J <- J V (one read and
+  // one write) -- instead of a sweep's k - 1 rounds that each read and write every
+  // column.  A pass that does not cut the largest |cos| at least in half (columns
+  // so nearly dependent that the rounding of G limits its rotations) hands over to
+  // the pair-by-pair sweeps, which take every inner product from the columns
+  // themselves.  After each sweep or pass the host reads its rotation count (a stream
+  // synchronisation) and stops once one rotated nothing.
   const int kk = (k + 1) / 2 * 2;
+  bool blocked = wk.A2 && wk.G && wk.V && (!J || wk.J2) && m <= 0x7fffffff;
+  const size_t glds = sizeof(double) * (size_t)k * k;
+  const bool g_in_lds = glds <= kOrthMaxLds;
+  if (blocked && g_in_lds &&
+      (e = hipFuncSetAttribute((const void*)gram_jacobi_kernel<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)glds)) != hipSuccess)
+    return e;
+  double prev = HUGE_VAL;
   for (int sw = 0; sw < max_sweeps; ++sw) {
+    int nrot = 0;
+    if (blocked) {
+      if ((e = launch_tsgemm(m, k, k, A, 1, m, A, 1, m, wk.G, k, wk.part, wk.part_elems, s)) != hipSuccess) return e;
+      if (g_in_lds)
+        hipLaunchKernelGGL(gram_jacobi_kernel<true>, dim3(1), dim3(kOneWG), glds, s, k, wk.G, wk.V, sw, rot, offmax,
+                           tol, kGramInnerEps, kGramInnerSweeps);
+      else
+        hipLaunchKernelGGL(gram_jacobi_kernel<false>, dim3(1), dim3(kOneWG), 0, s, k, wk.G, wk.V, sw, rot, offmax,
+                           tol, kGramInnerEps, kGramInnerSweeps);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+      double off = 0.0;
+      if ((e = hipMemcpyAsync(&nrot, rot + sw, sizeof(int), hipMemcpyDeviceToHost, s)) != hipSuccess) return e;
+      if ((e = hipMemcpyAsync(&off, offmax + sw, sizeof(double), hipMemcpyDeviceToHost, s)) != hipSuccess) return e;
+      if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
+      if (nrot == 0) break;
+      if ((e = launch_mul_small(A, m, k, wk.V, wk.A2, s)) != hipSuccess) return e;
+      if ((e = hipMemcpyAsync(A, wk.A2, lds, hipMemcpyDeviceToDevice, s)) != hipSuccess) return e;
+      if (J) {
+        if ((e = launch_mul_small(J, k, k, wk.V, wk.J2, s)) != hipSuccess) return e;
+        if ((e = hipMemcpyAsync(J, wk.J2, glds, hipMemcpyDeviceToDevice, s)) != hipSuccess) return e;
+      }
+      if (off > 0.5 * prev) blocked = false;
+      prev = off;
+      continue;
+    }
     for (int r = 0; r < kk - 1; ++r) {
       hipLaunchKernelGGL(tall_jacobi_round_kernel, dim3(kk / 2), dim3(kTallThreads), 0, s, A, m, k, kk, J, r, sw, rot,
                          offmax, tol);
       if ((e = hipGetLastError()) != hipSuccess) return e;
     }
-    int nrot = 0;
     if ((e = hipMemcpyAsync(&nrot, rot + sw, sizeof(int), hipMemcpyDeviceToHost, s)) != hipSuccess) return e;
     if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
     if (nrot == 0) break;
