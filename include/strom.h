@@ -201,17 +201,22 @@ st_status st_rom_layout(const st_rom_desc* d, st_rom_layout_t* out);
  *            of the subspace iteration (its convergence; the refinement
  *            does not depend on it being small)
  *   diag[1]  sweeps of the refinement's one-sided Jacobi that rotated (the
- *            larger of its two runs; 30 means the sweep limit was reached)
+ *            larger of its two runs; 30 means the sweep limit was reached);
+ *            a run over columns longer than 144 KB counts its blocked passes
+ *            (Gram of the columns, its two-sided Jacobi, one product) as sweeps
  *   diag[2]  largest |cos| between two columns seen in the last sweep of
  *            either run (<= 1e-14 max(1, sqrt(rows / 65536)) once converged)
  *   diag[3]  number of columns k of the refinement
+ *   diag[4]  pair-by-pair sweeps that followed a blocked pass which did not
+ *            halve the largest |cos| (nearly dependent columns; the larger
+ *            of the two runs, 0 when the blocked passes converged alone)
  *
  * Limits (ST_EUNSUPPORTED beyond them): n_mu <= 64; N_t n_mu <= 15360
  * (a temporal snapshot matrix is staged in 120 KB of LDS); n_t[i] <= 512;
  * n_s <= 224 (n_s plus the 32 guard vectors of the subspace iteration
  * <= 256); min(N_s, n_mu N_t) < 2^31.
  * ====================================================================== */
-#define ST_POD_DIAG 4
+#define ST_POD_DIAG 5
 size_t st_build_bases_workspace(int64_t N_s, int32_t N_t, int32_t n_mu, int32_t n_s, const int32_t* n_t,
                                 int32_t gram_prec);
 

@@ -862,12 +862,13 @@ __global__ __launch_bounds__(kOneWG) void gram_jacobi_kernel(int k, double* __re
 // After the sweeps: column norms (singular values), descending order (ties by
 // index), sigma and the permutation of the leading n_out; diagnostics
 // (accumulated over calls by maximum) diag[1] = sweeps that rotated, diag[2] =
-// largest |cos| between column pairs seen in the last sweep that ran; diag[3] = k.
+// largest |cos| between column pairs seen in the last sweep that ran; diag[3] = k;
+// diag[4] = pair-by-pair sweeps that followed a stalled blocked pass.
 __global__ __launch_bounds__(kOneWG) void tall_jacobi_finish_kernel(const double* __restrict__ A, int64_t m, int k,
                                                                      int n_out, const int* __restrict__ rot,
                                                                      const double* __restrict__ offmax, int max_sweeps,
-                                                                     double* __restrict__ sigma, int* __restrict__ perm,
-                                                                     double* __restrict__ diag) {
+                                                                     int fallback_sweeps, double* __restrict__ sigma,
+                                                                     int* __restrict__ perm, double* __restrict__ diag) {
   __shared__ double nrm[kMaxSubspaceDev];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   for (int j = wave; j < k; j += kOneWG / 64) {
@@ -893,6 +894,7 @@ __global__ __launch_bounds__(kOneWG) void tall_jacobi_finish_kernel(const double
     diag[1] = fmax(diag[1], (double)used);
     diag[2] = fmax(diag[2], offmax[last]);
     diag[3] = (double)k;
+    diag[4] = fmax(diag[4], (double)fallback_sweeps);
   }
 }
 
@@ -950,6 +952,7 @@ __global__ __launch_bounds__(kOneWG) void ritz_residual_kernel(const double* __r
     diag[0] = evals[0] > 0.0 ? worst / evals[0] : worst;
     diag[1] = 0.0;
     diag[2] = 0.0;
+    diag[4] = 0.0;
   }
 }
 
@@ -1221,7 +1224,8 @@ hipError_t launch_copy_cols(const double* src, int64_t ld_src, double* dst, int6
 }
 
 hipError_t launch_tall_jacobi(double* A, int64_t m, int k, double* J, int* rot, double* offmax, int max_sweeps,
-                              double tol, const TallJacobiWork& wk, hipStream_t s) {
+                              double tol, const TallJacobiWork& wk, int* fallback_sweeps, hipStream_t s) {
+  if (fallback_sweeps) *fallback_sweeps = 0;
   if (k < 1 || k > kMaxSubspaceDev || m < 1) return hipErrorInvalidValue;
   const int64_t init = (int64_t)k * k > max_sweeps ? (int64_t)k * k : max_sweeps;
   hipLaunchKernelGGL(tall_jacobi_init_kernel, dim3((unsigned)((init + 255) / 256)), dim3(256), 0, s, J, k, rot, offmax,
@@ -1248,6 +1252,7 @@ hipError_t launch_tall_jacobi(double* A, int64_t m, int k, double* J, int* rot, 
   // synchronisation) and stops once one rotated nothing.
   const int kk = (k + 1) / 2 * 2;
   bool blocked = wk.A2 && wk.G && wk.V && (!J || wk.J2) && m <= 0x7fffffff;
+  const bool started_blocked = blocked;
   const size_t glds = sizeof(double) * (size_t)k * k;
   const bool g_in_lds = glds <= kOrthMaxLds;
   if (blocked && g_in_lds &&
@@ -1281,6 +1286,7 @@ hipError_t launch_tall_jacobi(double* A, int64_t m, int k, double* J, int* rot, 
       prev = off;
       continue;
     }
+    if (started_blocked && fallback_sweeps) ++*fallback_sweeps;
     for (int r = 0; r < kk - 1; ++r) {
       hipLaunchKernelGGL(tall_jacobi_round_kernel, dim3(kk / 2), dim3(kTallThreads), 0, s, A, m, k, kk, J, r, sw, rot,
                          offmax, tol);
@@ -1294,11 +1300,11 @@ hipError_t launch_tall_jacobi(double* A, int64_t m, int k, double* J, int* rot, 
 }
 
 hipError_t launch_tall_jacobi_finish(const double* A, int64_t m, int k, const double* J, int n_out, const int* rot,
-                                     const double* offmax, int max_sweeps, double* sigma, int* perm, double* V,
-                                     double* Jp, double* diag, hipStream_t s) {
+                                     const double* offmax, int max_sweeps, int fallback_sweeps, double* sigma, int* perm,
+                                     double* V, double* Jp, double* diag, hipStream_t s) {
   if (k < 1 || k > kMaxSubspaceDev || n_out > k) return hipErrorInvalidValue;
   hipLaunchKernelGGL(tall_jacobi_finish_kernel, dim3(1), dim3(kOneWG), 0, s, A, m, k, n_out, rot, offmax, max_sweeps,
-                     sigma, perm, diag);
+                     fallback_sweeps, sigma, perm, diag);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int64_t n = (m + k) * n_out;

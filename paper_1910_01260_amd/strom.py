@@ -209,7 +209,7 @@ def csr_to_device(row_ptr, col_idx, val, device="cuda"):
     return d, (rp, ci, va)
 
 
-POD_DIAG = ("ritz_residual", "jacobi_sweeps", "jacobi_off", "refine_cols")
+POD_DIAG = ("ritz_residual", "jacobi_sweeps", "jacobi_off", "refine_cols", "jacobi_fallback_sweeps")
 
 
 def st_build_bases(U: torch.Tensor, N_t: int, n_mu: int, n_s: int, n_t: Sequence[int], gram_prec: int = ST_F64,
@@ -225,6 +225,9 @@ def st_build_bases(U: torch.Tensor, N_t: int, n_mu: int, n_s: int, n_t: Sequence
     else:
         raise ValueError("U must be column-major (U.T contiguous)")
     prec = ST_F64 if U.dtype == torch.float64 else ST_F32
+    if diag is not None and (diag.dtype != torch.float64 or diag.device != U.device or not diag.is_contiguous()
+                             or diag.numel() < len(POD_DIAG)):
+        raise ValueError(f"diag must be a contiguous float64 tensor of >= {len(POD_DIAG)} elements on U's device")
     nt = np.ascontiguousarray(np.asarray(n_t, dtype=np.int32))
     n = int(nt.sum())
     ws_bytes = lib().st_build_bases_workspace(N_s, N_t, n_mu, n_s, nt.ctypes.data, gram_prec)

@@ -207,3 +207,56 @@ def test_pod_reduced_precision_gram_reports_error(prec, f32):
         worst_s, worst_a = max(worst_s, err_s), max(worst_a, sin_a)
     print(f"[{name}] gram_prec={prec} f32_storage={f32}: max rel sigma err {worst_s:.2e}, "
           f"max sin(angle) {worst_a:.2e} over {len(good)} resolved modes")
+
+
+def _graded_snapshots(seed=5, N_s=20000, m=400, decades=15.0, k=55):
+    """U = Q1 diag(sigma) Q2^T with sigma_i = 10^(-decades i / k): the leading k + 1
+    modes (the refinement's columns) span 1 .. 10^-decades."""
+    rng = np.random.default_rng(seed)
+    Q1 = np.linalg.qr(rng.standard_normal((N_s, m)))[0]
+    Q2 = np.linalg.qr(rng.standard_normal((m, m)))[0]
+    return (Q1 * 10.0 ** (-decades * np.arange(m) / k)) @ Q2.T
+
+
+@pytest.mark.parametrize("prec", [strom.ST_F64, strom.ST_BF16X3])
+def test_pod_graded_tail_both_jacobi_paths(prec):
+    """Singular values over 15 decades inside the refinement's 56 columns of 20000
+    rows, too long for LDS: the refinement runs blocked passes (Gram of the columns,
+    its two-sided Jacobi, one product).  From the FP64 Gram's eigenvectors they
+    converge; from the split-BF16 Gram's (error ~1e-6 ||G||) the tail columns are
+    dominated by leakage of the leading modes, nearly dependent once normalised,
+    the blocked passes stall and the pair-by-pair sweeps take over (diag[4] > 0).
+    Either way: orthonormal basis, sigma within 1e-12 sigma_1 where the Gram
+    resolves the mode (all of them in FP64; sigma_i^2 >= 10 u_eff sigma_1^2 with
+    split-BF16, within 1e-5 sigma_1 beyond), and vectors within their SVD bound."""
+    U = _graded_snapshots()
+    N_t, n_mu, n_s = 100, 4, 40
+    diag = torch.zeros(len(strom.POD_DIAG), dtype=torch.float64, device="cuda")
+    print(f"[graded] st_build_bases N_s={U.shape[0]} m={U.shape[1]} n_s={n_s} prec={prec}", flush=True)
+    Phi_s, _, sigma, _ = strom.st_build_bases(colmajor(U), N_t, n_mu, n_s, [4] * n_s, prec, diag=diag)
+    torch.cuda.synchronize()
+    dg = dict(zip(strom.POD_DIAG, diag.cpu().numpy().tolist()))
+    print(f"[graded] prec {prec} diagnostics {dg}", flush=True)
+    Phi_s = Phi_s.cpu().numpy()
+    sigma = sigma.cpu().numpy()
+    oPhi, osig, _ = opod.pod(U, n_s)
+    np.testing.assert_allclose(Phi_s.T @ Phi_s, np.eye(n_s), atol=1e-13)
+    assert dg["jacobi_sweeps"] < 30 and dg["jacobi_off"] <= 1e-14, dg
+    if prec == strom.ST_F64:
+        resolved = np.ones(n_s, dtype=bool)
+    else:
+        resolved = osig[:n_s] ** 2 >= 10 * _U_EFF[prec] * osig[0] ** 2
+        assert resolved[:7].all() and dg["jacobi_fallback_sweeps"] > 0, dg
+        assert np.abs(sigma - osig[:n_s]).max() <= 1e-5 * osig[0]
+    ds = np.abs(sigma - osig[:n_s])[resolved]
+    assert ds.max() <= 1e-12 * osig[0], ds.max() / osig[0]
+    checked = 0
+    for i in np.flatnonzero(resolved):
+        tol = _svd_vector_tol(osig, i)
+        if tol > 1e-3:
+            continue
+        assert np.linalg.norm(Phi_s[:, i] - oPhi[:, i]) <= tol, (i, tol)
+        checked += 1
+    print(f"[graded] prec {prec}: {resolved.sum()} modes resolved, {checked} vectors checked; "
+          f"|dsigma| <= {ds.max() / osig[0]:.1e} sigma_1 on them")
+    assert checked >= (30 if prec == strom.ST_F64 else 7)
