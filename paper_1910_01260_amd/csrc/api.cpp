@@ -875,6 +875,7 @@ st_status st_build_bases(const void* U, int32_t U_prec, int64_t ldU, int64_t N_s
   const TallJacobiWork wk1{w.Y1, w.H, w.Z, w.Zs, w.part, w.part_elems};
   const TallJacobiWork wk2{w.Y2, w.H, w.Z, w.Zs, w.part, w.part_elems};
   int fb = 0;  // pair-by-pair sweeps after a stalled blocked pass (diagnostic)
+  const double* gfin = nullptr;  // Gram of a run's final columns, when its last step was a blocked pass
   if (!d.transposed) {
     // C1 = U X0 (N_s x kr), X0 = Y[:, :kr] in R^m
     if (f32in)
@@ -883,9 +884,9 @@ st_status st_build_bases(const void* U, int32_t U_prec, int64_t ldU, int64_t N_s
     else
       ST_TRY(launch_tsgemm(d.m, (int)N_s, kr, (const double*)U, ldU, 1, w.Y, 1, p, w.C1, (int)N_s, w.part,
                            w.part_elems, s));
-    ST_TRY(launch_tall_jacobi(w.C1, N_s, kr, nullptr, w.rot, w.offmax, kRefineSweeps, tol_s, wk1, &fb, s));
-    ST_TRY(launch_tall_jacobi_finish(w.C1, N_s, kr, nullptr, kr, w.rot, w.offmax, kRefineSweeps, fb, w.sigk, w.perm,
-                                     w.Y1, nullptr, w.diag, s));
+    ST_TRY(launch_tall_jacobi(w.C1, N_s, kr, nullptr, w.rot, w.offmax, kRefineSweeps, tol_s, wk1, &fb, &gfin, s));
+    ST_TRY(launch_tall_jacobi_finish(w.C1, N_s, kr, nullptr, kr, w.rot, w.offmax, kRefineSweeps, fb, gfin, w.sigk,
+                                     w.perm, w.Y1, nullptr, w.diag, s));
     // C2 = U^T Y1 (m x kr)
     if (f32in)
       ST_TRY(launch_tsgemm_xf(N_s, (int)d.m, kr, (const float*)U, 1, ldU, w.Y1, 1, N_s, w.C2, (int)d.m, w.part,
@@ -893,9 +894,9 @@ st_status st_build_bases(const void* U, int32_t U_prec, int64_t ldU, int64_t N_s
     else
       ST_TRY(launch_tsgemm(N_s, (int)d.m, kr, (const double*)U, 1, ldU, w.Y1, 1, N_s, w.C2, (int)d.m, w.part,
                            w.part_elems, s));
-    ST_TRY(launch_tall_jacobi(w.C2, d.m, kr, w.J, w.rot, w.offmax, kRefineSweeps, tol_m, wk2, &fb, s));
-    ST_TRY(launch_tall_jacobi_finish(w.C2, d.m, kr, w.J, ns, w.rot, w.offmax, kRefineSweeps, fb, w.sig, w.perm, w.V,
-                                     w.Jp, w.diag, s));
+    ST_TRY(launch_tall_jacobi(w.C2, d.m, kr, w.J, w.rot, w.offmax, kRefineSweeps, tol_m, wk2, &fb, &gfin, s));
+    ST_TRY(launch_tall_jacobi_finish(w.C2, d.m, kr, w.J, ns, w.rot, w.offmax, kRefineSweeps, fb, gfin, w.sig, w.perm,
+                                     w.V, w.Jp, w.diag, s));
     // Phi_s = Y1 Jp (N_s x n_s)
     ST_TRY(launch_tsgemm(kr, (int)N_s, ns, w.Y1, N_s, 1, w.Jp, 1, kr, Phi_s, (int)N_s, w.part, w.part_elems, s));
   } else {
@@ -906,9 +907,9 @@ st_status st_build_bases(const void* U, int32_t U_prec, int64_t ldU, int64_t N_s
     else
       ST_TRY(launch_tsgemm(N_s, (int)d.m, kr, (const double*)U, 1, ldU, w.Y, 1, p, w.C2, (int)d.m, w.part,
                            w.part_elems, s));
-    ST_TRY(launch_tall_jacobi(w.C2, d.m, kr, nullptr, w.rot, w.offmax, kRefineSweeps, tol_m, wk2, &fb, s));
-    ST_TRY(launch_tall_jacobi_finish(w.C2, d.m, kr, nullptr, kr, w.rot, w.offmax, kRefineSweeps, fb, w.sigk, w.perm,
-                                     w.Y2, nullptr, w.diag, s));
+    ST_TRY(launch_tall_jacobi(w.C2, d.m, kr, nullptr, w.rot, w.offmax, kRefineSweeps, tol_m, wk2, &fb, &gfin, s));
+    ST_TRY(launch_tall_jacobi_finish(w.C2, d.m, kr, nullptr, kr, w.rot, w.offmax, kRefineSweeps, fb, gfin, w.sigk,
+                                     w.perm, w.Y2, nullptr, w.diag, s));
     // C2 = U Y1 (N_s x kr), Y1 in R^m
     if (f32in)
       ST_TRY(launch_tsgemm_xf(d.m, (int)N_s, kr, (const float*)U, ldU, 1, w.Y2, 1, d.m, w.C1, (int)N_s, w.part,
@@ -916,9 +917,9 @@ st_status st_build_bases(const void* U, int32_t U_prec, int64_t ldU, int64_t N_s
     else
       ST_TRY(launch_tsgemm(d.m, (int)N_s, kr, (const double*)U, ldU, 1, w.Y2, 1, d.m, w.C1, (int)N_s, w.part,
                            w.part_elems, s));
-    ST_TRY(launch_tall_jacobi(w.C1, N_s, kr, w.J, w.rot, w.offmax, kRefineSweeps, tol_s, wk1, &fb, s));
-    ST_TRY(launch_tall_jacobi_finish(w.C1, N_s, kr, w.J, ns, w.rot, w.offmax, kRefineSweeps, fb, w.sig, w.perm, Phi_s,
-                                     w.Jp, w.diag, s));
+    ST_TRY(launch_tall_jacobi(w.C1, N_s, kr, w.J, w.rot, w.offmax, kRefineSweeps, tol_s, wk1, &fb, &gfin, s));
+    ST_TRY(launch_tall_jacobi_finish(w.C1, N_s, kr, w.J, ns, w.rot, w.offmax, kRefineSweeps, fb, gfin, w.sig, w.perm,
+                                     Phi_s, w.Jp, w.diag, s));
     // V = Y1 Jp (m x n_s)
     ST_TRY(launch_tsgemm(kr, (int)d.m, ns, w.Y2, d.m, 1, w.Jp, 1, kr, w.V, (int)d.m, w.part, w.part_elems, s));
   }

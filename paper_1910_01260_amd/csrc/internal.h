@@ -118,11 +118,14 @@ struct TallJacobiWork {
 };
 // one-sided Jacobi SVD of the tall m x k matrix A (in place), rotations accumulated in J
 hipError_t launch_tall_jacobi(double* A, int64_t m, int k, double* J, int* rot, double* offmax, int max_sweeps,
-                              double tol, const TallJacobiWork& wk, int* fallback_sweeps, hipStream_t s);
-// fallback_sweeps: the pair-by-pair sweeps that followed a stalled blocked pass (into diag[4])
+                              double tol, const TallJacobiWork& wk, int* fallback_sweeps, const double** final_gram,
+                              hipStream_t s);
+// fallback_sweeps: the pair-by-pair sweeps that followed a stalled blocked pass (into diag[4]);
+// G (may be null): the k x k Gram of the final columns, whose diagonal then gives the norms
+// (launch_tall_jacobi's final_gram: set when its last step was a blocked pass that rotated nothing)
 hipError_t launch_tall_jacobi_finish(const double* A, int64_t m, int k, const double* J, int n_out, const int* rot,
-                                     const double* offmax, int max_sweeps, int fallback_sweeps, double* sigma, int* perm,
-                                     double* V, double* Jp, double* diag, hipStream_t s);
+                                     const double* offmax, int max_sweeps, int fallback_sweeps, const double* G,
+                                     double* sigma, int* perm, double* V, double* Jp, double* diag, hipStream_t s);
 hipError_t launch_ritz_residual(const double* GY, const double* Y, int64_t p, int n, const double* evals, double* diag,
                                 hipStream_t s);
 hipError_t launch_temporal_svd(const double* V, int64_t ldV, int N_t, int n_mu, int n_s, const int32_t* moff,

@@ -19,8 +19,8 @@ namespace {
 
 constexpr int kOneWG = 1024;
 constexpr int kTsvdThreads = 1024;  // one workgroup per mode: one wave per column pair of a round
-constexpr size_t kOrthMaxLds = 144 * 1024;
-constexpr int kMaxSubspaceDev = 256;  // column limit of the subspace kernels (k <= 256)  // single-workgroup kernels stage their matrices in LDS up to this size
+constexpr size_t kOrthMaxLds = 144 * 1024;  // single-workgroup kernels stage their matrices in LDS up to this size
+constexpr int kMaxSubspaceDev = 256;        // column limit of the subspace kernels (k <= 256)
 
 // wavefront reductions of the device library (DPP based, all lanes active)
 extern "C" __device__ double __ockl_wfred_add_f64(double);
@@ -606,7 +606,7 @@ __global__ void copy_cols_kernel(const double* src, int64_t ld_src, double* dst,
 constexpr int kTallThreads = 256;
 // inner two-sided Jacobi of a blocked pass: relative skip threshold and sweep limit
 constexpr double kGramInnerEps = 1e-16;
-constexpr int kGramInnerSweeps = 30;
+constexpr int kGramInnerSweeps = 10;
 
 // Pair `pr` of round `round` over kk (even) players: player 0 stays, the others rotate.
 __device__ inline void tournament_pair(int round, int pr, int kk, int& a, int& b) {
@@ -863,20 +863,26 @@ __global__ __launch_bounds__(kOneWG) void gram_jacobi_kernel(int k, double* __re
 // index), sigma and the permutation of the leading n_out; diagnostics
 // (accumulated over calls by maximum) diag[1] = sweeps that rotated, diag[2] =
 // largest |cos| between column pairs seen in the last sweep that ran; diag[3] = k;
-// diag[4] = pair-by-pair sweeps that followed a stalled blocked pass.
+// diag[4] = pair-by-pair sweeps that followed a stalled blocked pass.  With G (the
+// k x k Gram of the final columns, column-major) the norms are its diagonal.
 __global__ __launch_bounds__(kOneWG) void tall_jacobi_finish_kernel(const double* __restrict__ A, int64_t m, int k,
                                                                      int n_out, const int* __restrict__ rot,
                                                                      const double* __restrict__ offmax, int max_sweeps,
-                                                                     int fallback_sweeps, double* __restrict__ sigma,
-                                                                     int* __restrict__ perm, double* __restrict__ diag) {
+                                                                     int fallback_sweeps, const double* __restrict__ G,
+                                                                     double* __restrict__ sigma, int* __restrict__ perm,
+                                                                     double* __restrict__ diag) {
   __shared__ double nrm[kMaxSubspaceDev];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  for (int j = wave; j < k; j += kOneWG / 64) {
-    const double* x = A + (int64_t)j * m;
-    double s = 0.0;
-    for (int64_t r = lane; r < m; r += 64) s = fma(x[r], x[r], s);
-    s = __ockl_wfred_add_f64(s);
-    if (lane == 0) nrm[j] = sqrt(s);
+  if (G) {  // the Gram of the final columns (a blocked pass that rotated nothing) holds their squared norms
+    for (int j = tid; j < k; j += kOneWG) nrm[j] = sqrt(fabs(G[j + (int64_t)j * k]));
+  } else {
+    for (int j = wave; j < k; j += kOneWG / 64) {
+      const double* x = A + (int64_t)j * m;
+      double s = 0.0;
+      for (int64_t r = lane; r < m; r += 64) s = fma(x[r], x[r], s);
+      s = __ockl_wfred_add_f64(s);
+      if (lane == 0) nrm[j] = sqrt(s);
+    }
   }
   __syncthreads();
   for (int j = tid; j < k; j += kOneWG) {
@@ -1224,8 +1230,10 @@ hipError_t launch_copy_cols(const double* src, int64_t ld_src, double* dst, int6
 }
 
 hipError_t launch_tall_jacobi(double* A, int64_t m, int k, double* J, int* rot, double* offmax, int max_sweeps,
-                              double tol, const TallJacobiWork& wk, int* fallback_sweeps, hipStream_t s) {
+                              double tol, const TallJacobiWork& wk, int* fallback_sweeps, const double** final_gram,
+                              hipStream_t s) {
   if (fallback_sweeps) *fallback_sweeps = 0;
+  if (final_gram) *final_gram = nullptr;
   if (k < 1 || k > kMaxSubspaceDev || m < 1) return hipErrorInvalidValue;
   const int64_t init = (int64_t)k * k > max_sweeps ? (int64_t)k * k : max_sweeps;
   hipLaunchKernelGGL(tall_jacobi_init_kernel, dim3((unsigned)((init + 255) / 256)), dim3(256), 0, s, J, k, rot, offmax,
@@ -1275,7 +1283,10 @@ hipError_t launch_tall_jacobi(double* A, int64_t m, int k, double* J, int* rot, 
       if ((e = hipMemcpyAsync(&nrot, rot + sw, sizeof(int), hipMemcpyDeviceToHost, s)) != hipSuccess) return e;
       if ((e = hipMemcpyAsync(&off, offmax + sw, sizeof(double), hipMemcpyDeviceToHost, s)) != hipSuccess) return e;
       if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
-      if (nrot == 0) break;
+      if (nrot == 0) {
+        if (final_gram) *final_gram = wk.G;  // G holds the Gram of the final columns (the kernel reads it only)
+        break;
+      }
       if ((e = launch_mul_small(A, m, k, wk.V, wk.A2, s)) != hipSuccess) return e;
       if ((e = hipMemcpyAsync(A, wk.A2, lds, hipMemcpyDeviceToDevice, s)) != hipSuccess) return e;
       if (J) {
@@ -1300,11 +1311,11 @@ hipError_t launch_tall_jacobi(double* A, int64_t m, int k, double* J, int* rot, 
 }
 
 hipError_t launch_tall_jacobi_finish(const double* A, int64_t m, int k, const double* J, int n_out, const int* rot,
-                                     const double* offmax, int max_sweeps, int fallback_sweeps, double* sigma, int* perm,
-                                     double* V, double* Jp, double* diag, hipStream_t s) {
+                                     const double* offmax, int max_sweeps, int fallback_sweeps, const double* G,
+                                     double* sigma, int* perm, double* V, double* Jp, double* diag, hipStream_t s) {
   if (k < 1 || k > kMaxSubspaceDev || n_out > k) return hipErrorInvalidValue;
   hipLaunchKernelGGL(tall_jacobi_finish_kernel, dim3(1), dim3(kOneWG), 0, s, A, m, k, n_out, rot, offmax, max_sweeps,
-                     fallback_sweeps, sigma, perm, diag);
+                     fallback_sweeps, G, sigma, perm, diag);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int64_t n = (m + k) * n_out;
