@@ -594,7 +594,9 @@ def bench_c4(args):
     strom.lib()
     log = lambda m: print(f"[c4] {m}", file=sys.stderr, flush=True)
     N3, NT, NMU, NS, NTM = 128, 500, 16, 100, 30
-    nq = min(args.queries, 128)
+    # 256 queries: at n = 3000 the LU runs one query per workgroup of 512 threads, one workgroup
+    # per CU, so 256 queries occupy every CU once (128 would leave half of them idle)
+    nq = min(args.queries, 256)
     prob = W.advdiff3d(n=N3, N_t=NT, n_train=NMU)
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
 
