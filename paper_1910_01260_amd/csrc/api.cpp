@@ -754,8 +754,8 @@ bool pod_dims(int64_t N_s, int32_t N_t, int32_t n_mu, int32_t n_s, const int32_t
 
 struct PodWs {
   double *G, *X, *Y, *H, *Z, *Zs, *evals, *sig, *V, *part;
-  double *C1, *C2, *Y1, *Y2, *J, *Jp, *sigk, *offmax, *diag;
-  int32_t *moff, *perm, *rot;
+  double *C1, *C2, *Y1, *Y2, *J, *Jp, *sigk, *offmax, *diag, *oC, *on0;
+  int32_t *moff, *perm, *rot, *oflag;
   size_t part_elems, total;
 };
 
@@ -783,12 +783,15 @@ PodWs pod_ws(const PodDims& d, void* base) {
   w.moff = c.take<int32_t>(d.n_s + 1);
   w.perm = c.take<int32_t>(d.kr);
   w.rot = c.take<int32_t>(kRefineSweeps);
+  w.oC = c.take<double>((size_t)d.k * 16);  // blocked Gram-Schmidt of the subspace iteration
+  w.on0 = c.take<double>(16);
+  w.oflag = c.take<int32_t>(1);
   size_t pe = gram_partial_elems(d.transposed ? d.m : d.N_s, (int)d.p);
   const size_t cands[] = {tsgemm_partial_elems(d.p, (int)d.p, d.k), tsgemm_partial_elems(d.p, d.k, d.k),
                           tsgemm_partial_elems(d.k, (int)d.p, d.k), tsgemm_partial_elems(d.N_s, (int)d.m, d.kr),
                           tsgemm_partial_elems(d.m, (int)d.N_s, d.kr), tsgemm_partial_elems(d.kr, (int)d.N_s, d.n_s),
                           tsgemm_partial_elems(d.kr, (int)d.m, d.n_s), tsgemm_partial_elems(d.N_s, d.kr, d.kr),
-                          tsgemm_partial_elems(d.m, d.kr, d.kr)};
+                          tsgemm_partial_elems(d.m, d.kr, d.kr), tsgemm_partial_elems(d.p, 1, 1) * d.k * 16};
   for (size_t v : cands) pe = v > pe ? v : pe;
   w.part = c.take<double>(pe);
   w.part_elems = pe;
@@ -839,11 +842,12 @@ st_status st_build_bases(const void* U, int32_t U_prec, int64_t ldU, int64_t N_s
   // a2: subspace iteration on G, then Rayleigh-Ritz
   const uint64_t seed = 0x5EED1910ULL;
   ST_TRY(launch_rand_fill(w.X, p, k, seed, s));
-  ST_TRY(launch_orth(w.X, p, k, seed + 1, s));
+  const OrthWork owk{w.oC, w.on0, w.oflag, w.part, w.part_elems};
+  ST_TRY(launch_orth(w.X, p, k, seed + 1, owk, s));
   for (int it = 0; it < kSubspaceIters; ++it) {
     ST_TRY(launch_tsgemm(p, p, k, w.G, 1, p, w.X, 1, p, w.Y, p, w.part, w.part_elems, s));  // Y = G X
     ST_TRY(launch_copy_cols(w.Y, p, w.X, p, p, k, s));
-    ST_TRY(launch_orth(w.X, p, k, seed + 2 + it, s));
+    ST_TRY(launch_orth(w.X, p, k, seed + 2 + it, owk, s));
   }
   ST_TRY(launch_tsgemm(p, p, k, w.G, 1, p, w.X, 1, p, w.Y, p, w.part, w.part_elems, s));    // Y = G X
   ST_TRY(launch_tsgemm(p, k, k, w.X, 1, p, w.Y, 1, p, w.H, k, w.part, w.part_elems, s));    // H = X^T G X

@@ -100,7 +100,16 @@ size_t gram_partial_elems(int64_t K, int p);
 hipError_t launch_gram(int64_t K, int p, const void* X, int in_prec, int64_t ks, int64_t ms, int gram_prec, double* G,
                        double* partial, size_t partial_elems, hipStream_t s);
 hipError_t launch_rand_fill(double* X, int64_t p, int k, uint64_t seed, hipStream_t s);
-hipError_t launch_orth(double* X, int64_t p, int k, uint64_t seed, hipStream_t s);
+// Work areas of launch_orth's blocked sweep for columns too long for LDS: C (k x 16), n0sq
+// (16), flag (1 int), part (split partials of the block products, part_elems doubles).
+// All null: one workgroup sweeps the columns in global memory.
+struct OrthWork {
+  double *C, *n0sq;
+  int* flag;
+  double* part;
+  size_t part_elems;
+};
+hipError_t launch_orth(double* X, int64_t p, int k, uint64_t seed, const OrthWork& wk, hipStream_t s);
 hipError_t launch_jacobi(int k, double* A, double* Z, double* evals, double* Zout, hipStream_t s);
 hipError_t launch_chol_inv(int n, double* S, double* Rinv, hipStream_t s);
 hipError_t launch_scale_or_refill(double* X, int64_t p, int k, const double* sigma, double cut, uint64_t seed,

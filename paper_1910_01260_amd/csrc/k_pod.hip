@@ -21,6 +21,7 @@ constexpr int kOneWG = 1024;
 constexpr int kTsvdThreads = 1024;  // one workgroup per mode: one wave per column pair of a round
 constexpr size_t kOrthMaxLds = 144 * 1024;  // single-workgroup kernels stage their matrices in LDS up to this size
 constexpr int kMaxSubspaceDev = 256;        // column limit of the subspace kernels (k <= 256)
+constexpr int kOrthBlock = 16;             // column block of the blocked Gram-Schmidt (long columns)
 
 // wavefront reductions of the device library (DPP based, all lanes active)
 extern "C" __device__ double __ockl_wfred_add_f64(double);
@@ -325,9 +326,16 @@ __global__ void rand_fill_kernel(double* X, int64_t p, int k, uint64_t seed) {
 // but 1e-10 of its norm (dependent on the previous ones) is replaced by a
 // pseudo-random vector and orthogonalised again.  With IN_LDS the columns are
 // staged in LDS for the whole sweep (every column step touches all previous
-// columns, so a global round trip per step would dominate).
+// columns, so a global round trip per step would dominate).  As the last step of
+// a blocked sweep (X a block of columns col0 .. col0 + k - 1 already projected
+// against the columns before it): n0sq holds each column's squared norm before
+// that projection (the reference of the dependence test), the pseudo-random
+// refills are numbered by col0 + j, and *refilled is set when one was needed
+// (the caller then projects the block against the earlier columns again).
 template <bool IN_LDS>
-__global__ __launch_bounds__(kOneWG) void orth_cgs2_kernel(double* Xg, int64_t p, int k, uint64_t seed) {
+__global__ __launch_bounds__(kOneWG) void orth_cgs2_kernel(double* Xg, int64_t p, int k, uint64_t seed,
+                                                           const double* __restrict__ n0sq, int col0,
+                                                           int* __restrict__ refilled) {
   extern __shared__ __align__(16) double xs_lds[];
   __shared__ double coef[256];
   __shared__ double red[kOneWG / 64];
@@ -365,7 +373,7 @@ __global__ __launch_bounds__(kOneWG) void orth_cgs2_kernel(double* Xg, int64_t p
       // first pass: the projections and the column's own squared norm (slot j) together
       dots(xj, j + 1);
       __syncthreads();
-      const double n0 = sqrt(coef[j]);
+      const double n0 = (n0sq && attempt == 0) ? sqrt(n0sq[j]) : sqrt(coef[j]);
       double nn;
       if (j > 0) {
         project(xj, j);
@@ -385,7 +393,8 @@ __global__ __launch_bounds__(kOneWG) void orth_cgs2_kernel(double* Xg, int64_t p
         break;
       }
       // dependent column: refill and retry
-      for (int64_t r = tid; r < p; r += kOneWG) xj[r] = rand_pm(seed + 7919ULL * (attempt + 1), r, j);
+      for (int64_t r = tid; r < p; r += kOneWG) xj[r] = rand_pm(seed + 7919ULL * (attempt + 1), r, col0 + j);
+      if (tid == 0 && refilled) *refilled = 1;
       __syncthreads();
     }
   }
@@ -1167,7 +1176,44 @@ hipError_t launch_rand_fill(double* X, int64_t p, int k, uint64_t seed, hipStrea
   return hipGetLastError();
 }
 
-hipError_t launch_orth(double* X, int64_t p, int k, uint64_t seed, hipStream_t s) {
+// n0sq[c] = ||X[:, c]||^2 (one workgroup per column, fixed summation order); the
+// first workgroup also clears *flag.
+__global__ __launch_bounds__(256) void col_sumsq_kernel(const double* __restrict__ X, int64_t p,
+                                                        double* __restrict__ n0sq, int* __restrict__ flag) {
+  __shared__ double red[256 / 64];
+  const double* x = X + (int64_t)blockIdx.x * p;
+  double acc = 0.0;
+  for (int64_t r = threadIdx.x; r < p; r += 256) acc = fma(x[r], x[r], acc);
+  acc = block_sum(acc, red);
+  if (threadIdx.x == 0) {
+    n0sq[blockIdx.x] = acc;
+    if (blockIdx.x == 0) *flag = 0;
+  }
+}
+
+// Xb[:, c] -= Xp C[:, c] for c < nb (Xb p x nb, Xp p x j0, C j0 x nb, all
+// column-major, ld p resp. j0; nb <= kOrthBlock): one thread per row, C in LDS.
+__global__ __launch_bounds__(256) void sub_mul_kernel(double* __restrict__ Xb, const double* __restrict__ Xp,
+                                                      int64_t p, int j0, int nb, const double* __restrict__ C) {
+  extern __shared__ __align__(16) double cs[];
+  for (int e = threadIdx.x; e < j0 * nb; e += 256) cs[e] = C[e];
+  __syncthreads();
+  const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (r >= p) return;
+  double acc[kOrthBlock];
+#pragma unroll
+  for (int c = 0; c < kOrthBlock; ++c) acc[c] = c < nb ? Xb[r + (int64_t)c * p] : 0.0;
+  for (int l = 0; l < j0; ++l) {
+    const double a = Xp[r + (int64_t)l * p];
+#pragma unroll
+    for (int c = 0; c < kOrthBlock; ++c) acc[c] = fma(-a, cs[l + c * j0], acc[c]);
+  }
+#pragma unroll
+  for (int c = 0; c < kOrthBlock; ++c)
+    if (c < nb) Xb[r + (int64_t)c * p] = acc[c];
+}
+
+hipError_t launch_orth(double* X, int64_t p, int k, uint64_t seed, const OrthWork& wk, hipStream_t s) {
   const size_t lds = sizeof(double) * (size_t)p * (size_t)k;
   if (lds <= kOrthMaxLds) {
     if (!g_capturing) {
@@ -1175,11 +1221,43 @@ hipError_t launch_orth(double* X, int64_t p, int k, uint64_t seed, hipStream_t s
                                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
       if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(orth_cgs2_kernel<true>, dim3(1), dim3(kOneWG), lds, s, X, p, k, seed);
-  } else {
-    hipLaunchKernelGGL(orth_cgs2_kernel<false>, dim3(1), dim3(kOneWG), 0, s, X, p, k, seed);
+    hipLaunchKernelGGL(orth_cgs2_kernel<true>, dim3(1), dim3(kOneWG), lds, s, X, p, k, seed, nullptr, 0, nullptr);
+    return hipGetLastError();
   }
-  return hipGetLastError();
+  if (!wk.C || !wk.n0sq || !wk.flag || !wk.part) {
+    hipLaunchKernelGGL(orth_cgs2_kernel<false>, dim3(1), dim3(kOneWG), 0, s, X, p, k, seed, nullptr, 0, nullptr);
+    return hipGetLastError();
+  }
+  // Block classical Gram-Schmidt with reorthogonalisation (BCGS2) for columns too
+  // long for LDS: per block of kOrthBlock columns, two passes of C = X_prev^T X_blk
+  // and X_blk -= X_prev C on the whole device, then the one-workgroup CGS2 inside the
+  // block (which tests dependence against the norms before the projections).  A block
+  // that needed a pseudo-random refill is projected and orthogonalised again.
+  hipError_t e = hipSuccess;
+  for (int j0 = 0; j0 < k; j0 += kOrthBlock) {
+    const int nb = k - j0 < kOrthBlock ? k - j0 : kOrthBlock;
+    double* Xb = X + (int64_t)j0 * p;
+    for (int attempt = 0; attempt < 3; ++attempt) {
+      hipLaunchKernelGGL(col_sumsq_kernel, dim3(nb), dim3(256), 0, s, Xb, p, wk.n0sq, wk.flag);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+      for (int pass = 0; pass < 2 && j0 > 0; ++pass) {
+        if ((e = launch_tsgemm(p, j0, nb, X, 1, p, Xb, 1, p, wk.C, j0, wk.part, wk.part_elems, s)) != hipSuccess)
+          return e;
+        hipLaunchKernelGGL(sub_mul_kernel, dim3((unsigned)((p + 255) / 256)), dim3(256),
+                           sizeof(double) * (size_t)j0 * nb, s, Xb, X, p, j0, nb, wk.C);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+      }
+      hipLaunchKernelGGL(orth_cgs2_kernel<false>, dim3(1), dim3(kOneWG), 0, s, Xb, p, nb, seed, wk.n0sq, j0,
+                         wk.flag);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+      if (j0 == 0) break;  // nothing earlier to project against
+      int refilled = 0;
+      if ((e = hipMemcpyAsync(&refilled, wk.flag, sizeof(int), hipMemcpyDeviceToHost, s)) != hipSuccess) return e;
+      if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
+      if (!refilled) break;
+    }
+  }
+  return hipSuccess;
 }
 
 hipError_t launch_jacobi(int k, double* A, double* Z, double* evals, double* Zout, hipStream_t s) {
@@ -1240,13 +1318,13 @@ hipError_t launch_tall_jacobi(double* A, int64_t m, int k, double* J, int* rot, 
                      max_sweeps);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || k < 2) return e;
-  const size_t lds = sizeof(double) * (size_t)m * k;
-  if (lds <= kOrthMaxLds) {
+  const size_t abytes = sizeof(double) * (size_t)m * k;
+  if (abytes <= kOrthMaxLds) {
     // the whole matrix in LDS: every sweep in one launch
     if ((e = hipFuncSetAttribute((const void*)tall_jacobi_lds_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                 (int)lds)) != hipSuccess)
+                                 (int)abytes)) != hipSuccess)
       return e;
-    hipLaunchKernelGGL(tall_jacobi_lds_kernel, dim3(1), dim3(kOneWG), lds, s, A, m, k, J, max_sweeps, rot, offmax,
+    hipLaunchKernelGGL(tall_jacobi_lds_kernel, dim3(1), dim3(kOneWG), abytes, s, A, m, k, J, max_sweeps, rot, offmax,
                        tol);
     return hipGetLastError();
   }
@@ -1288,7 +1366,7 @@ hipError_t launch_tall_jacobi(double* A, int64_t m, int k, double* J, int* rot, 
         break;
       }
       if ((e = launch_mul_small(A, m, k, wk.V, wk.A2, s)) != hipSuccess) return e;
-      if ((e = hipMemcpyAsync(A, wk.A2, lds, hipMemcpyDeviceToDevice, s)) != hipSuccess) return e;
+      if ((e = hipMemcpyAsync(A, wk.A2, abytes, hipMemcpyDeviceToDevice, s)) != hipSuccess) return e;
       if (J) {
         if ((e = launch_mul_small(J, k, k, wk.V, wk.J2, s)) != hipSuccess) return e;
         if ((e = hipMemcpyAsync(J, wk.J2, glds, hipMemcpyDeviceToDevice, s)) != hipSuccess) return e;
