@@ -76,8 +76,8 @@ def source_hash(*names):
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(queries would shard across GPUs with no communication; see the design notes)", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
+              "(queries would shard across GPUs with no communication between them)", file=sys.stderr)
         sys.exit(2)
     if args.workload == "surrogate":
         return bench_surrogate(args)
