@@ -260,3 +260,33 @@ def test_pod_graded_tail_both_jacobi_paths(prec):
     print(f"[graded] prec {prec}: {resolved.sum()} modes resolved, {checked} vectors checked; "
           f"|dsigma| <= {ds.max() / osig[0]:.1e} sigma_1 on them")
     assert checked >= (30 if prec == strom.ST_F64 else 7)
+
+
+@pytest.mark.parametrize("N_s,N_t", [(3000, 150), (200, 150)])
+def test_pod_rank_deficient_snapshots(N_s, N_t):
+    """Snapshots of exact rank 10 (600 of them), 8 modes asked for: the subspace
+    iteration's 40 columns include 30 that G maps to round-off, so its Gram-Schmidt
+    must refill them with pseudo-random vectors — on 600-long columns in LDS-free
+    16-column blocks (a block dependent on the earlier ones is projected again) when
+    N_s >= 600, and on the 200-long columns of U U^T in LDS otherwise.  The leading
+    singular values and vectors still match the oracle's SVD and the basis is
+    orthonormal."""
+    rng = np.random.default_rng(21)
+    m, r, n_s = 4 * N_t, 10, 8
+    Q1 = np.linalg.qr(rng.standard_normal((N_s, r)))[0]
+    Q2 = np.linalg.qr(rng.standard_normal((m, r)))[0]
+    U = (Q1 * np.geomspace(1.0, 1e-2, r)) @ Q2.T
+    diag = torch.zeros(len(strom.POD_DIAG), dtype=torch.float64, device="cuda")
+    print(f"[rank10] st_build_bases N_s={N_s} m={m} n_s={n_s}", flush=True)
+    Phi_s, _, sigma, _ = strom.st_build_bases(colmajor(U), N_t, 4, n_s, [4] * n_s, diag=diag)
+    torch.cuda.synchronize()
+    dg = dict(zip(strom.POD_DIAG, diag.cpu().numpy().tolist()))
+    print(f"[rank10] diagnostics {dg}", flush=True)
+    Phi_s = Phi_s.cpu().numpy()
+    sigma = sigma.cpu().numpy()
+    oPhi, osig, _ = opod.pod(U, n_s)
+    np.testing.assert_allclose(Phi_s.T @ Phi_s, np.eye(n_s), atol=1e-13)
+    np.testing.assert_allclose(sigma, osig[:n_s], rtol=0, atol=1e-12 * osig[0])
+    for i in range(n_s):
+        tol = _svd_vector_tol(osig, i)
+        assert np.linalg.norm(Phi_s[:, i] - oPhi[:, i]) <= tol, (i, tol)
