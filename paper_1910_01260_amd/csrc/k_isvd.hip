@@ -30,6 +30,9 @@ constexpr int kIT = 256;           // threads of every kernel here
 constexpr int kNW = kIT / 64;      // waves per workgroup
 constexpr int kApplyRows = 64;     // rows per workgroup of the factor updates
 constexpr int kColPass = 8;        // output columns per lane and pass
+constexpr int kStageElems = 8192;  // rows of M^T staged in LDS by the factor updates (doubles)
+constexpr int kStageMaxGrid = 256; // ... when their grid has at most this many workgroups (one per CU)
+constexpr size_t kApplyLdsMax = 156 * 1024;  // dynamic LDS of the apply kernels (their static LDS comes on top)
 constexpr int kMaxN = kIsvdMaxRank + 1;
 constexpr int kGrp = 8;  // lanes per column in the norms of the bordered SVD's vectors
 constexpr int64_t kFrontRows = 4096;  // snapshots up to this length take the one-workgroup front
@@ -451,10 +454,13 @@ __global__ __launch_bounds__(kIT) void isvd_front_kernel(const double* __restric
 
 // X[row, 0:rnew] <- [X[row, 0:r], extra(row)] M over rows [row0, row1), in
 // place (every row is read into LDS before any is written).  MT holds M^T
-// row by row: MT[j * ldq + c] = M[j, c].
-template <typename Extra>
+// row by row: MT[j * ldq + c] = M[j, c].  With STAGED the rows of MT are first
+// copied into LDS (mts, row stride ldm = rnew rounded up to kColPass, zero
+// padded) and read from there as broadcasts; otherwise every lane reads them
+// through the scalar cache, whose misses then stall each step of the product.
+template <bool STAGED, typename Extra>
 __device__ void apply_rows(double* __restrict__ X, int64_t ldx, int64_t row0, int64_t row1, int r, int rnew,
-                           const double* __restrict__ MT, int ldq, Extra extra, double* tile) {
+                           const double* __restrict__ MT, int ldq, Extra extra, double* tile, double* mts, int ldm) {
   const int tid = threadIdx.x;
   const int n_in = r + 1;
   const int lane = tid & 63, wave = tid >> 6;
@@ -467,6 +473,11 @@ __device__ void apply_rows(double* __restrict__ X, int64_t ldx, int64_t row0, in
   } else {
     for (int j = wave; j < n_in; j += kNW) tile[j * kApplyRows + lane] = 0.0;
   }
+  if (STAGED)
+    for (int e = tid; e < n_in * ldm; e += kIT) {
+      const int j = e / ldm, c = e - j * ldm;
+      mts[e] = c < rnew ? MT[(int64_t)j * ldq + c] : 0.0;
+    }
   __syncthreads();
   for (int cb = wave * kColPass; cb < rnew; cb += kNW * kColPass) {
     const int cbu = __builtin_amdgcn_readfirstlane(cb);
@@ -475,7 +486,7 @@ __device__ void apply_rows(double* __restrict__ X, int64_t ldx, int64_t row0, in
     for (int q = 0; q < kColPass; ++q) acc[q] = 0.0;
     for (int j = 0; j < n_in; ++j) {
       const double t = tile[j * kApplyRows + lane];
-      const double* m = MT + (int64_t)j * ldq + cbu;
+      const double* m = STAGED ? mts + j * ldm + cbu : MT + (int64_t)j * ldq + cbu;
 #pragma unroll
       for (int q = 0; q < kColPass; ++q) acc[q] = fma(t, m[q], acc[q]);
     }
@@ -487,17 +498,31 @@ __device__ void apply_rows(double* __restrict__ X, int64_t ldx, int64_t row0, in
   }
 }
 
+// The MT staging area of the apply kernels follows the row tile ((r_max + 1)
+// kApplyRows doubles); stage_cap doubles of it (0: none), used when the step's
+// (r + 1) x ldm block fits.
+__device__ inline bool stage_fits(int r, int rnew, int stage_cap, int& ldm) {
+  ldm = (rnew + kColPass - 1) / kColPass * kColPass;
+  return (int64_t)(r + 1) * ldm <= stage_cap;
+}
+
 __global__ __launch_bounds__(kIT) void isvd_apply_w_kernel(double* __restrict__ W, int64_t N_s,
                                                            const int32_t* state, const double* __restrict__ res,
                                                            const double* __restrict__ scal,
-                                                           const double* __restrict__ UqT, int ldq, double* part) {
+                                                           const double* __restrict__ UqT, int ldq, double* part,
+                                                           int stage_cap) {
   extern __shared__ __align__(16) double tile[];
   const int r = state[S_R], rnew = state[S_RNEW];
   const bool noop = state[S_MODE] == M_NOOP;
   const int64_t row0 = (int64_t)blockIdx.x * kApplyRows, row1 = min(row0 + kApplyRows, N_s);
   if (!noop && rnew > 0) {
     const double invp = scal[C_INVP];
-    apply_rows(W, N_s, row0, row1, r, rnew, UqT, ldq, [&](int64_t row) { return res[row] * invp; }, tile);
+    auto extra = [&](int64_t row) { return res[row] * invp; };
+    int ldm;
+    if (stage_fits(r, rnew, stage_cap, ldm))
+      apply_rows<true>(W, N_s, row0, row1, r, rnew, UqT, ldq, extra, tile, tile + ldq * kApplyRows, ldm);
+    else
+      apply_rows<false>(W, N_s, row0, row1, r, rnew, UqT, ldq, extra, tile, nullptr, 0);
   }
   __syncthreads();
   // partial of the orthogonality test of Alg. 2: W(:,1)^T W(:,end)
@@ -547,14 +572,20 @@ __device__ void orthonormalise(double* __restrict__ W, int64_t N_s, int n) {
 
 __global__ __launch_bounds__(kIT) void isvd_apply_v_kernel(double* __restrict__ V, int64_t m_max,
                                                            const int32_t* state, const double* __restrict__ VqT,
-                                                           int ldq) {
+                                                           int ldq, int stage_cap) {
   extern __shared__ __align__(16) double tile[];
   const int r = state[S_R], rnew = state[S_RNEW];
   const bool noop = state[S_MODE] == M_NOOP;
   const int64_t k = state[S_K];
   const int64_t row0 = (int64_t)blockIdx.x * kApplyRows, row1 = min(row0 + kApplyRows, k + 1);
-  if (!noop && rnew > 0 && row0 < row1)
-    apply_rows(V, m_max, row0, row1, r, rnew, VqT, ldq, [&](int64_t row) { return row == k ? 1.0 : 0.0; }, tile);
+  if (!noop && rnew > 0 && row0 < row1) {
+    auto extra = [&](int64_t row) { return row == k ? 1.0 : 0.0; };
+    int ldm;
+    if (stage_fits(r, rnew, stage_cap, ldm))
+      apply_rows<true>(V, m_max, row0, row1, r, rnew, VqT, ldq, extra, tile, tile + ldq * kApplyRows, ldm);
+    else
+      apply_rows<false>(V, m_max, row0, row1, r, rnew, VqT, ldq, extra, tile, nullptr, 0);
+  }
 }
 
 // End of a step (one workgroup): the orthogonality test from the W update's
@@ -601,7 +632,20 @@ int isvd_row_blocks(int64_t N_s) {
   return (int)((N_s + rpb - 1) / rpb);
 }
 
-size_t isvd_apply_lds_bytes(int r_max) { return sizeof(double) * (size_t)(r_max + 1) * kApplyRows; }
+// LDS of the apply kernels: the row tile, then up to kStageElems doubles for the
+// rows of M^T, as many as fit beside the tile in kApplyLdsMax bytes.
+int isvd_stage_cap(int r_max) {
+  const int64_t tile = (int64_t)(r_max + 1) * kApplyRows;
+  const int64_t want = (int64_t)(r_max + 1) * ((r_max + kColPass - 1) / kColPass * kColPass);
+  int64_t cap = want < kStageElems ? want : kStageElems;
+  const int64_t room = (int64_t)(kApplyLdsMax / sizeof(double)) - tile;
+  if (cap > room) cap = room;
+  return cap > 0 ? (int)cap : 0;
+}
+
+size_t isvd_apply_lds_bytes(int r_max) {
+  return sizeof(double) * ((size_t)(r_max + 1) * kApplyRows + (size_t)isvd_stage_cap(r_max));
+}
 
 hipError_t launch_isvd_reset(int32_t* state, hipStream_t s) {
   hipLaunchKernelGGL(isvd_reset_kernel, dim3(1), dim3(64), 0, s, state);
@@ -636,11 +680,18 @@ hipError_t launch_isvd_step(const IsvdArgs& a, const double* u, hipStream_t s) {
                        a.UqT, a.VqT, a.r_max, a.m_max, a.eps_svd, a.eps_sv);
   }
   const int GW = (int)((a.N_s + kApplyRows - 1) / kApplyRows);
-  const double orth_tol = fmin(a.eps_svd, bsvd::kEps * (double)a.N_s);
-  hipLaunchKernelGGL(isvd_apply_w_kernel, dim3(GW), dim3(kIT), lds, s, a.W, a.N_s, a.state, a.res, a.scal, a.UqT,
-                     ldq, a.part);
   const int GV = (int)((a.m_max + kApplyRows - 1) / kApplyRows);
-  hipLaunchKernelGGL(isvd_apply_v_kernel, dim3(GV), dim3(kIT), lds, s, a.V, a.m_max, a.state, a.VqT, ldq);
+  const double orth_tol = fmin(a.eps_svd, bsvd::kEps * (double)a.N_s);
+  // Staging M^T in LDS takes the room of a second workgroup per CU: it pays while
+  // the grid leaves CUs idle anyway (measured: the 4-block W and 64-block V updates
+  // of 256-row snapshots gain, a 768-block W update of 49152-row ones loses).
+  const int cap = isvd_stage_cap(a.r_max);
+  const int cap_w = GW <= kStageMaxGrid ? cap : 0, cap_v = GV <= kStageMaxGrid ? cap : 0;
+  const size_t tile = sizeof(double) * (size_t)ldq * kApplyRows;
+  hipLaunchKernelGGL(isvd_apply_w_kernel, dim3(GW), dim3(kIT), tile + sizeof(double) * (size_t)cap_w, s, a.W, a.N_s,
+                     a.state, a.res, a.scal, a.UqT, ldq, a.part, cap_w);
+  hipLaunchKernelGGL(isvd_apply_v_kernel, dim3(GV), dim3(kIT), tile + sizeof(double) * (size_t)cap_v, s, a.V,
+                     a.m_max, a.state, a.VqT, ldq, cap_v);
   hipLaunchKernelGGL(isvd_commit_kernel, dim3(1), dim3(kIT), 0, s, a.W, a.N_s, a.state, a.part, GW, orth_tol);
   return hipGetLastError();
 }
