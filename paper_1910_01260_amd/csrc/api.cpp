@@ -791,7 +791,8 @@ PodWs pod_ws(const PodDims& d, void* base) {
                           tsgemm_partial_elems(d.k, (int)d.p, d.k), tsgemm_partial_elems(d.N_s, (int)d.m, d.kr),
                           tsgemm_partial_elems(d.m, (int)d.N_s, d.kr), tsgemm_partial_elems(d.kr, (int)d.N_s, d.n_s),
                           tsgemm_partial_elems(d.kr, (int)d.m, d.n_s), tsgemm_partial_elems(d.N_s, d.kr, d.kr),
-                          tsgemm_partial_elems(d.m, d.kr, d.kr), tsgemm_partial_elems(d.p, 1, 1) * d.k * 16};
+                          tsgemm_partial_elems(d.m, d.kr, d.kr), tsgemm_partial_elems(d.p, (int)d.p, d.n_s),
+                          tsgemm_partial_elems(d.p, 1, 1) * d.k * 16};
   for (size_t v : cands) pe = v > pe ? v : pe;
   w.part = c.take<double>(pe);
   w.part_elems = pe;

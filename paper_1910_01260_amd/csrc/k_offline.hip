@@ -16,6 +16,7 @@ namespace strom {
 namespace {
 
 constexpr int kTile = 32;
+constexpr int kTile64 = 64;  // output tile of the register-blocked tall-skinny product
 
 __global__ void index_tables_kernel(ModeTable mt, MutRomView rom) {
   // one workgroup; n_s <= kMaxModes
@@ -168,6 +169,70 @@ __global__ __launch_bounds__(256) void tsgemm_partial_kernel(int64_t N, int32_t 
   }
 }
 
+// The same product with a 64 x 64 output tile per workgroup and a 4 x 4 register
+// block per thread: eight LDS reads per sixteen FMAs instead of five per four (the
+// 32 x 32 form is bound by its LDS reads).  Used when both output sides are >= 64.
+template <typename TX>
+__global__ __launch_bounds__(256) void tsgemm_partial64_kernel(int64_t N, int32_t p, int32_t q,
+                                                              const TX* __restrict__ X, int64_t xrs, int64_t xcs,
+                                                              const double* __restrict__ Y, int64_t yrs, int64_t ycs,
+                                                              const double* __restrict__ wrow, int64_t rows_per_split,
+                                                              double* __restrict__ partial) {
+  constexpr int T = kTile64, KC = kTile;  // output tile side, rows per staged chunk
+  __shared__ double Xs[KC][T + 1];
+  __shared__ double Ys[KC][T + 1];
+  const int a0 = blockIdx.x * T, b0 = blockIdx.y * T;
+  const int64_t rbeg = (int64_t)blockIdx.z * rows_per_split;
+  const int64_t rend = min(N, rbeg + rows_per_split);
+  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;  // 16 x 16 threads, outputs ty + 16 i, tx + 16 j
+  double acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
+  const bool x_rows_contig = (xrs == 1);
+  const bool y_rows_contig = (yrs == 1);
+  for (int64_t r0 = rbeg; r0 < rend; r0 += KC) {
+    for (int e = threadIdx.x; e < KC * T; e += 256) {
+      int kk, a;
+      if (x_rows_contig) { kk = e % KC; a = e / KC; } else { a = e % T; kk = e / T; }
+      const int64_t r = r0 + kk;
+      double v = 0.0;
+      if (r < rend && a0 + a < p) {
+        v = (double)X[r * xrs + (int64_t)(a0 + a) * xcs];
+        if (wrow) v *= wrow[r];
+      }
+      Xs[kk][a] = v;
+      int bb;
+      if (y_rows_contig) { kk = e % KC; bb = e / KC; } else { bb = e % T; kk = e / T; }
+      const int64_t r2 = r0 + kk;
+      Ys[kk][bb] = (r2 < rend && b0 + bb < q) ? Y[r2 * yrs + (int64_t)(b0 + bb) * ycs] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int kk = 0; kk < KC; ++kk) {
+      double xv[4], yv[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) xv[i] = Xs[kk][ty + 16 * i];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) yv[j] = Ys[kk][tx + 16 * j];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = fma(xv[i], yv[j], acc[i][j]);
+    }
+    __syncthreads();
+  }
+  double* out = partial + (int64_t)blockIdx.z * p * q;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int a = a0 + ty + 16 * i, b = b0 + tx + 16 * j;
+      if (a < p && b < q) out[a + (int64_t)b * p] = acc[i][j];
+    }
+}
+
 // C[a + b*ldc] = sum_z partial[z][a + b*p], summed in split order (deterministic).
 __global__ void tsgemm_reduce_kernel(int32_t p, int32_t q, int32_t splits, const double* __restrict__ partial,
                                      double* __restrict__ C, int32_t ldc) {
@@ -180,8 +245,12 @@ __global__ void tsgemm_reduce_kernel(int32_t p, int32_t q, int32_t splits, const
   C[a + (int64_t)b * ldc] = s;
 }
 
+// output tile side of a p x q tall-skinny product
+inline int tsgemm_tile(int32_t p, int32_t q) { return (p >= kTile64 && q >= kTile64) ? kTile64 : kTile; }
+
 int tsgemm_splits(int64_t N, int32_t p, int32_t q) {
-  const int64_t tiles = (int64_t)((p + kTile - 1) / kTile) * ((q + kTile - 1) / kTile);
+  const int t = tsgemm_tile(p, q);
+  const int64_t tiles = (int64_t)((p + t - 1) / t) * ((q + t - 1) / t);
   if (tiles <= 0 || N <= 0) return 1;
   int64_t splits = (512 + tiles - 1) / tiles;
   const int64_t max_splits = (N + 255) / 256;
@@ -307,9 +376,14 @@ hipError_t tsgemm_go(int64_t N, int32_t p, int32_t q, const TX* X, int64_t xrs, 
   if ((size_t)splits * p * q > partial_elems) return hipErrorInvalidValue;
   int64_t rps = (N + splits - 1) / splits;
   rps = (rps + kTile - 1) / kTile * kTile;
-  dim3 grid((p + kTile - 1) / kTile, (q + kTile - 1) / kTile, splits);
-  hipLaunchKernelGGL(tsgemm_partial_kernel<TX>, grid, dim3(256), 0, s, N, p, q, X, xrs, xcs, Y, yrs, ycs, wrow, rps,
-                     partial);
+  const int t = tsgemm_tile(p, q);
+  dim3 grid((p + t - 1) / t, (q + t - 1) / t, splits);
+  if (t == kTile64)
+    hipLaunchKernelGGL(tsgemm_partial64_kernel<TX>, grid, dim3(256), 0, s, N, p, q, X, xrs, xcs, Y, yrs, ycs, wrow,
+                       rps, partial);
+  else
+    hipLaunchKernelGGL(tsgemm_partial_kernel<TX>, grid, dim3(256), 0, s, N, p, q, X, xrs, xcs, Y, yrs, ycs, wrow, rps,
+                       partial);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int64_t pq = (int64_t)p * q;
