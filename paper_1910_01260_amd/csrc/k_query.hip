@@ -686,6 +686,9 @@ __global__ __launch_bounds__(kResMfThreads) void residual_mf_kernel(RomView rom,
     const double* xv = xs + loff[i];
     const int ni = nt[i];
     double z = 0.0;
+    // unrolled so that several of the strided Phi_t loads are in flight at once (the FMA
+    // order, and so the result, is that of the plain loop)
+#pragma unroll 8
     for (int j = 0; j < ni; ++j) z = fma(ph[(int64_t)j * N_t], xv[j], z);
     Z[e] = z;
   }
@@ -724,6 +727,7 @@ __global__ __launch_bounds__(kResMfThreads) void residual_mf_kernel(RomView rom,
     const double* vm = V + (size_t)m * N_t;
     double acc = 0.0;
     if (ok)
+#pragma unroll 8
       for (int k = c16; k < N_t; k += 16) acc = fma(ph[k], vm[k], acc);
     acc = row16_sum(acc);
     if (ok && c16 == 0) r[off + c] = rhs[off + c] - acc;
