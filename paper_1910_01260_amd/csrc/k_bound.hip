@@ -109,6 +109,7 @@ __global__ __launch_bounds__(kBoundThreads) void fom_residual_kernel(
       const int nt = s_loff[i + 1] - s_loff[i];
       const double* pt = rom.Phit + (int64_t)rom.moff[i] * N_t + k;
       const double* ci = c + s_loff[i];
+#pragma unroll 8  // several strided loads in flight; same FMA order
       for (int j = 0; j < nt; ++j) y = fma(pt[(int64_t)j * N_t], ci[j], y);
     }
     ys[e] = y;

@@ -917,6 +917,7 @@ __global__ __launch_bounds__(kRecThreads) void reconstruct_kernel(int64_t N_s, i
     const int kk = e / n_s, i = e % n_s;
     const int nti = loff[i + 1] - loff[i];
     double y = 0.0;
+#pragma unroll 8  // several strided loads in flight; same FMA order
     for (int j = 0; j < nti; ++j) y = fma(Phi_t[(int64_t)(moff[i] + j) * ldt + k0 + kk], c[loff[i] + j], y);
     Y[kk * n_s + i] = y;
   }
